@@ -1,0 +1,237 @@
+"""CPU FP64 oracle of the non-negative tensor-train (nTT) sweep.
+
+TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this module.  The GPU library never calls it,
+and it shares no code with the GPU library: it is a plain, slow, obviously
+correct restatement of what the paper computes, in float64.
+
+What it follows
+---------------
+* Eq.(1)-(2), TT format: A[i_1..i_d] = sum_k G1[i_1,k_1] G2[k_1,i_2,k_2] ... Gd[k_{d-1},i_d].
+* Alg.2 (distnTT), one process: X_1 = reshape(A, n_1 x n_2...n_d); for each stage l,
+  X_l is (r_{l-1} n_l) x (n_{l+1}...n_d) (the reading of the text under Alg.2), it is
+  factored by NMF into W (m x r_l) and H (r_l x k); core l = reshape(W, r_{l-1} x n_l x r_l)
+  and the next unfolding is reshape(H, r_l n_{l+1} x ...).  The last core is H.
+* NMF by multiplicative updates (MU), the method the experiments time (Sec. IV-B,
+  IV-C): the paper names MU and the Frobenius objective but prints no rule, so this
+  is the Lee-Seung rule for min 1/2 ||X - W H||_F^2 with W, H >= 0, H updated first:
+      H <- max(0, H * (W^T X) / ((W^T W) H + eps))
+      W <- max(0, W * (X H^T) / (W (H H^T) + eps))
+* Objective 1/2 ||X - W H||_F^2 (Alg.3, the correction test), computed here as the
+  explicit residual, never by the Gram identity.
+* Eq.(3) relative error, Eq.(4) compression ratio.
+
+Readings where the paper is silent or garbled (ranks are given, not chosen by the
+SVD rule; ranks above min(m, k) are clamped; a fresh random stream per stage; the
+stopping rule) are stated at each function.
+
+Random initial factors use the SplitMix64 counter rule (Steele, Lea and Flood,
+OOPSLA 2014), implemented here on its own: value i of stream tag under seed is the
+SplitMix64 finaliser applied to seed + GAMMA * (tag * 2^32 + i + 1), and a uniform is
+its top 24 bits times 2^-24.  W of stage l uses tag 2l, H uses tag 2l + 1.
+
+parity pinned: every function here is checked by the CPU tests against closed forms,
+brute force, invariants or numbers printed in the paper.  The one calibrated (not
+pinned) quantity is how low the relative error gets at the true ranks after T
+iterations; only its monotone decrease is pinned.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- random init
+def splitmix64_at(seed: int, counter: int) -> int:
+    """SplitMix64 finaliser applied to seed + GAMMA * counter (pure Python ints)."""
+    z = (seed + GAMMA * counter) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def rng_uniform(seed: int, tag: int, count: int) -> np.ndarray:
+    """Uniforms on [0,1) of stream ``tag``: u_i = (z_i >> 40) / 2^24 (float64, FP32-exact)."""
+    seed &= M64
+    ctr = np.uint64((tag << 32) & M64) + np.arange(1, count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + np.uint64(GAMMA) * ctr
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(40)).astype(np.float64) / float(1 << 24)
+
+
+def init_factors(seed: int, stage: int, m: int, r: int, k: int):
+    """Random W0 (m x r) and H0 (r x k), uniform on [0,1) (Alg.3 'rand' init, no rescaling).
+
+    Stage ``stage`` is 1-based; W uses stream 2*stage, H stream 2*stage + 1, entries in C order.
+    """
+    w = rng_uniform(seed, 2 * stage, m * r).reshape(m, r)
+    h = rng_uniform(seed, 2 * stage + 1, r * k).reshape(r, k)
+    return w, h
+
+
+# ---------------------------------------------------------------- ranks, Eq.(4)
+def effective_ranks(dims, ranks):
+    """Clamp r_l to min(r_l, r_{l-1} n_l, n_{l+1}...n_d), left to right (TT-SVD convention).
+
+    The paper chooses r_l by the SVD threshold rule (Alg.2); here ranks are given and
+    an infeasible one is lowered to the largest rank the unfolding can hold.
+    """
+    d = len(dims)
+    out = [1]
+    for l in range(1, d):
+        m = out[-1] * dims[l - 1]
+        k = int(np.prod(dims[l:], dtype=np.int64))
+        out.append(int(min(ranks[l], m, k)))
+    out.append(1)
+    return out
+
+
+def compression_ratio(dims, ranks) -> float:
+    """Eq.(4): prod n_i / sum n_i r_{i-1} r_i."""
+    num = 1
+    for n in dims:
+        num *= int(n)
+    den = sum(int(dims[i]) * int(ranks[i]) * int(ranks[i + 1]) for i in range(len(dims)))
+    return num / den
+
+
+# ---------------------------------------------------------------- NMF by MU
+def objective(X, W, H) -> float:
+    """1/2 ||X - W H||_F^2 as the explicit residual."""
+    R = X - W @ H
+    return 0.5 * float(np.sum(R * R))
+
+
+def mu_step(X, W, H, eps):
+    """One Lee-Seung MU iteration, H first then W, with max(0, .) and additive eps."""
+    H = np.maximum(0.0, H * (W.T @ X) / ((W.T @ W) @ H + eps))
+    W = np.maximum(0.0, W * (X @ H.T) / (W @ (H @ H.T) + eps))
+    return W, H
+
+
+def stop_now(f_hist, t, nx, tol, check_every) -> bool:
+    """Stopping test at t % K == 0 (used only when tol > 0).
+
+    Stop when the relative residual sqrt(2 f_t)/||X|| <= tol, or when the objective
+    fell by no more than tol * f_{t-K} over the last K iterations.  (The paper runs a
+    fixed iteration count; this rule is the reading used for a tolerance budget.)
+    """
+    if tol <= 0 or t % check_every != 0:
+        return False
+    f_t = f_hist[t]
+    f_prev = f_hist[t - check_every]
+    if math.sqrt(2.0 * max(f_t, 0.0)) / nx <= tol:
+        return True
+    return (f_prev - f_t) <= tol * f_prev
+
+
+def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
+           record_objective=False, snapshots=()):
+    """NMF of X by MU from (W0, H0); returns a dict with W, H, iters, objective, snaps.
+
+    ``objective[t]`` is the explicit objective after t full iterations (index 0 = init),
+    filled when ``record_objective`` or ``tol > 0``.  ``snaps[t] = (W_t, H_t)`` for t in
+    ``snapshots``.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    W = np.array(W0, dtype=np.float64)
+    H = np.array(H0, dtype=np.float64)
+    want_obj = record_objective or tol > 0
+    nx = math.sqrt(float(np.sum(X * X)))
+    f_hist = [objective(X, W, H)] if want_obj else []
+    snaps = {}
+    if 0 in snapshots:
+        snaps[0] = (W.copy(), H.copy())
+    t_done = 0
+    for t in range(1, iters + 1):
+        W, H = mu_step(X, W, H, eps)
+        t_done = t
+        if want_obj:
+            f_hist.append(objective(X, W, H))
+        if t in snapshots:
+            snaps[t] = (W.copy(), H.copy())
+        if want_obj and stop_now(f_hist, t, nx, tol, check_every):
+            break
+    return {"W": W, "H": H, "iters": t_done, "objective": np.array(f_hist),
+            "snaps": snaps, "norm_x": nx}
+
+
+# ---------------------------------------------------------------- the nTT sweep
+def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
+                  inits=None, record_objective=False, snapshots=()):
+    """Alg.2 with given ranks and MU as the NMF: returns cores and per-stage details.
+
+    ``A`` is the d-way tensor (converted to float64, C order).  ``ranks`` has d+1
+    entries with r_0 = r_d = 1.  ``inits`` optionally maps stage l (1-based) to
+    (W0, H0); otherwise the seeded uniform init of ``init_factors`` is used.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    dims = list(A.shape)
+    d = len(dims)
+    r = effective_ranks(dims, ranks)
+    X = A.reshape(dims[0], -1)
+    cores, stages = [], []
+    for l in range(1, d):
+        m, k = X.shape
+        assert m == r[l - 1] * dims[l - 1]
+        rl = r[l]
+        if inits is not None and l in inits:
+            W0, H0 = inits[l]
+        else:
+            W0, H0 = init_factors(seed, l, m, rl, k)
+        res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots)
+        res.update({"X": X, "W0": W0, "H0": H0, "m": m, "k": k, "r": rl})
+        stages.append(res)
+        cores.append(res["W"].reshape(r[l - 1], dims[l - 1], rl))
+        H = res["H"]
+        if l < d - 1:
+            X = H.reshape(rl * dims[l], -1)
+    cores.append(stages[-1]["H"].reshape(r[d - 1], dims[d - 1], 1))
+    return {"cores": cores, "ranks": r, "stages": stages}
+
+
+# ---------------------------------------------------------------- Eq.(1)-(3)
+def tt_reconstruct(cores) -> np.ndarray:
+    """Eq.(1): contract the cores left to right (last axis of the partial product
+    against the first axis of the next core)."""
+    dims = [c.shape[1] for c in cores]
+    P = np.asarray(cores[0], dtype=np.float64).reshape(dims[0], -1)
+    for G in cores[1:]:
+        G = np.asarray(G, dtype=np.float64)
+        P = P.reshape(-1, G.shape[0]) @ G.reshape(G.shape[0], -1)
+    return P.reshape(dims)
+
+
+def tt_element(cores, idx) -> float:
+    """Eq.(2) for one entry: the explicit sum over k_1..k_{d-1} (pure Python loops)."""
+    d = len(cores)
+    rk = [c.shape[2] for c in cores[:-1]]
+    total = 0.0
+    for ks in itertools.product(*[range(r) for r in rk]):
+        term = float(cores[0][0, idx[0], ks[0]])
+        for j in range(1, d - 1):
+            term *= float(cores[j][ks[j - 1], idx[j], ks[j]])
+        term *= float(cores[d - 1][ks[d - 2], idx[d - 1], 0])
+        total += term
+    return total
+
+
+def rel_error(A, Ahat) -> float:
+    """Eq.(3): ||A - Ahat||_F / ||A||_F."""
+    A = np.asarray(A, dtype=np.float64)
+    D = A - np.asarray(Ahat, dtype=np.float64)
+    return math.sqrt(float(np.sum(D * D))) / math.sqrt(float(np.sum(A * A)))
+
+
+def ntt_flops(shapes, iters_per_stage) -> float:
+    """Algorithmic flops of the MU sweep: 4mkr + 4(m+k)r^2 per iteration per stage."""
+    return float(sum(t * (4.0 * m * k * r + 4.0 * (m + k) * r * r)
+                     for (m, k, r), t in zip(shapes, iters_per_stage)))

@@ -1,0 +1,292 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Every test here is CPU-only.  Each one fixes a property that a plausible slip in
+the oracle (a dropped term, a sign, a swapped index, a transposed operand) breaks:
+published generator outputs, numbers printed in the paper, brute force on tiny
+inputs, closed forms and theorems about MU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------------ generator rule
+def test_splitmix64_published_vectors():
+    g = json.load(open(os.path.join(GOLD, "splitmix64_vectors.json")))
+    want = [int(x) for x in g["outputs"]]
+    # tag 0, counters 1..5 is the plain published sequence
+    got = [O.splitmix64_at(g["seed"], i + 1) for i in range(5)]
+    assert got == want
+    raw = S.splitmix64(g["seed"], 0, 0, 5)
+    assert [int(x) for x in raw] == want
+
+
+def test_uniform_rule_matches_between_oracle_and_generator():
+    # two independent implementations of the same published rule
+    for seed, tag in [(0, 0), (1, 2), (2**63 + 5, 7), (12345, 0x101)]:
+        a = O.rng_uniform(seed, tag, 1000)
+        b = S.uniform01(seed, tag, (1000,)).astype(np.float64)
+        assert np.array_equal(a, b)
+        assert a.min() >= 0.0 and a.max() < 1.0
+        assert np.array_equal(a.astype(np.float32).astype(np.float64), a)  # FP32-exact
+        # top 24 bits of the raw output
+        raw = S.splitmix64(seed, tag, 0, 1000)
+        assert np.array_equal(a * (1 << 24), (raw >> np.uint64(40)).astype(np.float64))
+
+
+def test_uniform_moments():
+    u = O.rng_uniform(99, 3, 200000)
+    assert abs(u.mean() - 0.5) < 3e-3
+    assert abs(u.var() - 1.0 / 12) < 2e-3
+
+
+# ------------------------------------------------------------------ Eq.(2) brute force
+@pytest.mark.parametrize("dims,ranks", [((3, 2, 4), (1, 2, 3, 1)),
+                                        ((2, 3, 2, 3), (1, 2, 3, 2, 1)),
+                                        ((4, 4), (1, 3, 1)),
+                                        ((2, 2, 2, 2, 2), (1, 2, 2, 2, 2, 1))])
+def test_reconstruct_equals_bruteforce_sum(dims, ranks):
+    rng = _rng(1)
+    cores = [rng.random((ranks[k], dims[k], ranks[k + 1])) for k in range(len(dims))]
+    full = O.tt_reconstruct(cores)
+    assert full.shape == tuple(dims)
+    for idx in np.ndindex(*dims):
+        assert math.isclose(full[idx], O.tt_element(cores, idx), rel_tol=1e-13)
+    # third route: einsum over the explicit index string
+    letters = "abcdefghij"
+    spec = ",".join(f"{'z' if k == 0 else letters[k - 1]}{chr(ord('p') + k)}"
+                    f"{'y' if k == len(dims) - 1 else letters[k]}" for k in range(len(dims)))
+    out = "".join(chr(ord("p") + k) for k in range(len(dims)))
+    ein = np.einsum(spec + "->" + out, *cores)
+    np.testing.assert_allclose(full, ein, rtol=1e-13)
+
+
+def test_generator_tensor_equals_oracle_reconstruction():
+    dims, ranks = (5, 4, 6, 3), (1, 3, 2, 4, 1)
+    cores = S.random_cores(dims, ranks, seed=11)
+    a = S.contract_cores(cores)
+    ref = O.tt_reconstruct([c.astype(np.float64) for c in cores])
+    # the generator rounds once to float32
+    np.testing.assert_allclose(a.astype(np.float64), ref, rtol=2 ** -23)
+    assert a.dtype == np.float32 and a.min() >= 0
+
+
+def test_generated_unfoldings_have_the_generating_ranks():
+    dims, ranks = (6, 7, 8, 5), (1, 3, 4, 2, 1)
+    a = S.contract_cores(S.random_cores(dims, ranks, seed=3)).astype(np.float64)
+    for l in range(1, len(dims)):
+        X = a.reshape(int(np.prod(dims[:l])), -1)
+        assert np.linalg.matrix_rank(X, tol=1e-6 * np.linalg.norm(X)) == ranks[l]
+
+
+# ------------------------------------------------------------------ Eq.(3), Eq.(4)
+def test_compression_ratio_printed_values():
+    g = json.load(open(os.path.join(GOLD, "compression_ratio_pins.json")))
+    for c in g["cases"]:
+        cr = O.compression_ratio(c["dims"], c["ranks"])
+        assert math.isclose(cr, c["exact"], rel_tol=1e-12)
+        # the paper prints three significant digits, truncated (14799.1 -> 1.47e4)
+        e = int(math.floor(math.log10(cr)))
+        mant = math.floor(cr / 10 ** (e - 2)) / 100.0
+        assert f"{mant:.2f}e{e}" == c["printed"]
+
+
+def test_compression_ratio_closed_forms():
+    # uncompressed TT with full ranks of a matrix: C = n1 n2 / (n1 r + n2 r)
+    assert O.compression_ratio([10, 20], [1, 5, 1]) == 200 / (10 * 5 + 20 * 5)
+    assert O.compression_ratio([7], [1, 1]) == 1.0
+
+
+def test_rel_error_definition():
+    a = np.array([[3.0, 0.0], [0.0, 4.0]])
+    assert O.rel_error(a, a) == 0.0
+    assert math.isclose(O.rel_error(a, np.zeros_like(a)), 1.0)
+    assert math.isclose(O.rel_error(a, 2 * a), 1.0)
+    assert math.isclose(O.rel_error(a, a + np.array([[0.0, 5.0], [0.0, 0.0]])), 1.0)
+
+
+def test_effective_rank_clamp():
+    assert O.effective_ranks([2, 3, 4], [1, 5, 5, 1]) == [1, 2, 4, 1]
+    assert O.effective_ranks([16, 16, 16], [1, 4, 4, 1]) == [1, 4, 4, 1]
+    assert O.effective_ranks([4, 100, 2], [1, 50, 50, 1]) == [1, 4, 2, 1]
+
+
+# ------------------------------------------------------------------ MU theorems
+def _nonneg(m, n, seed):
+    return _rng(seed).random((m, n)) + 0.01
+
+
+def test_mu_objective_non_increasing_and_nonnegative():
+    X = _nonneg(30, 45, 0)
+    W0, H0 = O.init_factors(5, 1, 30, 4, 45)
+    res = O.mu_nmf(X, W0, H0, 300, record_objective=True)
+    f = res["objective"]
+    # Lee & Seung (2001): the Frobenius MU never increases the objective (eps = 0);
+    # eps = 1e-12 perturbs it at ~1e-12 relative
+    assert np.all(np.diff(f) <= 1e-10 * f[:-1])
+    assert f[-1] < 0.2 * f[0]
+    assert res["W"].min() >= 0 and res["H"].min() >= 0
+
+
+def test_mu_rank1_reaches_svd_truncation():
+    # Perron-Frobenius: the best rank-1 approximation of a positive matrix is non-negative,
+    # so converged rank-1 NMF attains the SVD truncation error.
+    X = _nonneg(12, 17, 1)
+    W0, H0 = O.init_factors(3, 1, 12, 1, 17)
+    res = O.mu_nmf(X, W0, H0, 2000, record_objective=True)
+    s = np.linalg.svd(X, compute_uv=False)
+    e_svd = math.sqrt(float(np.sum(s[1:] ** 2))) / math.sqrt(float(np.sum(s ** 2)))
+    e_mu = math.sqrt(2 * res["objective"][-1]) / res["norm_x"]
+    assert abs(e_mu - e_svd) <= 1e-9
+
+
+def test_mu_fixed_point_satisfies_kkt():
+    # At a limit point of MU the KKT conditions of min 1/2||X-WH||^2, W,H >= 0 hold:
+    # grad >= 0 everywhere and grad * factor = 0.  A transposed operand or a wrong
+    # numerator/denominator drives the iterates somewhere else.
+    X = _nonneg(20, 25, 2)
+    W0, H0 = O.init_factors(8, 1, 20, 3, 25)
+    res = O.mu_nmf(X, W0, H0, 20000)
+    W, H = res["W"], res["H"]
+    gH = W.T @ W @ H - W.T @ X
+    gW = W @ (H @ H.T) - X @ H.T
+    scale = np.linalg.norm(X) ** 2
+    assert np.abs(gH * H).max() / scale < 1e-6
+    assert np.abs(gW * W).max() / scale < 1e-6
+    assert gH.min() / np.linalg.norm(X) > -1e-3 and gW.min() / np.linalg.norm(X) > -1e-3
+
+
+def test_mu_exact_factorization_is_a_fixed_point():
+    rng = _rng(3)
+    Ws, Hs = rng.random((9, 3)) + 0.1, rng.random((3, 14)) + 0.1
+    X = Ws @ Hs
+    W1, H1 = O.mu_step(X, Ws, Hs, 1e-12)
+    assert np.abs(H1 - Hs).max() / Hs.max() < 1e-10
+    assert np.abs(W1 - Ws).max() / Ws.max() < 1e-10
+
+
+def test_mu_scale_covariance():
+    X = _nonneg(10, 13, 4)
+    W0, H0 = O.init_factors(1, 1, 10, 3, 13)
+    c = 7.5
+    a = O.mu_nmf(X, W0, H0, 50, eps=0.0)
+    b = O.mu_nmf(c * X, W0, c * H0, 50, eps=0.0)
+    np.testing.assert_allclose(b["W"], a["W"], rtol=1e-10)
+    np.testing.assert_allclose(b["H"], c * a["H"], rtol=1e-10)
+
+
+def test_mu_row_permutation_covariance():
+    X = _nonneg(11, 9, 5)
+    W0, H0 = O.init_factors(2, 1, 11, 2, 9)
+    p = _rng(6).permutation(11)
+    a = O.mu_nmf(X, W0, H0, 40)
+    b = O.mu_nmf(X[p], W0[p], H0, 40)
+    np.testing.assert_allclose(b["W"], a["W"][p], rtol=1e-11)
+    np.testing.assert_allclose(b["H"], a["H"], rtol=1e-11)
+
+
+def test_mu_h_first_order():
+    # The first half-step updates H from (W0, H0) alone; W then sees the new H.
+    X = _nonneg(6, 8, 7)
+    W0, H0 = O.init_factors(4, 1, 6, 2, 8)
+    W1, H1 = O.mu_step(X, W0, H0, 1e-12)
+    res = O.mu_nmf(X, W0, H0, 1, snapshots=(1,))
+    np.testing.assert_array_equal(res["snaps"][1][1], H1)
+    # with H fixed at H1 the W half-step is a closed-form ratio; recompute it by entries
+    N = X @ H1.T
+    D = W0 @ (H1 @ H1.T)
+    for i in range(6):
+        for j in range(2):
+            assert math.isclose(W1[i, j], W0[i, j] * N[i, j] / (D[i, j] + 1e-12), rel_tol=1e-14)
+
+
+def test_gram_identity_equals_explicit_residual():
+    X = _nonneg(15, 22, 8)
+    W, H = _rng(9).random((15, 4)), _rng(10).random((4, 22))
+    f_gram = 0.5 * (np.sum(X * X) - 2 * np.sum((W.T @ X) * H) + np.sum((W.T @ W) * (H @ H.T)))
+    assert math.isclose(O.objective(X, W, H), f_gram, rel_tol=1e-10)
+
+
+# ------------------------------------------------------------------ the sweep
+def test_sweep_d2_is_a_single_nmf():
+    X = _nonneg(12, 10, 11).astype(np.float32)
+    res = O.ntt_decompose(X, [1, 3, 1], 30, seed=4)
+    W0, H0 = O.init_factors(4, 1, 12, 3, 10)
+    ref = O.mu_nmf(X.astype(np.float64), W0, H0, 30)
+    np.testing.assert_array_equal(res["cores"][0].reshape(12, 3), ref["W"])
+    np.testing.assert_array_equal(res["cores"][1].reshape(3, 10), ref["H"])
+
+
+def test_sweep_shapes_and_nonnegativity():
+    dims, ranks = (4, 5, 3, 6), (1, 3, 4, 2, 1)
+    A = S.contract_cores(S.random_cores(dims, ranks, seed=5))
+    res = O.ntt_decompose(A, ranks, 20, seed=1)
+    r = res["ranks"]
+    for k, G in enumerate(res["cores"]):
+        assert G.shape == (r[k], dims[k], r[k + 1])
+        assert G.min() >= 0
+    # stage l factors the (r_{l-1} n_l) x (n_{l+1}...n_d) unfolding of the previous H
+    st = res["stages"]
+    assert (st[0]["m"], st[0]["k"]) == (4, 90)
+    assert (st[1]["m"], st[1]["k"]) == (15, 18)
+    assert (st[2]["m"], st[2]["k"]) == (12, 6)
+    np.testing.assert_array_equal(st[1]["X"], st[0]["H"].reshape(15, 18))
+
+
+def test_sweep_rank1_matches_tt_svd_rank1():
+    # With all TT ranks 1 the nTT of a positive tensor and the rank-1 TT-SVD coincide at
+    # convergence (each stage is the leading singular pair, which is non-negative).
+    dims = (5, 4, 6)
+    A = _rng(12).random(dims) + 0.2
+    res = O.ntt_decompose(A, [1, 1, 1, 1], 3000, seed=2)
+    e_ntt = O.rel_error(A, O.tt_reconstruct(res["cores"]))
+    # TT-SVD at ranks 1
+    X = A.reshape(5, -1)
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    G1 = U[:, :1] * s[0]
+    R = Vt[:1].reshape(4, 6)
+    U2, s2, Vt2 = np.linalg.svd(R, full_matrices=False)
+    Ahat = np.einsum("a,b,c->abc", G1[:, 0], U2[:, 0] * s2[0], Vt2[0])
+    e_svd = O.rel_error(A, Ahat)
+    assert abs(e_ntt - e_svd) < 1e-8
+
+
+def test_sweep_near_exact_recovery_improves_with_iterations():
+    # Noise-free TT-generated data has an exact non-negative TT at the true ranks; MU
+    # must keep lowering the error.  (How low it gets is calibrated, not pinned.)
+    w = S.workload("tt16x3_r4")
+    A = w.tensor()
+    errs = []
+    for T in (20, 100, 400):
+        res = O.ntt_decompose(A, w.target_ranks, T, seed=w.seed)
+        errs.append(O.rel_error(A, O.tt_reconstruct(res["cores"])))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.05
+
+
+def test_stop_rule_on_tolerance():
+    X = _nonneg(20, 30, 13)
+    W0, H0 = O.init_factors(1, 1, 20, 3, 30)
+    full = O.mu_nmf(X, W0, H0, 500, record_objective=True)
+    res = O.mu_nmf(X, W0, H0, 500, tol=1e-3, check_every=10)
+    t = res["iters"]
+    assert t % 10 == 0 and 10 <= t < 500
+    f = full["objective"]
+    # the rule holds at t and not at any earlier check point
+    def holds(s):
+        return (math.sqrt(2 * f[s]) / full["norm_x"] <= 1e-3) or (f[s - 10] - f[s] <= 1e-3 * f[s - 10])
+    assert holds(t)
+    assert not any(holds(s) for s in range(10, t, 10))
+    np.testing.assert_array_equal(res["W"], O.mu_nmf(X, W0, H0, t)["W"])
