@@ -1,0 +1,150 @@
+"""Benchmark of the nTT sweep on one MI355X.
+
+A step is one full pass of the hot path over the 32^5 workload (33.5M entries from
+rank-8 U[0,1) TT cores with 1% multiplicative noise): ntt_decompose (4 stages x 500
+MU iterations at ranks 8, FP32) followed by ntt_rel_error (Eq.(3), fused, FP64 sums).
+The input tensor is resident in HBM before the timed region starts.
+
+value = algorithmic GFLOP of the sweep per step (4mkr + 4(m+k)r^2 per iteration,
+summed over stages) / seconds per step.  One JSON line is printed.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nTT GFLOP/s & decomps/s, p50/p99 latency; BF16 vs FP32 at equal rel. error"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tt32x5_r8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(A, w, seconds):
+    """The FP64 oracle on this host, on a bounded sample: MU iterations of stage 1."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    X = A.reshape(A.shape[0], -1).astype(np.float64)
+    m, k = X.shape
+    r = w.target_ranks[1]
+    W, H = O.init_factors(w.seed, 1, m, r, k)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        W, H = O.mu_step(X, W, H, w.eps)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 500:
+            break
+    flops = n * (4.0 * m * k * r + 4.0 * (m + k) * r * r)
+    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}) of the same workload, "
+                      f"NumPy FP64, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth as S
+    from paper_2008_01340_amd import ntt
+
+    w = S.workload(args.workload)
+    A_host = w.tensor()
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(A_host).to(dev)
+    d = len(w.dims)
+    plan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed)
+    nbytes, eff, comp = plan.workspace()
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    cores = [torch.empty((eff[k], w.dims[k], eff[k + 1]), dtype=torch.float32, device=dev)
+             for k in range(d)]
+    tt_ws_bytes = ntt.ntt_tt_workspace(w.dims, eff)
+    tt_ws = torch.empty(tt_ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    core_ptrs = [c.data_ptr() for c in cores]
+
+    def step():
+        ntt.ntt_decompose(plan, stream, ws.data_ptr(), A.data_ptr(), core_ptrs, want_report=False)
+        return ntt.ntt_rel_error(w.dims, eff, A.data_ptr(), core_ptrs, tt_ws.data_ptr(),
+                                 tt_ws_bytes, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        err = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+
+    # stage shapes and algorithmic flops
+    shapes = []
+    for l in range(1, d):
+        m = eff[l - 1] * w.dims[l - 1]
+        k = int(np.prod(w.dims[l:]))
+        shapes.append((m, k, eff[l]))
+    gflop = sum(w.iters * (4.0 * m * k * r + 4.0 * (m + k) * r * r) for m, k, r in shapes) * 1e-9
+
+    # dominant kernel: the fused X pass of stage 1, timed per launch with HIP events
+    prof_plan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed,
+                         flags=ntt.NTT_PROFILE)
+    rep = ntt.ntt_decompose(prof_plan, stream, ws.data_ptr(), A.data_ptr(), core_ptrs)
+    m1, k1, r1 = shapes[0]
+    bytes_per_launch = 4.0 * m1 * k1 + 8.0 * r1 * k1 + 4.0 * m1 * r1
+    pass_ms = rep["pass_ms"][0]
+    achieved = bytes_per_launch / (pass_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": gflop / (ms * 1e-3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.note}", "dims": list(w.dims), "ranks": eff,
+                   "mu_iters_per_stage": w.iters, "precision": "fp32", "eps": w.eps},
+        "decomps_per_s": 1e3 / ms,
+        "gflop_per_step": gflop,
+        "rel_error": err,
+        "stage_ms": rep["ms"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
+                     "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * ntt.h -- C ABI of the MI355X non-negative tensor-train (nTT) library.
+ *
+ * The library factors a d-way non-negative tensor A (n_1 x ... x n_d) into TT cores
+ * G_1..G_d, G_k of shape r_{k-1} x n_k x r_k with r_0 = r_d = 1, so that
+ *     A[i_1..i_d] ~= sum_{k_1..k_{d-1}} G_1[i_1,k_1] G_2[k_1,i_2,k_2] ... G_d[k_{d-1},i_d]
+ * (paper: Eq.(1) and Eq.(2), the TT format).  The factorisation is the sequential
+ * sweep of Alg.2 (distnTT) run on one GPU: stage l unfolds the remaining tensor into
+ * an (r_{l-1} n_l) x (n_{l+1}...n_d) matrix X_l, factors X_l ~= W H by NMF with
+ * multiplicative updates (MU, the update the paper times in Sec. IV-B and IV-C),
+ * keeps W as core l and reshapes H into the next unfolding; the last H is core d.
+ *
+ * MU, H first then W, with eps added to the denominators and a clamp at zero:
+ *     H <- max(0, H .* (W^T X) ./ ((W^T W) H + eps))
+ *     W <- max(0, W .* (X H^T) ./ (W (H H^T) + eps))
+ *
+ * Conventions for every entry point
+ *   - Arrays are row-major (C order, last index fastest) float32 unless stated.
+ *   - "device" pointers point into GPU memory of the current HIP device; "host"
+ *     pointers into CPU memory.  All buffers are owned by the caller; the library
+ *     keeps no pointer after a call returns.
+ *   - The library allocates no device memory itself: ntt_decompose and ntt_rel_error
+ *     take a caller-provided device workspace whose size the query functions report.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued on it; every function below returns after its work has completed.
+ *   - Errors come back as ntt_status codes; no C++ exception crosses the ABI.  On
+ *     error the outputs are unspecified, nothing leaks and a plan stays valid.
+ *     ntt_last_error() gives a thread-local detail string of the last failure.
+ *   - A plan is not thread-safe: use one plan per host thread and stream.
+ */
+#ifndef NTT_H_
+#define NTT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NTT_MAX_DIMS 16
+#define NTT_MAX_RANK 32 /* largest TT rank the kernels take (padded to 16 or 32) */
+
+typedef enum {
+  NTT_OK = 0,
+  NTT_ERR_INVALID_ARG = 1,         /* bad shape, rank, count, null pointer */
+  NTT_ERR_RANK_INFEASIBLE = 2,     /* strict mode: r_l > min(r_{l-1} n_l, n_{l+1}..n_d) */
+  NTT_ERR_NEGATIVE_INPUT = 3,      /* input holds a negative, NaN or Inf entry */
+  NTT_ERR_WORKSPACE_TOO_SMALL = 4, /* workspace NULL or smaller than required */
+  NTT_ERR_ZERO_NORM = 5,           /* ||A||_F = 0 where a ratio needs it */
+  NTT_ERR_DEVICE = 6               /* a HIP call failed (detail in ntt_last_error) */
+} ntt_status;
+
+typedef enum {
+  NTT_PREC_FP32 = 0,      /* every GEMM in FP32 (MFMA f32), norms in FP64 */
+  NTT_PREC_BF16_MIXED = 1 /* W^T X and X H^T on a BF16 copy of X with FP32 accumulation;
+                             r x r Grams and epilogues FP32; the last fp32_tail_iters
+                             iterations of each stage FP32; norms FP64 */
+} ntt_precision;
+
+/* ntt_config.flags */
+#define NTT_STRICT_RANKS 1u     /* infeasible rank -> NTT_ERR_RANK_INFEASIBLE (else clamp) */
+#define NTT_VALIDATE_INPUT 2u   /* check A >= 0 and finite before the sweep */
+#define NTT_RECORD_OBJECTIVE 4u /* explicit FP64 objective of every iterate into objective_trace */
+#define NTT_PROFILE 8u          /* fill ntt_report.pass_ms with per-launch kernel timings */
+
+typedef struct {
+  int32_t d;            /* number of modes, 2..NTT_MAX_DIMS */
+  const int64_t* dims;  /* host, d entries n_1..n_d, each >= 1 */
+  const int64_t* ranks; /* host, d+1 entries r_0..r_d with r_0 = r_d = 1, inner >= 1 */
+  int32_t max_iters;    /* MU iterations per stage (>= 0) */
+  double tol;           /* 0: run exactly max_iters.  > 0: stop early at t % check_every == 0
+                           when sqrt(2 f_t)/||X_l|| <= tol or f_{t-K} - f_t <= tol f_{t-K},
+                           f_t = 1/2 ||X_l - W_t H_t||_F^2 evaluated explicitly in FP64 */
+  int32_t check_every;  /* K of the stopping test (>= 1) */
+  double eps;           /* MU denominator epsilon (>= 0); 1e-12 is usual */
+  uint64_t seed;        /* initial factors: SplitMix64 counter rule, W of stage l on stream
+                           2l, H on stream 2l+1, uniform on [0,1) (exact in FP32) */
+  int32_t precision;    /* ntt_precision */
+  int32_t fp32_tail_iters; /* BF16 mode: last N iterations of each stage in FP32 */
+  uint32_t flags;       /* NTT_* flags above */
+} ntt_config;
+
+typedef struct {
+  int64_t eff_ranks[NTT_MAX_DIMS + 1]; /* ranks after clamping */
+  int32_t iters[NTT_MAX_DIMS];         /* iterations run per stage */
+  double objective[NTT_MAX_DIMS];      /* final 1/2||X_l - W H||^2 per stage (explicit, FP64) */
+  double norm_x[NTT_MAX_DIMS];         /* ||X_l||_F per stage (FP64) */
+  double stage_rel_err[NTT_MAX_DIMS];  /* sqrt(2 objective)/norm_x per stage */
+  double ms[NTT_MAX_DIMS];             /* wall time per stage on the stream (hipEvents) */
+  double gflop[NTT_MAX_DIMS];          /* algorithmic GFLOP per stage: T(4mkr + 4(m+k)r^2) */
+  double pass_ms[NTT_MAX_DIMS];        /* NTT_PROFILE: mean duration of one MU iteration's
+                                          main X pass kernel per stage */
+  double total_ms;
+  double total_gflop;
+  double compression_ratio;            /* Eq.(4) at eff_ranks */
+} ntt_report;
+
+typedef struct ntt_plan_s* ntt_plan_t;
+
+/* Build a plan from a config (host only, no device work).  Validates the shape
+ * (d in 2..16, n_k >= 1, r_0 = r_d = 1, product of dims below 2^62), clamps ranks to
+ * r_l <= min(r_{l-1} n_l, n_{l+1}...n_d) left to right (or fails with
+ * NTT_ERR_RANK_INFEASIBLE under NTT_STRICT_RANKS), rejects an effective rank above
+ * NTT_MAX_RANK, and lays out the workspace.  *out is owned by the caller and freed
+ * with ntt_plan_destroy. */
+ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out);
+
+/* Query a plan: device workspace bytes ntt_decompose needs (bytes may be NULL),
+ * effective ranks (host array of d+1 entries, may be NULL) and the Eq.(4)
+ * compression ratio prod n_i / sum n_i r_{i-1} r_i at those ranks (may be NULL). */
+ntt_status ntt_plan_workspace(ntt_plan_t plan, size_t* bytes, int64_t* eff_ranks,
+                              double* compression);
+
+/* Run the sweep (Alg.2 with MU as the NMF, ranks given).
+ *   workspace : device, >= ntt_plan_workspace bytes, 256-byte aligned; contents on
+ *               entry are ignored, on exit unspecified.
+ *   A         : device, n_1*...*n_d floats, read only (never written).
+ *   cores     : host array of d device pointers; cores[k] receives G_{k+1} as
+ *               r_k x n_{k+1} x r_{k+1} floats (eff ranks).  Must not alias A or the
+ *               workspace.
+ *   init_W, init_H : NULL, or host arrays of d-1 device pointers giving W0 (m_l x r_l)
+ *               and H0 (r_l x k_l) per stage instead of the seeded rule; an entry may
+ *               be NULL to use the rule for that stage.
+ *   objective_trace : NULL, or device doubles, one per iteration of every stage in
+ *               order (sum over stages of max_iters); with NTT_RECORD_OBJECTIVE it
+ *               receives f_t = 1/2||X_l - W_t H_t||^2 after each iteration t.
+ *   report    : NULL or host struct filled on success.
+ * Returns after the stream has finished the sweep. */
+ntt_status ntt_decompose(ntt_plan_t plan, void* stream, void* workspace, const float* A,
+                         float* const* cores, const float* const* init_W,
+                         const float* const* init_H, double* objective_trace,
+                         ntt_report* report);
+
+/* Device bytes ntt_rel_error needs as workspace for a TT of this shape. */
+ntt_status ntt_tt_workspace(int32_t d, const int64_t* dims, const int64_t* ranks, size_t* bytes);
+
+/* Eq.(1)/(2): expand TT cores into the full tensor.
+ *   dims, ranks : host, d and d+1 entries (r_0 = r_d = 1, every r_k <= NTT_MAX_RANK).
+ *   cores       : host array of d device pointers, cores[k] is r_k x n_{k+1} x r_{k+1}.
+ *   A_out       : device, n_1*...*n_d floats, written. */
+ntt_status ntt_reconstruct(int32_t d, const int64_t* dims, const int64_t* ranks,
+                           const float* const* cores, float* A_out, void* stream);
+
+/* Eq.(3): *rel_err (host) = ||A - Ahat||_F / ||A||_F with Ahat the TT of `cores`, never
+ * materialised: the last contraction is fused with a streaming read of A and the
+ * squares are summed in FP64.  workspace: device, >= ntt_tt_workspace bytes.
+ * Returns NTT_ERR_ZERO_NORM when ||A||_F = 0. */
+ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_t* ranks, const float* A,
+                         const float* const* cores, void* workspace, size_t workspace_bytes,
+                         double* rel_err, void* stream);
+
+/* Eq.(4) for arbitrary ranks (host only). */
+double ntt_compression_ratio(int32_t d, const int64_t* dims, const int64_t* ranks);
+
+void ntt_plan_destroy(ntt_plan_t plan);
+const char* ntt_status_string(ntt_status s);
+const char* ntt_last_error(void);
+/* Library version string, e.g. "ntt-mi355x 0.1 gfx950". */
+const char* ntt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTT_H_ */

@@ -1,0 +1,592 @@
+// ntt_api.hip -- plan, workspace layout, stage executor and the C ABI of ntt.h.
+//
+// The executor runs the sweep of Alg.2 with MU as the NMF (ranks given, not chosen by
+// the SVD threshold rule).  Stage l factors X_l, an (r_{l-1} n_l) x (n_{l+1}...n_d)
+// row-major matrix that is a zero-copy view of the input (l = 1) or of the previous
+// stage's H.  W is updated in place inside the caller's core buffer l (its C-order
+// layout r_{l-1} x n_l x r_l is exactly W, m x r_l); H lives in one of two workspace
+// buffers (ping-pong, so X_l and H_l never alias), except that the last stage's H is
+// written straight into core d.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "ntt_internal.h"
+
+using namespace ntt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ntt_status fail(ntt_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(NTT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+constexpr int kFusedMaxRows = 256;   // fused one-pass kernel keeps m <= 16*16 rows in registers
+constexpr int kMaxPassBlocks = 1024; // persistent grid of the fused pass
+constexpr int kSumsqBlocks = 1024;
+constexpr int kGraphIters = 25;     // MU iterations per replayed graph
+constexpr size_t kMaxGraphs = 64;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Stage {
+  int64_t m = 0, k = 0;
+  int r = 0, rp = 16;
+  bool fused = true;
+  int mb = 1;       // fused: 16-row blocks
+  int mpad = 16;    // rows of the partial X H^T
+  int G = 1;        // number of partials (pass workgroups or column chunks)
+  int64_t chunk = 0;  // generic: columns per chunk
+};
+
+}  // namespace
+
+struct ntt_plan_s {
+  ntt_config cfg;
+  int d = 0;
+  int64_t dims[NTT_MAX_DIMS] = {};
+  int64_t eff[NTT_MAX_DIMS + 1] = {};
+  Stage st[NTT_MAX_DIMS];
+  double compression = 0.0;
+  int64_t total_iters = 0;
+  // workspace layout (bytes)
+  size_t off_h[2] = {0, 0};
+  size_t off_part = 0, part_stride = 0, off_rpart = 0, off_red = 0, off_gw = 0;
+  size_t off_scal = 0, off_ints = 0, total = 0;
+  std::vector<hipEvent_t> prof_events;
+  hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
+  bool events_ready = false;
+  // replayable blocks of MU iterations, one per (stage, block length, buffers)
+  struct GraphEntry {
+    int stage, iters;
+    const void *X, *H, *W, *ws;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  ~ntt_plan_s() {
+    for (auto e : prof_events) (void)hipEventDestroy(e);
+    if (events_ready)
+      for (auto e : stage_ev) (void)hipEventDestroy(e);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+static double compression_of(int d, const int64_t* dims, const int64_t* ranks) {
+  double num = 1.0, den = 0.0;
+  for (int i = 0; i < d; ++i) {
+    num *= (double)dims[i];
+    den += (double)dims[i] * (double)ranks[i] * (double)ranks[i + 1];
+  }
+  return num / den;
+}
+
+extern "C" {
+
+const char* ntt_version(void) { return "ntt-mi355x 0.1 gfx950"; }
+
+const char* ntt_last_error(void) { return g_last_error.c_str(); }
+
+const char* ntt_status_string(ntt_status s) {
+  switch (s) {
+    case NTT_OK: return "ok";
+    case NTT_ERR_INVALID_ARG: return "invalid argument";
+    case NTT_ERR_RANK_INFEASIBLE: return "rank infeasible";
+    case NTT_ERR_NEGATIVE_INPUT: return "negative, NaN or Inf input";
+    case NTT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case NTT_ERR_ZERO_NORM: return "zero norm";
+    case NTT_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+double ntt_compression_ratio(int32_t d, const int64_t* dims, const int64_t* ranks) {
+  if (d < 1 || d > NTT_MAX_DIMS || !dims || !ranks) return 0.0;
+  return compression_of(d, dims, ranks);
+}
+
+ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
+  if (!cfg || !out) return fail(NTT_ERR_INVALID_ARG, "null config or output");
+  *out = nullptr;
+  const int d = cfg->d;
+  if (d < 2 || d > NTT_MAX_DIMS) return fail(NTT_ERR_INVALID_ARG, "d must be in 2..16");
+  if (!cfg->dims || !cfg->ranks) return fail(NTT_ERR_INVALID_ARG, "null dims or ranks");
+  if (cfg->max_iters < 0) return fail(NTT_ERR_INVALID_ARG, "max_iters < 0");
+  if (cfg->check_every < 1) return fail(NTT_ERR_INVALID_ARG, "check_every < 1");
+  if (!(cfg->eps >= 0.0) || !std::isfinite(cfg->eps)) return fail(NTT_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (!(cfg->tol >= 0.0) || !std::isfinite(cfg->tol)) return fail(NTT_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (cfg->precision != NTT_PREC_FP32 && cfg->precision != NTT_PREC_BF16_MIXED)
+    return fail(NTT_ERR_INVALID_ARG, "unknown precision");
+  if (cfg->fp32_tail_iters < 0) return fail(NTT_ERR_INVALID_ARG, "fp32_tail_iters < 0");
+  if (cfg->precision == NTT_PREC_BF16_MIXED)
+    return fail(NTT_ERR_INVALID_ARG, "BF16 mixed precision is not available in this build");
+  int64_t total = 1;
+  for (int i = 0; i < d; ++i) {
+    if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
+    if (total > ((int64_t)1 << 62) / cfg->dims[i]) return fail(NTT_ERR_INVALID_ARG, "tensor too large");
+    total *= cfg->dims[i];
+  }
+  if (cfg->ranks[0] != 1 || cfg->ranks[d] != 1) return fail(NTT_ERR_INVALID_ARG, "r_0 and r_d must be 1");
+  for (int i = 1; i < d; ++i)
+    if (cfg->ranks[i] < 1) return fail(NTT_ERR_INVALID_ARG, "inner ranks must be >= 1");
+
+  auto* p = new ntt_plan_s();
+  p->cfg = *cfg;
+  p->cfg.dims = nullptr;
+  p->cfg.ranks = nullptr;
+  p->d = d;
+  for (int i = 0; i < d; ++i) p->dims[i] = cfg->dims[i];
+  // effective ranks: r_l <= min(r_{l-1} n_l, n_{l+1}...n_d), left to right
+  p->eff[0] = 1;
+  for (int l = 1; l < d; ++l) {
+    const int64_t m = p->eff[l - 1] * p->dims[l - 1];
+    int64_t k = 1;
+    for (int j = l; j < d; ++j) k *= p->dims[j];
+    const int64_t r = std::min(cfg->ranks[l], std::min(m, k));
+    if (r != cfg->ranks[l] && (cfg->flags & NTT_STRICT_RANKS)) {
+      delete p;
+      return fail(NTT_ERR_RANK_INFEASIBLE, "rank " + std::to_string(l) + " exceeds min(r_{l-1} n_l, n_{l+1}..n_d)");
+    }
+    if (r > NTT_MAX_RANK) {
+      delete p;
+      return fail(NTT_ERR_INVALID_ARG, "effective rank above NTT_MAX_RANK (32)");
+    }
+    p->eff[l] = r;
+  }
+  p->eff[d] = 1;
+  p->compression = compression_of(d, p->dims, p->eff);
+
+  // stages and workspace
+  size_t hsize[2] = {0, 0};
+  size_t part_stride = 0;
+  int gmax = 1;
+  size_t red_max = 0;
+  for (int l = 1; l < d; ++l) {
+    Stage& s = p->st[l - 1];
+    s.m = p->eff[l - 1] * p->dims[l - 1];
+    s.k = 1;
+    for (int j = l; j < d; ++j) s.k *= p->dims[j];
+    s.r = (int)p->eff[l];
+    s.rp = s.r <= 16 ? 16 : 32;
+    s.fused = s.m <= kFusedMaxRows;
+    const int64_t ngroups = (s.k + 15) / 16;
+    if (s.fused) {
+      const int64_t blocks16 = (s.m + 15) / 16;
+      s.mb = 1;
+      while (s.mb < blocks16) s.mb *= 2;
+      s.mpad = 16 * s.mb;
+      s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, kMaxPassBlocks));
+    } else {
+      s.mpad = (int)align_up((size_t)s.m, 16);
+      const int64_t want = std::max<int64_t>(1, std::min<int64_t>((s.k + 255) / 256, 256));
+      s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
+      s.G = (int)((s.k + s.chunk - 1) / s.chunk);
+    }
+    if (!s.fused) gmax = std::max<int>(gmax, (int)((s.k + 255) / 256));  // residual blocks
+    const size_t E = (size_t)s.mpad * s.rp + (size_t)s.rp * s.rp;
+    part_stride = std::max(part_stride, align_up(E, 64));
+    red_max = std::max(red_max, E);
+    gmax = std::max(gmax, s.G);
+    if (l < d - 1) {
+      const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
+      hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
+    }
+    p->total_iters += cfg->max_iters;
+  }
+  gmax = std::max(gmax, kSumsqBlocks);
+  size_t off = 0;
+  p->off_h[0] = off; off = align_up(off + hsize[0], 256);
+  p->off_h[1] = off; off = align_up(off + hsize[1], 256);
+  p->part_stride = part_stride;
+  p->off_part = off; off = align_up(off + (size_t)gmax * part_stride * sizeof(float), 256);
+  p->off_rpart = off; off = align_up(off + (size_t)gmax * sizeof(double), 256);
+  p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
+  p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
+  p->off_scal = off; off = align_up(off + SCAL_COUNT * sizeof(double), 256);
+  p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
+  p->total = off;
+  *out = p;
+  return NTT_OK;
+}
+
+ntt_status ntt_plan_workspace(ntt_plan_t p, size_t* bytes, int64_t* eff_ranks, double* compression) {
+  if (!p) return fail(NTT_ERR_INVALID_ARG, "null plan");
+  if (bytes) *bytes = p->total;
+  if (eff_ranks)
+    for (int i = 0; i <= p->d; ++i) eff_ranks[i] = p->eff[i];
+  if (compression) *compression = p->compression;
+  return NTT_OK;
+}
+
+void ntt_plan_destroy(ntt_plan_t p) { delete p; }
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_zero_ints(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+struct Ctx {
+  ntt_plan_s* p;
+  hipStream_t s;
+  char* ws;
+  float* part() const { return reinterpret_cast<float*>(ws + p->off_part); }
+  double* rpart() const { return reinterpret_cast<double*>(ws + p->off_rpart); }
+  double* red() const { return reinterpret_cast<double*>(ws + p->off_red); }
+  float* gw() const { return reinterpret_cast<float*>(ws + p->off_gw); }
+  double* scal() const { return reinterpret_cast<double*>(ws + p->off_scal); }
+  int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }  // [0] flags, [1] ticket
+};
+
+PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
+  PassArgs a;
+  a.X = X;
+  a.H = H;
+  a.W = W;
+  a.GW = c.gw();
+  a.part = c.part();
+  a.part_stride = (int64_t)c.p->part_stride;
+  a.rpart = c.rpart();
+  a.m = (int)s.m;
+  a.r = s.r;
+  a.mpad = s.mpad;
+  a.k = s.k;
+  a.eps = eps;
+  return a;
+}
+
+hipError_t run_pass(const Ctx& c, const Stage& s, const PassArgs& a, bool update, bool resid) {
+  if (s.fused) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, c.s);
+  return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, c.s);
+}
+
+int resid_blocks(const Stage& s) {
+  return s.fused ? s.G : (int)((s.k + 255) / 256);
+}
+
+}  // namespace
+
+extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace, const float* A,
+                                    float* const* cores, const float* const* init_W,
+                                    const float* const* init_H, double* objective_trace,
+                                    ntt_report* report) {
+  if (!p) return fail(NTT_ERR_INVALID_ARG, "null plan");
+  if (!workspace) return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(NTT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (!A || !cores) return fail(NTT_ERR_INVALID_ARG, "null A or cores");
+  const int d = p->d;
+  for (int i = 0; i < d; ++i)
+    if (!cores[i]) return fail(NTT_ERR_INVALID_ARG, "null core pointer");
+  const ntt_config& cfg = p->cfg;
+  const bool record = (cfg.flags & NTT_RECORD_OBJECTIVE) && objective_trace;
+  const bool profile = (cfg.flags & NTT_PROFILE) && report;
+  const bool want_final = record || report || cfg.tol > 0.0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Ctx c{p, s, reinterpret_cast<char*>(workspace)};
+  const float eps = (float)cfg.eps;
+
+  if (!p->events_ready) {
+    for (auto& e : p->stage_ev) HIP_TRY(hipEventCreate(&e));
+    p->events_ready = true;
+  }
+  if (profile && (int64_t)p->prof_events.size() < 2 * (int64_t)cfg.max_iters) {
+    const size_t need = 2 * (size_t)cfg.max_iters;
+    while (p->prof_events.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      p->prof_events.push_back(e);
+    }
+  }
+  ntt_report rep;
+  memset(&rep, 0, sizeof(rep));
+  for (int i = 0; i <= d; ++i) rep.eff_ranks[i] = p->eff[i];
+  rep.compression_ratio = p->compression;
+
+  k_zero_ints<<<1, 64, 0, s>>>(c.ints(), 64);
+  HIP_TRY(hipGetLastError());
+
+  int64_t trace_off = 0;
+  for (int l = 1; l < d; ++l) {
+    const Stage& st = p->st[l - 1];
+    const float* X = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
+    float* H = (l == d - 1) ? cores[d - 1] : reinterpret_cast<float*>(c.ws + p->off_h[(l - 1) & 1]);
+    float* W = cores[l - 1];
+    const int64_t mr = st.m * st.r, rk = (int64_t)st.r * st.k;
+    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1)], s));
+
+    // a1: ||X_l||^2 in FP64 (and the input check on the first unfolding)
+    const bool validate = (l == 1) && (cfg.flags & NTT_VALIDATE_INPUT);
+    HIP_TRY(launch_sumsq(X, st.m * st.k, c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
+                         c.scal() + SCAL_NX2, s));
+    if (validate) {
+      int flag = 0;
+      HIP_TRY(hipMemcpyAsync(&flag, c.ints(), sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (flag) return fail(NTT_ERR_NEGATIVE_INPUT, "input holds a negative, NaN or Inf entry");
+    }
+    // a2: initial factors
+    if (init_W && init_W[l - 1]) HIP_TRY(launch_copy(W, init_W[l - 1], mr, s));
+    else HIP_TRY(launch_init_uniform(W, mr, cfg.seed, 2ull * l, s));
+    if (init_H && init_H[l - 1]) HIP_TRY(launch_copy(H, init_H[l - 1], rk, s));
+    else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, s));
+    HIP_TRY(launch_gram_w(W, (int)st.m, st.r, st.rp, c.gw(), s));
+
+    const PassArgs pa = pass_args(c, st, X, H, W, eps);
+    FinArgs fa;
+    fa.part = c.part();
+    fa.part_stride = (int64_t)p->part_stride;
+    fa.G = st.G;
+    fa.mpad = st.mpad;
+    fa.m = (int)st.m;
+    fa.r = st.r;
+    fa.red = c.red();
+    fa.W = W;
+    fa.Wsrc = W;
+    fa.GW = c.gw();
+    fa.scal = c.scal();
+    fa.counter = c.ints() + 1;
+    fa.eps = eps;
+
+    auto residual_now = [&](double* trace_slot) -> hipError_t {
+      hipError_t e = run_pass(c, st, pa, false, true);
+      if (e != hipSuccess) return e;
+      return launch_resid_sum(c.rpart(), resid_blocks(st), c.scal() + SCAL_OBJ, trace_slot, s);
+    };
+    std::vector<double> fhist;
+    double nx = 0.0;
+    if (cfg.tol > 0.0) {
+      HIP_TRY(residual_now(nullptr));
+      double h2[2];
+      HIP_TRY(hipMemcpyAsync(h2, c.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      nx = std::sqrt(h2[SCAL_NX2]);
+      fhist.push_back(h2[SCAL_OBJ]);
+    }
+    int t_done = 0;
+    bool final_known = false;
+    // MU iterations (a3 + a4): each is the fused X pass (H-update and partials)
+    // followed by the W-update; blocks of them replay as graphs when nothing is recorded
+    const bool use_graph = !record && !profile && cfg.max_iters > 1;
+    auto graph_for = [&](int n, hipGraphExec_t* out) -> hipError_t {
+      for (auto& g : p->graphs)
+        if (g.stage == l && g.iters == n && g.X == X && g.H == H && g.W == W && g.ws == workspace) {
+          *out = g.exec;
+          return hipSuccess;
+        }
+      hipError_t e;
+      if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+      }
+      Ctx cc = c;
+      cc.s = p->cap_stream;
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      hipError_t le = hipSuccess;
+      for (int i = 0; i < n && le == hipSuccess; ++i) {
+        le = run_pass(cc, st, pa, true, false);
+        if (le == hipSuccess) {
+          FinArgs f2 = fa;
+          f2.rpart = nullptr;
+          f2.trace = nullptr;
+          le = launch_finalize(f2, st.rp, p->cap_stream);
+        }
+      }
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(p->cap_stream, &graph);
+      if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le;
+      }
+      if (e != hipSuccess) return e;
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return e;
+      if (p->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        p->graphs.erase(p->graphs.begin());
+      }
+      p->graphs.push_back({l, n, X, H, W, workspace, exec});
+      *out = exec;
+      return hipSuccess;
+    };
+    int t = 0;
+    while (t < cfg.max_iters) {
+      // iterations up to the next stopping check (or the end)
+      int block = cfg.max_iters - t;
+      if (cfg.tol > 0.0) block = std::min(block, cfg.check_every - (t % cfg.check_every));
+      if (use_graph) {
+        while (block >= kGraphIters || (block > 1 && cfg.tol > 0.0)) {
+          const int n = std::min(block, kGraphIters);
+          hipGraphExec_t ex = nullptr;
+          HIP_TRY(graph_for(n, &ex));
+          HIP_TRY(hipGraphLaunch(ex, s));
+          t += n;
+          block -= n;
+        }
+      }
+      for (; block > 0; --block) {
+        ++t;
+        const bool resid = record;  // f_{t-1} of the incoming iterate
+        double* slot = (resid && t >= 2) ? objective_trace + trace_off + (t - 2) : nullptr;
+        if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1)], s));
+        HIP_TRY(run_pass(c, st, pa, true, resid));
+        if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1) + 1], s));
+        FinArgs f2 = fa;
+        if (resid && !st.fused) {
+          HIP_TRY(launch_resid_sum(c.rpart(), resid_blocks(st), c.scal() + SCAL_OBJ, slot, s));
+          f2.rpart = nullptr;
+          f2.trace = nullptr;
+        } else {
+          f2.rpart = resid ? c.rpart() : nullptr;
+          f2.trace = resid ? slot : nullptr;
+        }
+        HIP_TRY(launch_finalize(f2, st.rp, s));
+      }
+      t_done = t;
+      final_known = false;
+      if (cfg.tol > 0.0 && t % cfg.check_every == 0) {
+        HIP_TRY(residual_now(record ? objective_trace + trace_off + (t - 1) : nullptr));
+        double ft = 0.0;
+        HIP_TRY(hipMemcpyAsync(&ft, c.scal() + SCAL_OBJ, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        fhist.resize(t + 1, 0.0);
+        fhist[t] = ft;
+        final_known = true;
+        const double fprev = fhist[t - cfg.check_every];
+        if (std::sqrt(2.0 * std::max(ft, 0.0)) / nx <= cfg.tol || (fprev - ft) <= cfg.tol * fprev) break;
+      }
+    }
+    if (want_final && !final_known)
+      HIP_TRY(residual_now((record && t_done >= 1) ? objective_trace + trace_off + (t_done - 1) : nullptr));
+    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1) + 1], s));
+    rep.iters[l - 1] = t_done;
+    rep.gflop[l - 1] = (double)t_done * (4.0 * st.m * st.k * st.r + 4.0 * (st.m + st.k) * st.r * st.r) * 1e-9;
+    if (report) {
+      double h2[2];
+      HIP_TRY(hipMemcpyAsync(h2, c.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      rep.norm_x[l - 1] = std::sqrt(h2[SCAL_NX2]);
+      rep.objective[l - 1] = h2[SCAL_OBJ];
+      rep.stage_rel_err[l - 1] =
+          rep.norm_x[l - 1] > 0 ? std::sqrt(2.0 * std::max(h2[SCAL_OBJ], 0.0)) / rep.norm_x[l - 1] : 0.0;
+      if (profile && t_done > 0) {
+        double sum = 0.0;
+        for (int t = 0; t < t_done; ++t) {
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, p->prof_events[2 * t], p->prof_events[2 * t + 1]));
+          sum += ms;
+        }
+        rep.pass_ms[l - 1] = sum / t_done;
+      }
+    }
+    trace_off += cfg.max_iters;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (report) {
+    for (int l = 1; l < d; ++l) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, p->stage_ev[2 * (l - 1)], p->stage_ev[2 * (l - 1) + 1]));
+      rep.ms[l - 1] = ms;
+      rep.total_ms += ms;
+      rep.total_gflop += rep.gflop[l - 1];
+    }
+    *report = rep;
+  }
+  return NTT_OK;
+}
+
+// ------------------------------------------------------------------ TT expansion entry points
+static ntt_status tt_args(int32_t d, const int64_t* dims, const int64_t* ranks,
+                          const float* const* cores, TTArgs* t) {
+  if (d < 2 || d > NTT_MAX_DIMS) return fail(NTT_ERR_INVALID_ARG, "d must be in 2..16");
+  if (!dims || !ranks || !cores) return fail(NTT_ERR_INVALID_ARG, "null dims, ranks or cores");
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(NTT_ERR_INVALID_ARG, "r_0 and r_d must be 1");
+  memset(t, 0, sizeof(*t));
+  t->d = d;
+  int64_t rows = 1;
+  for (int i = 0; i < d; ++i) {
+    if (dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
+    if (!cores[i]) return fail(NTT_ERR_INVALID_ARG, "null core pointer");
+    t->dims[i] = dims[i];
+    t->cores[i] = cores[i];
+    if (i < d - 1) {
+      if (rows > ((int64_t)1 << 62) / dims[i]) return fail(NTT_ERR_INVALID_ARG, "tensor too large");
+      rows *= dims[i];
+    }
+  }
+  if (rows > ((int64_t)1 << 62) / dims[d - 1]) return fail(NTT_ERR_INVALID_ARG, "tensor too large");
+  for (int i = 0; i <= d; ++i) {
+    if (ranks[i] < 1 || ranks[i] > NTT_MAX_RANK) return fail(NTT_ERR_INVALID_ARG, "ranks must be in 1..32");
+    t->ranks[i] = (int)ranks[i];
+  }
+  t->rows = rows;
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_tt_workspace(int32_t d, const int64_t* dims, const int64_t* ranks, size_t* bytes) {
+  TTArgs t;
+  std::vector<const float*> dummy(NTT_MAX_DIMS, reinterpret_cast<const float*>(16));
+  ntt_status st = tt_args(d, dims, ranks, dummy.data(), &t);
+  if (st != NTT_OK) return st;
+  if (!bytes) return fail(NTT_ERR_INVALID_ARG, "null bytes");
+  const int64_t nb = (t.rows + 63) / 64;
+  *bytes = align_up((size_t)(2 * nb + 2) * sizeof(double), 256);
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_reconstruct(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                      const float* const* cores, float* A_out, void* stream) {
+  TTArgs t;
+  ntt_status st = tt_args(d, dims, ranks, cores, &t);
+  if (st != NTT_OK) return st;
+  if (!A_out) return fail(NTT_ERR_INVALID_ARG, "null output");
+  t.out = A_out;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_tt_expand(t, 0, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_t* ranks, const float* A,
+                                    const float* const* cores, void* workspace, size_t workspace_bytes,
+                                    double* rel_err, void* stream) {
+  TTArgs t;
+  ntt_status st = tt_args(d, dims, ranks, cores, &t);
+  if (st != NTT_OK) return st;
+  if (!A || !rel_err) return fail(NTT_ERR_INVALID_ARG, "null A or rel_err");
+  size_t need = 0;
+  ntt_tt_workspace(d, dims, ranks, &need);
+  if (!workspace || workspace_bytes < need) return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  t.A = A;
+  t.part = reinterpret_cast<double*>(workspace);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_tt_expand(t, 1, s));
+  const int64_t nb = (t.rows + 63) / 64;
+  double tot[2];
+  HIP_TRY(hipMemcpyAsync(tot, t.part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(tot[1] > 0.0)) return fail(NTT_ERR_ZERO_NORM, "||A||_F = 0");
+  *rel_err = std::sqrt(tot[0] / tot[1]);
+  return NTT_OK;
+}

@@ -1,0 +1,72 @@
+// ntt_internal.h -- kernel argument blocks and launchers shared by the library sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/ntt.h"
+
+namespace ntt {
+
+// FP64 scalars kept on the device per stage
+enum { SCAL_NX2 = 0, SCAL_OBJ = 1, SCAL_MONITOR = 2, SCAL_OBJ0 = 3, SCAL_COUNT = 8 };
+
+// One MU pass over the columns of an m x k unfolding.
+struct PassArgs {
+  const float* X;       // m x k, row stride k
+  float* H;             // r x k, row stride k (updated in place)
+  const float* W;       // m x r
+  const float* GW;      // RP x RP, W^T W zero padded
+  float* part;          // per-workgroup partials: [mpad][RP] X H^T, then [RP][RP] H H^T
+  int64_t part_stride;  // floats between workgroups' partials
+  double* rpart;        // per-workgroup residual sums (FP64)
+  int m, r, mpad;
+  int64_t k;
+  float eps;
+};
+
+// Reduction of the pass partials and the W-update.
+struct FinArgs {
+  const float* part;
+  int64_t part_stride;
+  int G;           // number of partials
+  int mpad, m, r;
+  double* red;     // reduced X H^T (mpad x RP) then H H^T (RP x RP), FP64
+  float* W;        // m x r, updated in place
+  const float* Wsrc;  // same buffer as W: old entries are read before being written
+  float* GW;       // RP x RP, receives W'^T W'
+  double* scal;    // SCAL_* scalars
+  const double* rpart;  // residual partials of this pass (NULL when none)
+  double* trace;   // where to store the residual objective (NULL: do not store)
+  int* counter;    // ticket, 0 on entry, reset to 0 on exit
+  float eps;
+};
+
+// TT expansion (Eq.(2)) over the rows of the (n_1...n_{d-1}) x n_d matrix.
+struct TTArgs {
+  int d;
+  int64_t rows;
+  int64_t dims[NTT_MAX_DIMS];
+  int ranks[NTT_MAX_DIMS + 1];
+  const float* cores[NTT_MAX_DIMS];
+  const float* A;  // MODE 1 input
+  float* out;      // MODE 0 output
+  double* part;    // MODE 1 per-block (err, ref) pairs, then the two totals
+};
+
+hipError_t launch_init_uniform(float* out, int64_t n, uint64_t seed, uint64_t tag, hipStream_t s);
+hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, int* flags,
+                        int validate, double* out, hipStream_t s);
+hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
+hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
+                             hipStream_t s);
+hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
+                               bool resid, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);
+hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
+hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
+
+}  // namespace ntt

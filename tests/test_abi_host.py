@@ -1,0 +1,131 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared symbol,
+and the plan (no device work) validates, clamps and sizes correctly."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle as O
+from paper_2008_01340_amd import ntt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ntt.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(ntt_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ntt.load()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = _declared_functions()
+    for want in ["ntt_plan", "ntt_decompose", "ntt_reconstruct", "ntt_rel_error"]:
+        assert want in names
+    assert sorted(names) == sorted(ntt.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", ntt.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in _declared_functions():
+        assert name in exported, name
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in ntt.ntt_version()
+    for s in range(7):
+        assert lib.ntt_status_string(s).decode()
+    assert lib.ntt_status_string(99).decode() == "unknown status"
+
+
+def test_plan_clamps_ranks_like_the_oracle():
+    for dims, ranks in [((2, 3, 4), (1, 5, 5, 1)), ((16, 16, 16), (1, 4, 4, 1)),
+                        ((4, 100, 2), (1, 50, 50, 1)), ((3, 3, 3, 3), (1, 9, 9, 9, 1))]:
+        p = ntt.Plan(dims, ranks, 10)
+        nbytes, eff, comp = p.workspace()
+        assert eff == O.effective_ranks(dims, ranks)
+        assert comp == pytest.approx(O.compression_ratio(dims, eff), rel=1e-14)
+        assert nbytes > 0 and nbytes % 256 == 0
+
+
+def test_plan_strict_ranks_errors():
+    with pytest.raises(ntt.NttError) as e:
+        ntt.Plan((2, 3, 4), (1, 5, 5, 1), 10, flags=ntt.NTT_STRICT_RANKS)
+    assert e.value.status == ntt.NTT_ERR_RANK_INFEASIBLE
+    ntt.Plan((16, 16, 16), (1, 4, 4, 1), 10, flags=ntt.NTT_STRICT_RANKS)
+
+
+@pytest.mark.parametrize("kw,dims,ranks", [
+    ({}, (5,), (1, 1)),                          # d < 2
+    ({}, (4, 0, 3), (1, 2, 2, 1)),               # zero mode
+    ({}, (4, 5, 3), (2, 2, 2, 1)),               # r_0 != 1
+    ({}, (4, 5, 3), (1, 2, 2, 3)),               # r_d != 1
+    ({}, (4, 5, 3), (1, 0, 2, 1)),               # zero rank
+    ({"max_iters": -1}, (4, 5), (1, 2, 1)),
+    ({"check_every": 0}, (4, 5), (1, 2, 1)),
+    ({"eps": -1.0}, (4, 5), (1, 2, 1)),
+    ({"eps": float("nan")}, (4, 5), (1, 2, 1)),
+    ({"tol": -0.1}, (4, 5), (1, 2, 1)),
+    ({"precision": 7}, (4, 5), (1, 2, 1)),
+    ({}, (64, 64, 64), (1, 40, 40, 1)),          # effective rank above 32
+    ({}, (1 << 32, 1 << 32, 4), (1, 1, 1, 1)),   # product overflows
+])
+def test_plan_rejects_invalid_configs(kw, dims, ranks):
+    args = {"max_iters": 10}
+    args.update(kw)
+    it = args.pop("max_iters")
+    with pytest.raises(ntt.NttError) as e:
+        ntt.Plan(dims, ranks, it, **args)
+    assert e.value.status == ntt.NTT_ERR_INVALID_ARG
+
+
+def test_plan_null_pointers(lib):
+    assert lib.ntt_plan(None, None) == ntt.NTT_ERR_INVALID_ARG
+    assert lib.ntt_plan_workspace(None, None, None, None) == ntt.NTT_ERR_INVALID_ARG
+    assert "null" in lib.ntt_last_error().decode()
+    lib.ntt_plan_destroy(None)  # no-op
+
+
+def test_decompose_argument_errors_without_device_work(lib):
+    p = ntt.Plan((4, 5), (1, 2, 1), 3)
+    # null workspace and null tensor are rejected before any HIP call
+    st = lib.ntt_decompose(p.handle, None, None, None, None, None, None, None, None)
+    assert st == ntt.NTT_ERR_WORKSPACE_TOO_SMALL
+    st = lib.ntt_decompose(p.handle, None, ctypes.c_void_p(256), None, None, None, None, None, None)
+    assert st == ntt.NTT_ERR_INVALID_ARG
+    st = lib.ntt_decompose(p.handle, None, ctypes.c_void_p(257), ctypes.c_void_p(256),
+                           ntt._ptrs([256, 512]), None, None, None, None)
+    assert st == ntt.NTT_ERR_INVALID_ARG  # misaligned workspace
+
+
+def test_tt_workspace_and_validation():
+    n = ntt.ntt_tt_workspace((4, 5, 6), (1, 2, 3, 1))
+    assert n >= 2 * 8 and n % 256 == 0
+    for dims, ranks in [((4,), (1, 1)), ((4, 5), (1, 33, 1)), ((4, 5), (2, 2, 1))]:
+        with pytest.raises(ntt.NttError):
+            ntt.ntt_tt_workspace(dims, ranks)
+
+
+def test_compression_ratio_entry_point_matches_eq4_pins():
+    assert ntt.ntt_compression_ratio((48, 42, 64, 38), (1, 1, 1, 1, 1)) == pytest.approx(25536.0)
+    assert ntt.ntt_compression_ratio((100, 260, 3, 85), (1, 1, 1, 1, 1)) == pytest.approx(14799.107142857143)
+
+
+def test_workspace_scales_with_the_problem():
+    small = ntt.Plan((16, 16, 16), (1, 4, 4, 1), 10).workspace()[0]
+    big = ntt.Plan((32,) * 5, (1, 8, 8, 8, 8, 1), 10).workspace()[0]
+    # the 32^5 sweep holds H_1 (8 x 32^4 floats) in the workspace
+    assert big >= 8 * 32 ** 4 * 4
+    assert small < big
