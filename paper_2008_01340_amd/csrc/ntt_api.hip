@@ -49,7 +49,6 @@ struct Stage {
   int r = 0, rp = 16;
   bool fused = true;
   int mb = 1;       // fused: 16-row blocks
-  int mpad = 16;    // rows of the partial X H^T
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
 };
@@ -190,16 +189,14 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
       const int64_t blocks16 = (s.m + 15) / 16;
       s.mb = 1;
       while (s.mb < blocks16) s.mb *= 2;
-      s.mpad = 16 * s.mb;
       s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, kMaxPassBlocks));
     } else {
-      s.mpad = (int)align_up((size_t)s.m, 16);
       const int64_t want = std::max<int64_t>(1, std::min<int64_t>((s.k + 255) / 256, 256));
       s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
       s.G = (int)((s.k + s.chunk - 1) / s.chunk);
     }
     if (!s.fused) gmax = std::max<int>(gmax, (int)((s.k + 255) / 256));  // residual blocks
-    const size_t E = (size_t)s.mpad * s.rp + (size_t)s.rp * s.rp;
+    const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
     part_stride = std::max(part_stride, align_up(E, 64));
     red_max = std::max(red_max, E);
     gmax = std::max(gmax, s.G);
@@ -267,7 +264,6 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
   a.rpart = c.rpart();
   a.m = (int)s.m;
   a.r = s.r;
-  a.mpad = s.mpad;
   a.k = s.k;
   a.eps = eps;
   return a;
@@ -355,15 +351,12 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
     fa.part = c.part();
     fa.part_stride = (int64_t)p->part_stride;
     fa.G = st.G;
-    fa.mpad = st.mpad;
     fa.m = (int)st.m;
     fa.r = st.r;
     fa.red = c.red();
     fa.W = W;
-    fa.Wsrc = W;
     fa.GW = c.gw();
     fa.scal = c.scal();
-    fa.counter = c.ints() + 1;
     fa.eps = eps;
 
     auto residual_now = [&](double* trace_slot) -> hipError_t {

@@ -19,10 +19,10 @@ struct PassArgs {
   float* H;             // r x k, row stride k (updated in place)
   const float* W;       // m x r
   const float* GW;      // RP x RP, W^T W zero padded
-  float* part;          // per-workgroup partials: [mpad][RP] X H^T, then [RP][RP] H H^T
+  float* part;          // per-workgroup partials: [m][r] X H^T, then [r][r] H H^T
   int64_t part_stride;  // floats between workgroups' partials
   double* rpart;        // per-workgroup residual sums (FP64)
-  int m, r, mpad;
+  int m, r;
   int64_t k;
   float eps;
 };
@@ -32,15 +32,13 @@ struct FinArgs {
   const float* part;
   int64_t part_stride;
   int G;           // number of partials
-  int mpad, m, r;
-  double* red;     // reduced X H^T (mpad x RP) then H H^T (RP x RP), FP64
+  int m, r;
+  double* red;     // reduced X H^T (m x r) then H H^T (r x r), FP64
   float* W;        // m x r, updated in place
-  const float* Wsrc;  // same buffer as W: old entries are read before being written
   float* GW;       // RP x RP, receives W'^T W'
   double* scal;    // SCAL_* scalars
   const double* rpart;  // residual partials of this pass (NULL when none)
   double* trace;   // where to store the residual objective (NULL: do not store)
-  int* counter;    // ticket, 0 on entry, reset to 0 on exit
   float eps;
 };
 

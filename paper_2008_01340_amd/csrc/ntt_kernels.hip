@@ -159,17 +159,28 @@ __global__ __launch_bounds__(256) void k_gram_w(const float* __restrict__ W, int
 }
 
 // ------------------------------------------------------------------ fused MU pass
+// x / y by the hardware reciprocal and one Newton-Raphson correction
+// (q0 = x r, e = x - y q0, q = q0 + e r): within about 1 ulp for normal y.
+__device__ __forceinline__ float fast_div(float x, float y) {
+  const float r = __builtin_amdgcn_rcpf(y);
+  const float q0 = x * r;
+  const float e = fmaf(-y, q0, x);
+  return fmaf(e, r, q0);
+}
+
 // Variant for m <= 16*MB (MB 16-row blocks held in registers) and r <= RP.
 // Each wavefront takes 16-column groups (group g = global wave id + s * total waves).
 // UPDATE: do the H-update and accumulate X H_new^T and H_new H_new^T partials.
 // RESID : accumulate sum (X - W H_in)^2 in FP64 over the incoming W, H.
+// Per-workgroup partial (written when UPDATE): X H_new^T as m x r, then H_new H_new^T
+// as r x r, both row-major and compact.
 template <int RP, int MB, bool UPDATE, bool RESID>
 __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   constexpr int NH = RP / 16;  // 16-row halves of the padded rank
   constexpr int MPAD = 16 * MB;
   constexpr int SX = 20;       // LDS row stride of 16-wide transposition tiles
   __shared__ __attribute__((aligned(16))) float sWt[RP][MPAD + 4];   // W^T, zero padded
-  __shared__ __attribute__((aligned(16))) float sW[RESID ? MPAD : 1][RP + 4];  // W rows (residual A operand)
+  __shared__ __attribute__((aligned(16))) float sW[RESID ? MPAD : 1][RP + 4];  // W rows
   __shared__ __attribute__((aligned(16))) float sX[4][16 * SX];      // per-wave 16x16 X block
   __shared__ __attribute__((aligned(16))) float sHn[4][RP * SX];     // per-wave H_new block
   __shared__ double sRes[4];
@@ -179,12 +190,26 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   const int m = p.m, r = p.r;
   const int64_t k = p.k;
 
-  // stage W and W^T in LDS
-  for (int e = tid; e < RP * MPAD; e += 256) {
-    const int i = e / RP, c = e % RP;
-    const float v = (i < m && c < r) ? p.W[(int64_t)i * r + c] : 0.f;
-    sWt[c][i] = v;
-    if (RESID) sW[i][c] = v;
+  // stage W and W^T in LDS (all loads first, then the stores)
+  {
+    constexpr int NWL = (RP * MPAD + 255) / 256;
+    float wtmp[NWL];
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      const int i = e / RP, c = e % RP;
+      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
+      wtmp[t] = (e < RP * MPAD && i < m && c < r) ? v : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      if (e < RP * MPAD) {
+        const int i = e / RP, c = e % RP;
+        sWt[c][i] = wtmp[t];
+        if (RESID) sW[i][c] = wtmp[t];
+      }
+    }
   }
   // G_W as the A operand of (W^T W) H: lane (a,b), half h, K step (q,kk) -> G[16h+a][16q+4b+kk]
   float gw[NH][NH][4];
@@ -216,55 +241,48 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   float* sHw = sHn[w];
 
   // Loads of a 16-column group: X rows 16*blk + a, columns j0+4b .. j0+4b+3 (the A
-  // operand of X H^T) and H[16h+4b+kk][j0+a].
+  // operand of X H^T) and H[16h+4b+kk][j0+a].  Addresses are clamped into the arrays
+  // and out-of-range values replaced by zero, so interior groups need no branches.
   auto load_group = [&](int64_t g, float (&xr)[MB][4], float (&hv)[NH][4]) {
     const int64_t j0 = g << 4;
-    const bool full = vec_ok && (j0 + 16 <= k);
+    if (vec_ok && (j0 + 16 <= k)) {
 #pragma unroll
-    for (int blk = 0; blk < MB; ++blk) {
-      const int row = 16 * blk + a;
-      if (full) {
-        if (row < m) {
-          const float4 v = *reinterpret_cast<const float4*>(p.X + (int64_t)row * k + j0 + 4 * b);
-          xr[blk][0] = v.x; xr[blk][1] = v.y; xr[blk][2] = v.z; xr[blk][3] = v.w;
-        } else {
-          xr[blk][0] = xr[blk][1] = xr[blk][2] = xr[blk][3] = 0.f;
-        }
-      } else {
+      for (int blk = 0; blk < MB; ++blk) {
+        const int row = 16 * blk + a;
+        const float4 v = *reinterpret_cast<const float4*>(p.X + (int64_t)min(row, m - 1) * k + j0 + 4 * b);
+        const bool ok = row < m;
+        xr[blk][0] = ok ? v.x : 0.f;
+        xr[blk][1] = ok ? v.y : 0.f;
+        xr[blk][2] = ok ? v.z : 0.f;
+        xr[blk][3] = ok ? v.w : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int blk = 0; blk < MB; ++blk) {
+        const int row = 16 * blk + a;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
-          xr[blk][q] = (row < m && col < k) ? p.X[(int64_t)row * k + col] : 0.f;
+          const float v = p.X[(int64_t)min(row, m - 1) * k + min(col, k - 1)];
+          xr[blk][q] = (row < m && col < k) ? v : 0.f;
         }
       }
     }
+    const int64_t col = j0 + a;
+    const int64_t colc = min(col, k - 1);
 #pragma unroll
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int c = 16 * h + 4 * b + kk;
-        const int64_t col = j0 + a;
-        hv[h][kk] = (c < r && col < k) ? p.H[(int64_t)c * k + col] : 0.f;
+        const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
+        hv[h][kk] = (c < r && col < k) ? v : 0.f;
       }
   };
 
-  float xn[MB][4], hn_[NH][4];
-  int64_t g = (int64_t)blockIdx.x * 4 + w;
-  if (g < ngroups) load_group(g, xn, hn_);
-  for (; g < ngroups; g += wstride) {
+  auto process_group = [&](int64_t g, const float (&xr)[MB][4], const float (&hv)[NH][4]) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
-    float xr[MB][4], hv[NH][4];
-#pragma unroll
-    for (int blk = 0; blk < MB; ++blk)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xr[blk][q] = xn[blk][q];
-#pragma unroll
-    for (int h = 0; h < NH; ++h)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) hv[h][q] = hn_[h][q];
-    if (g + wstride < ngroups) load_group(g + wstride, xn, hn_);  // prefetch the next group
-
     // N_H = W^T X (M = rank, N = column, K = row) and the residual X - W H
     v4f nh[NH];
 #pragma unroll
@@ -306,83 +324,93 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
         }
       }
     }
-
-    if (UPDATE) {
-      // D_H = G_W H (M = rank, N = column, K = rank)
-      v4f dh[NH];
+    if (!UPDATE) return;
+    // D_H = G_W H (M = rank, N = column, K = rank)
+    v4f dh[NH];
 #pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        dh[h] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int h = 0; h < NH; ++h) {
+      dh[h] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < NH; ++q)
+      for (int q = 0; q < NH; ++q)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) dh[h] = mfma16(gw[h][q][kk], hv[q][kk], dh[h]);
-      }
-      // epilogue: lane (a,b) reg i -> H_new[16h + 4b + i][j0 + a]
-      wave_sync();
-#pragma unroll
-      for (int h = 0; h < NH; ++h)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int c = 16 * h + 4 * b + i;
-          const float hn = (c < r) ? fmaxf(0.f, hv[h][i] * nh[h][i] / (dh[h][i] + p.eps)) : 0.f;
-          sHw[c * SX + a] = hn;
-        }
-      wave_sync();
-      // transposed read: lane (a,b) -> H_new[16h + a][j0 + 4b .. 4b+3]
-      float4 hn4[NH];
-#pragma unroll
-      for (int h = 0; h < NH; ++h) hn4[h] = *reinterpret_cast<const float4*>(&sHw[(16 * h + a) * SX + 4 * b]);
-      // store H_new (in place)
-#pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        const int c = 16 * h + a;
-        if (c < r) {
-          float* dst = p.H + (int64_t)c * k + j0 + 4 * b;
-          if (full) {
-            *reinterpret_cast<float4*>(dst) = hn4[h];
-          } else {
-            const float vv[4] = {hn4[h].x, hn4[h].y, hn4[h].z, hn4[h].w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (j0 + 4 * b + q < k) dst[q] = vv[q];
-          }
-        }
-      }
-      // X H_new^T (M = row, N = rank, K = column) and H_new H_new^T
-#pragma unroll
-      for (int blk = 0; blk < MB; ++blk)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          accW[blk][h] = mfma16(xr[blk][0], hn4[h].x, accW[blk][h]);
-          accW[blk][h] = mfma16(xr[blk][1], hn4[h].y, accW[blk][h]);
-          accW[blk][h] = mfma16(xr[blk][2], hn4[h].z, accW[blk][h]);
-          accW[blk][h] = mfma16(xr[blk][3], hn4[h].w, accW[blk][h]);
-        }
-#pragma unroll
-      for (int h = 0; h < NH; ++h)
-#pragma unroll
-        for (int q = 0; q < NH; ++q) {
-          accG[h][q] = mfma16(hn4[h].x, hn4[q].x, accG[h][q]);
-          accG[h][q] = mfma16(hn4[h].y, hn4[q].y, accG[h][q]);
-          accG[h][q] = mfma16(hn4[h].z, hn4[q].z, accG[h][q]);
-          accG[h][q] = mfma16(hn4[h].w, hn4[q].w, accG[h][q]);
-        }
+        for (int kk = 0; kk < 4; ++kk) dh[h] = mfma16(gw[h][q][kk], hv[q][kk], dh[h]);
     }
+    // epilogue: lane (a,b) reg i -> H_new[16h + 4b + i][j0 + a]
+    wave_sync();
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * h + 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(hv[h][i] * nh[h][i], dh[h][i] + p.eps));
+        sHw[c * SX + a] = (c < r) ? q : 0.f;
+      }
+    wave_sync();
+    // transposed read: lane (a,b) -> H_new[16h + a][j0 + 4b .. 4b+3]
+    float4 hn4[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) hn4[h] = *reinterpret_cast<const float4*>(&sHw[(16 * h + a) * SX + 4 * b]);
+    // store H_new (in place)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int c = 16 * h + a;
+      if (c < r) {
+        float* dst = p.H + (int64_t)c * k + j0 + 4 * b;
+        if (full) {
+          *reinterpret_cast<float4*>(dst) = hn4[h];
+        } else {
+          const float vv[4] = {hn4[h].x, hn4[h].y, hn4[h].z, hn4[h].w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (j0 + 4 * b + q < k) dst[q] = vv[q];
+        }
+      }
+    }
+    // X H_new^T (M = row, N = rank, K = column) and H_new H_new^T
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        accW[blk][h] = mfma16(xr[blk][0], hn4[h].x, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][1], hn4[h].y, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][2], hn4[h].z, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][3], hn4[h].w, accW[blk][h]);
+      }
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < NH; ++q) {
+        accG[h][q] = mfma16(hn4[h].x, hn4[q].x, accG[h][q]);
+        accG[h][q] = mfma16(hn4[h].y, hn4[q].y, accG[h][q]);
+        accG[h][q] = mfma16(hn4[h].z, hn4[q].z, accG[h][q]);
+        accG[h][q] = mfma16(hn4[h].w, hn4[q].w, accG[h][q]);
+      }
+  };
+
+  // two register sets: the next group's loads are in flight while one is processed
+  float xa[MB][4], ha[NH][4], xb[MB][4], hb[NH][4];
+  int64_t g = (int64_t)blockIdx.x * 4 + w;
+  if (g < ngroups) load_group(g, xa, ha);
+  while (g < ngroups) {
+    const int64_t g2 = g + wstride;
+    if (g2 < ngroups) load_group(g2, xb, hb);
+    process_group(g, xa, ha);
+    if (g2 >= ngroups) break;
+    const int64_t g3 = g2 + wstride;
+    if (g3 < ngroups) load_group(g3, xa, ha);
+    process_group(g2, xb, hb);
+    g = g3;
   }
 
-  // ---- per-workgroup partials, waves combined in the fixed order 0+1+2+3
+  // ---- per-workgroup partials, waves combined in the fixed order 3, 2, 1, 0
   if (RESID) {
     res = wave_sum(res);
     if (lane == 0) sRes[w] = res;
   }
   if (UPDATE) {
-    constexpr int E = MPAD * RP + RP * RP;
     float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
-    // reuse sWt as the reduction buffer when it is large enough, else write per wave in turn
     float* buf = &sWt[0][0];
-    constexpr int BUFN = RP * (MPAD + 4);
-    static_assert(BUFN >= MPAD * RP, "reduction buffer");
+    static_assert(RP * (MPAD + 4) >= MPAD * RP, "reduction buffer");
     __syncthreads();
     for (int turn = 3; turn >= 0; --turn) {
       if (w == turn) {
@@ -398,7 +426,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
       }
       __syncthreads();
     }
-    for (int e = tid; e < MPAD * RP; e += 256) dst[e] = buf[e];
+    for (int e = tid; e < m * r; e += 256) dst[e] = buf[(e / r) * RP + (e % r)];
     float* gbuf = &sHn[0][0];
     static_assert(4 * RP * SX >= RP * RP, "gram reduction buffer");
     __syncthreads();
@@ -416,8 +444,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
       }
       __syncthreads();
     }
-    for (int e = tid; e < RP * RP; e += 256) dst[MPAD * RP + e] = gbuf[e];
-    (void)E;
+    for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * RP + (e % r)];
   } else {
     __syncthreads();
   }
@@ -485,7 +512,7 @@ __global__ __launch_bounds__(256) void k_gen_hupdate(PassArgs p) {
 }
 
 // X H^T and H H^T partials: block (g, rb) covers column chunk g and rows 64rb..64rb+63.
-// Partial layout per chunk g: [mpad][RP] then [RP][RP] (written by rb == 0).
+// Partial layout per chunk g: [m][r] then [r][r], compact (H H^T written by rb == 0).
 template <int RP>
 __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
   __shared__ float sX[64][65];
@@ -548,66 +575,79 @@ __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
     if (qd == 0) {
       const int gi = 64 * rb + row;
       const float s = ((red[tid] + red[tid + 1]) + red[tid + 2]) + red[tid + 3];
-      if (gi < p.mpad) dst[(int64_t)gi * RP + c] = s;
+      if (gi < m && c < r) dst[(int64_t)gi * r + c] = s;
     }
   }
   if (rb == 0) {
 #pragma unroll
     for (int t = 0; t < NG; ++t) {
       const int pidx = tid + 256 * t;
-      if (pidx < RP * RP) dst[(int64_t)p.mpad * RP + pidx] = accg[t];
+      if (pidx < RP * RP && pidx / RP < r && pidx % RP < r)
+        dst[(int64_t)m * r + (pidx / RP) * r + (pidx % RP)] = accg[t];
     }
   }
 }
 
-// ------------------------------------------------------------------ finalize (W-update)
-// Blocks 0..nb-1 reduce the partials entry-wise in FP64 (fixed order: 16 interleaved
-// chunks, then chunks 0..15 in order).  The last block to finish (ticket counter)
-// applies W <- max(0, W .* N_W ./ (W G_H + eps)), writes G_W' = W'^T W' (FP32, zero
-// padded) and the Gram-identity monitor; it records the residual objective, if one was
-// accumulated this iteration, into the trace; then it resets the ticket.
-template <int RP>
-__global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
+// ------------------------------------------------------------------ W-update
+// (1) k_reduce_partials: red[e] = sum over g of part[g][e] in FP64, for the E = m r + r r
+//     entries of the partials (X H^T then H H^T); 16 entries per block, 16 chunk
+//     threads per entry, four interleaved accumulators per thread, then chunks 0..15
+//     in order: a fixed summation order, so results do not depend on scheduling.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ part,
+                                                         int64_t stride, int G, int64_t E,
+                                                         double* __restrict__ red) {
   __shared__ double sPart[16][17];
-  __shared__ double sGH[RP][RP + 1];
-  __shared__ double sGW[RP][RP + 1];
-  __shared__ int sLast;
-  __shared__ double sRed[4];
-  __shared__ float sWc[256][RP + 1];
   const int tid = threadIdx.x;
   const int e_loc = tid & 15, ch = tid >> 4;
-  const int64_t E = (int64_t)f.mpad * RP + RP * RP;
   const int64_t e = (int64_t)blockIdx.x * 16 + e_loc;
-  double acc = 0.0;
-  if (e < E)
-    for (int g = ch; g < f.G; g += 16) acc += (double)f.part[(int64_t)g * f.part_stride + e];
-  sPart[ch][e_loc] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (e < E) {
+    int g = ch;
+    for (; g + 48 < G; g += 64) {
+      a0 += (double)part[(int64_t)g * stride + e];
+      a1 += (double)part[(int64_t)(g + 16) * stride + e];
+      a2 += (double)part[(int64_t)(g + 32) * stride + e];
+      a3 += (double)part[(int64_t)(g + 48) * stride + e];
+    }
+    for (; g < G; g += 16) a0 += (double)part[(int64_t)g * stride + e];
+  }
+  sPart[ch][e_loc] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (tid < 16 && (int64_t)blockIdx.x * 16 + tid < E) {
     double s = 0.0;
     for (int c = 0; c < 16; ++c) s += sPart[c][tid];
-    f.red[(int64_t)blockIdx.x * 16 + tid] = s;
+    red[(int64_t)blockIdx.x * 16 + tid] = s;
   }
-  // ticket
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const int t = atomicAdd(f.counter, 1);
-    sLast = (t == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!sLast) return;
-  __threadfence();
+}
 
+// (2) k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
+//     and G_H = H H^T from `red`, 256 rows at a time, one thread per row (rows are
+//     independent, so the update is in place; each thread reads its whole row before
+//     writing it).  FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also
+//     go to LDS, where the block accumulates G_W' = W'^T W' (FP64) for the next
+//     H-update.  It also writes the Gram-identity monitor
+//       f = 1/2 (||X||^2 - 2 <W', X H^T> + <W'^T W', H H^T>)
+//     and, when this iteration accumulated one, the explicit residual objective.
+template <int RP>
+__global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
+  __shared__ double sGH[RP][RP + 1];
+  __shared__ double sGW[RP][RP + 1];
+  __shared__ float sWc[256][RP + 1];
+  __shared__ double sRed[4];
+  const int tid = threadIdx.x;
   const int m = f.m, r = f.r;
   const double* NW = f.red;
-  const double* GH = f.red + (int64_t)f.mpad * RP;
-  for (int pidx = tid; pidx < RP * RP; pidx += 256) sGH[pidx / RP][pidx % RP] = GH[pidx];
+  const double* GH = f.red + (int64_t)m * r;
+  for (int pidx = tid; pidx < RP * RP; pidx += 256) {
+    const int c = pidx / RP, q = pidx % RP;
+    sGH[c][q] = (c < r && q < r) ? GH[c * r + q] : 0.0;
+  }
+  double rsum = 0.0;
+  if (f.rpart && tid < 64) {
+    for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
+    rsum = wave_sum(rsum);
+  }
   __syncthreads();
-  // W update, 256 rows at a time, one thread per row (rows are independent, so the
-  // update is in place: the old row is read into registers before it is overwritten);
-  // FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also go to LDS, where
-  // the block accumulates G_W' = W'^T W' in FP64.
   constexpr int NP = (RP * RP + 255) / 256;
   double gacc[NP];
 #pragma unroll
@@ -615,29 +655,38 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
   double dot_wn = 0.0;
   for (int i0 = 0; i0 < m; i0 += 256) {
     const int i = i0 + tid;
-    __syncthreads();
     if (i < m) {
       float wrow[RP];
+      double nrow[RP];
+      const int64_t base = (int64_t)i * r;
 #pragma unroll
-      for (int q = 0; q < RP; ++q) wrow[q] = (q < r) ? f.W[(int64_t)i * r + q] : 0.f;
-#pragma unroll 1
-      for (int c = 0; c < r; ++c) {
+      for (int q = 0; q < RP; ++q) {
+        const int qc = min(q, r - 1);
+        const float wv = f.W[base + qc];
+        const double nv = NW[base + qc];
+        wrow[q] = (q < r) ? wv : 0.f;
+        nrow[q] = (q < r) ? nv : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < RP; ++c) {
         double dw = 0.0;
 #pragma unroll
         for (int q = 0; q < RP; ++q) dw += (double)wrow[q] * sGH[q][c];
-        const double nwv = NW[(int64_t)i * RP + c];
-        const double wold = (double)f.Wsrc[(int64_t)i * r + c];
-        const float wf = (float)fmax(0.0, wold * nwv / (dw + (double)f.eps));
-        f.W[(int64_t)i * r + c] = wf;
+        const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)f.eps));
+        const float wf = (c < r) ? (float)wn : 0.f;
         sWc[tid][c] = wf;
-        dot_wn += (double)wf * nwv;
+        dot_wn += (double)wf * nrow[c];
       }
-      for (int c = r; c < RP; ++c) sWc[tid][c] = 0.f;
+#pragma unroll
+      for (int c = 0; c < RP; ++c)
+        if (c < r) f.W[base + c] = sWc[tid][c];
     } else {
+#pragma unroll
       for (int c = 0; c < RP; ++c) sWc[tid][c] = 0.f;
     }
     __syncthreads();
     gram_chunk<RP>(sWc, min(256, m - i0), gacc);
+    __syncthreads();
   }
 #pragma unroll
   for (int t = 0; t < NP; ++t) {
@@ -649,11 +698,6 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
   }
   dot_wn = wave_sum(dot_wn);
   if ((tid & 63) == 0) sRed[tid >> 6] = dot_wn;
-  double rsum = 0.0;
-  if (f.rpart && tid < 64) {
-    for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
-    rsum = wave_sum(rsum);
-  }
   __syncthreads();
   if (tid == 0) {
     const double wn = ((sRed[0] + sRed[1]) + sRed[2]) + sRed[3];
@@ -666,7 +710,6 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
       f.scal[SCAL_OBJ] = obj;
       if (f.trace) f.trace[0] = obj;
     }
-    *f.counter = 0;
   }
 }
 
@@ -867,10 +910,12 @@ hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chun
 }
 
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
-  const int64_t E = (int64_t)f.mpad * rp + (int64_t)rp * rp;
+  const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
   const int nb = (int)((E + 15) / 16);
-  if (rp == 16) k_finalize<16><<<nb, 256, 0, s>>>(f);
-  else k_finalize<32><<<nb, 256, 0, s>>>(f);
+  k_reduce_partials<<<nb, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  NTT_CHECK_LAUNCH();
+  if (rp == 16) k_wupdate<16><<<1, 256, 0, s>>>(f);
+  else k_wupdate<32><<<1, 256, 0, s>>>(f);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
