@@ -36,19 +36,25 @@ ntt_status fail(ntt_status s, const std::string& msg) {
       return fail(NTT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-constexpr int kFusedMaxRows = 256;   // fused one-pass kernel keeps m <= 16*16 rows in registers
-constexpr int kMaxPassBlocks = 1024; // persistent grid of the fused pass
+#ifndef NTT_MAX_PASS_BLOCKS
+#define NTT_MAX_PASS_BLOCKS 1024
+#endif
+constexpr int kMaxPassBlocks = NTT_MAX_PASS_BLOCKS;  // persistent grid of the fused pass
 constexpr int kSumsqBlocks = 1024;
 constexpr int kGraphIters = 25;     // MU iterations per replayed graph
 constexpr size_t kMaxGraphs = 64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+enum PassKind { PASS_S = 0, PASS_L = 1, PASS_GENERIC = 2 };
+
 struct Stage {
   int64_t m = 0, k = 0;
   int r = 0, rp = 16;
-  bool fused = true;
-  int mb = 1;       // fused: 16-row blocks
+  bool fused = true;  // one X pass per iteration (PASS_S or PASS_L)
+  int kind = PASS_S;
+  int cls = 0;      // PASS_L: row class
+  int mb = 1;       // PASS_S: 16-row blocks
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
 };
@@ -183,14 +189,25 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     for (int j = l; j < d; ++j) s.k *= p->dims[j];
     s.r = (int)p->eff[l];
     s.rp = s.r <= 16 ? 16 : 32;
-    s.fused = s.m <= kFusedMaxRows;
     const int64_t ngroups = (s.k + 15) / 16;
-    if (s.fused) {
-      const int64_t blocks16 = (s.m + 15) / 16;
-      s.mb = 1;
-      while (s.mb < blocks16) s.mb *= 2;
-      s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, kMaxPassBlocks));
+    const double Ed = (double)s.m * s.r + (double)s.r * s.r;
+    // partials cost G E floats per iteration: keep them within ~10% of the X bytes,
+    // but use at least 256 workgroups when there are that many groups
+    const int64_t gcap = std::max<int64_t>(
+        256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
+    s.cls = pass_L_class(s.m, s.rp);
+    if (s.m <= 32) {
+      s.kind = PASS_S;
+      s.mb = s.m <= 16 ? 1 : 2;
+      s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, gcap));
+    } else if (s.cls >= 0) {
+      s.kind = PASS_L;
+      s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
     } else {
+      s.kind = PASS_GENERIC;
+    }
+    s.fused = s.kind != PASS_GENERIC;
+    if (!s.fused) {
       const int64_t want = std::max<int64_t>(1, std::min<int64_t>((s.k + 255) / 256, 256));
       s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
       s.G = (int)((s.k + s.chunk - 1) / s.chunk);
@@ -270,7 +287,8 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
 }
 
 hipError_t run_pass(const Ctx& c, const Stage& s, const PassArgs& a, bool update, bool resid) {
-  if (s.fused) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, c.s);
+  if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, c.s);
+  if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, c.s);
   return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, c.s);
 }
 
@@ -423,11 +441,27 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
       *out = exec;
       return hipSuccess;
     };
+    // small unfoldings: whole blocks of iterations in one single-workgroup launch
+    const bool one_wg = !record && !profile && stage_1wg_ok(st.m, st.k, st.r);
     int t = 0;
     while (t < cfg.max_iters) {
       // iterations up to the next stopping check (or the end)
       int block = cfg.max_iters - t;
       if (cfg.tol > 0.0) block = std::min(block, cfg.check_every - (t % cfg.check_every));
+      if (one_wg) {
+        StageArgs sa;
+        sa.X = X;
+        sa.W = W;
+        sa.H = H;
+        sa.m = (int)st.m;
+        sa.r = st.r;
+        sa.k = (int)st.k;
+        sa.iters = block;
+        sa.eps = eps;
+        HIP_TRY(launch_stage_1wg(sa, s));
+        t += block;
+        block = 0;
+      }
       if (use_graph) {
         while (block >= kGraphIters || (block > 1 && cfg.tol > 0.0)) {
           const int n = std::min(block, kGraphIters);

@@ -42,6 +42,15 @@ struct FinArgs {
   float eps;
 };
 
+// A whole stage of MU iterations in one workgroup (small unfoldings).
+struct StageArgs {
+  const float* X;  // m x k
+  float* W;        // m x r, read at entry, written at exit
+  float* H;        // r x k, read at entry, written at exit
+  int m, r, k, iters;
+  float eps;
+};
+
 // TT expansion (Eq.(2)) over the rows of the (n_1...n_{d-1}) x n_d matrix.
 struct TTArgs {
   int d;
@@ -61,6 +70,12 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, in
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              hipStream_t s);
+int pass_L_class(int64_t m, int rp);  // -1 when m is beyond the row-split variant
+int pass_L_waves(int cls);
+hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
+                         hipStream_t s);
+bool stage_1wg_ok(int64_t m, int64_t k, int r);
+hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);

@@ -21,6 +21,15 @@
 
 #include "ntt_internal.h"
 
+// Tuning knobs (compile-time): minimum waves per SIMD requested from the
+// register allocator for the r <= 8 pass, and whether it prefetches the next group.
+#ifndef NTT_R8_MIN_WG
+#define NTT_R8_MIN_WG 1
+#endif
+#ifndef NTT_R8_PREFETCH
+#define NTT_R8_PREFETCH 1
+#endif
+
 namespace ntt {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -451,6 +460,694 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   if (RESID && tid == 0) p.rpart[blockIdx.x] = ((sRes[0] + sRes[1]) + sRes[2]) + sRes[3];
 }
 
+// ------------------------------------------------------------------ fused MU pass, r <= 8
+// Specialisation of k_mu_pass (UPDATE only) for r <= 8.  The two 16-wide MFMA products
+// (W^T X and X H_new^T) keep the MFMA path; the r x r products (W^T W) H and
+// H_new H_new^T, which would fill only a quarter of a 16x16 MFMA tile at r = 8, run on
+// the VALU from LDS copies of the H tiles:
+//   D_H[c][j] = sum_{q<8} G[c][q] H[q][j]   : lane (a, b<2) forms rows 4b..4b+3 of column a
+//   G_H[c][q] += H_new[c][j] H_new[q][j]     : lane (a, b) accumulates the 4x4 block
+//                                              (rows 4(b&1).., cols 4(b>>1)..) of column a
+// Rows and columns beyond r are zero in G and H_new, so the 8-wide sums are exact for any
+// r <= 8.
+template <int MB>
+__global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
+  constexpr int MPAD = 16 * MB;
+  constexpr int SX = 20;
+  __shared__ __attribute__((aligned(16))) float sWt[16][MPAD + 4];  // W^T, zero padded
+  __shared__ __attribute__((aligned(16))) float sG[8][8];           // W^T W (8 x 8)
+  __shared__ __attribute__((aligned(16))) float sX[4][16 * SX];     // per-wave X block
+  __shared__ __attribute__((aligned(16))) float sHn[4][16 * SX];    // per-wave H_new [rank][col]
+  __shared__ __attribute__((aligned(16))) float sHc[4][16 * SX];    // per-wave H columns [col][rank]
+  __shared__ __attribute__((aligned(16))) float sHnc[4][16 * SX];   // per-wave H_new [col][rank]
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+
+  {
+    constexpr int NWL = (16 * MPAD + 255) / 256;
+    float wtmp[NWL];
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      const int i = e / 16, c = e % 16;
+      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
+      wtmp[t] = (e < 16 * MPAD && i < m && c < r) ? v : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      if (e < 16 * MPAD) sWt[e % 16][e / 16] = wtmp[t];
+    }
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sG[c][q] = p.GW[c * 16 + q];  // zero beyond r
+    }
+  }
+  __syncthreads();
+
+  v4f accW[MB];     // X H_new^T: lane (a,b) reg i -> row 16*blk+4b+i, rank a
+  float pg[4][4];   // G_H block of this lane
+#pragma unroll
+  for (int i = 0; i < MB; ++i) accW[i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pg[i][q] = 0.f;
+
+  const int64_t ngroups = (k + 15) >> 4;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  const bool vec_ok = ((k & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+  float* sXw = sX[w];
+  float* sHw = sHn[w];
+  float* sHcw = sHc[w];
+  float* sHncw = sHnc[w];
+  const int rq = 4 * (b & 1), cq = 4 * (b >> 1);  // G_H block of this lane
+  // row pointers of this lane (clamped into the matrix)
+  const float* xrow[MB];
+#pragma unroll
+  for (int blk = 0; blk < MB; ++blk) xrow[blk] = p.X + (int64_t)min(16 * blk + a, m - 1) * k;
+  const float* hrow[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) hrow[kk] = p.H + (int64_t)min(4 * b + kk, r - 1) * k;
+
+  auto load_group = [&](int64_t g, float (&xr)[MB][4], float (&hv)[4]) {
+    const int64_t j0 = g << 4;
+    if (vec_ok && (j0 + 16 <= k)) {
+#pragma unroll
+      for (int blk = 0; blk < MB; ++blk) {
+        const float4 v = *reinterpret_cast<const float4*>(xrow[blk] + j0 + 4 * b);
+        xr[blk][0] = v.x; xr[blk][1] = v.y; xr[blk][2] = v.z; xr[blk][3] = v.w;
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[kk] = hrow[kk][j0 + a];
+    } else {
+#pragma unroll
+      for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t col = j0 + 4 * b + q;
+          const float v = xrow[blk][min(col, k - 1)];
+          xr[blk][q] = col < k ? v : 0.f;
+        }
+      const int64_t col = j0 + a;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const float v = hrow[kk][min(col, k - 1)];
+        hv[kk] = col < k ? v : 0.f;
+      }
+    }
+  };
+
+  int64_t g = (int64_t)blockIdx.x * 4 + w;
+#if NTT_R8_PREFETCH
+  float xn[MB][4], hn_[4];
+  if (g < ngroups) load_group(g, xn, hn_);
+#endif
+  for (; g < ngroups; g += wstride) {
+    const int64_t j0 = g << 4;
+    const bool full = vec_ok && (j0 + 16 <= k);
+    float xr[MB][4], hv[4];
+#if NTT_R8_PREFETCH
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xr[blk][q] = xn[blk][q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hv[q] = hn_[q];
+    if (g + wstride < ngroups) load_group(g + wstride, xn, hn_);
+#else
+    load_group(g, xr, hv);
+#endif
+
+    // H tile to LDS as [column][rank]; rows >= r of the loads hold copies of row r-1,
+    // so they are zeroed here
+    wave_sync();
+    {
+      float4 hz;
+      hz.x = (4 * b + 0 < r) ? hv[0] : 0.f;
+      hz.y = (4 * b + 1 < r) ? hv[1] : 0.f;
+      hz.z = (4 * b + 2 < r) ? hv[2] : 0.f;
+      hz.w = (4 * b + 3 < r) ? hv[3] : 0.f;
+      *reinterpret_cast<float4*>(&sHcw[a * SX + 4 * b]) = hz;
+    }
+    // N_H = W^T X (M = rank, N = column, K = row)
+    v4f nh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+      if (blk > 0) wave_sync();
+      *reinterpret_cast<float4*>(&sXw[a * SX + 4 * b]) =
+          make_float4(xr[blk][0], xr[blk][1], xr[blk][2], xr[blk][3]);
+      wave_sync();
+      float xt[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) xt[kk] = sXw[(4 * b + kk) * SX + a];
+      const float4 wt = *reinterpret_cast<const float4*>(&sWt[a][16 * blk + 4 * b]);
+      nh = mfma16(wt.x, xt[0], nh);
+      nh = mfma16(wt.y, xt[1], nh);
+      nh = mfma16(wt.z, xt[2], nh);
+      nh = mfma16(wt.w, xt[3], nh);
+    }
+    // D_H on the VALU: lane (a, b < 2) -> rows 4b..4b+3 of column a
+    const float4 hc0 = *reinterpret_cast<const float4*>(&sHcw[a * SX]);
+    const float4 hc1 = *reinterpret_cast<const float4*>(&sHcw[a * SX + 4]);
+    const float hc[8] = {hc0.x, hc0.y, hc0.z, hc0.w, hc1.x, hc1.y, hc1.z, hc1.w};
+    float hnew[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int c = rq + kk;  // = 4b + kk for b < 2
+      const float4 g0 = *reinterpret_cast<const float4*>(&sG[c][0]);
+      const float4 g1 = *reinterpret_cast<const float4*>(&sG[c][4]);
+      float dh = g0.x * hc[0];
+      dh = fmaf(g0.y, hc[1], dh);
+      dh = fmaf(g0.z, hc[2], dh);
+      dh = fmaf(g0.w, hc[3], dh);
+      dh = fmaf(g1.x, hc[4], dh);
+      dh = fmaf(g1.y, hc[5], dh);
+      dh = fmaf(g1.z, hc[6], dh);
+      dh = fmaf(g1.w, hc[7], dh);
+      const float q = fmaxf(0.f, fast_div(hv[kk] * nh[kk], dh + p.eps));
+      hnew[kk] = (b < 2 && 4 * b + kk < r) ? q : 0.f;
+    }
+    // H_new to LDS in both layouts: [rank][col] (X H^T operand) and [col][rank] (G_H)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) sHw[(4 * b + kk) * SX + a] = hnew[kk];
+    *reinterpret_cast<float4*>(&sHncw[a * SX + 4 * b]) = make_float4(hnew[0], hnew[1], hnew[2], hnew[3]);
+    wave_sync();
+    const float4 hn4 = *reinterpret_cast<const float4*>(&sHw[a * SX + 4 * b]);  // H_new[a][j0+4b..]
+    if (a < r) {
+      float* dst = p.H + (int64_t)a * k + j0 + 4 * b;
+      if (full) {
+        *reinterpret_cast<float4*>(dst) = hn4;
+      } else {
+        const float vv[4] = {hn4.x, hn4.y, hn4.z, hn4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (j0 + 4 * b + q < k) dst[q] = vv[q];
+      }
+    }
+    // X H_new^T (M = row, N = rank, K = column)
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+      accW[blk] = mfma16(xr[blk][0], hn4.x, accW[blk]);
+      accW[blk] = mfma16(xr[blk][1], hn4.y, accW[blk]);
+      accW[blk] = mfma16(xr[blk][2], hn4.z, accW[blk]);
+      accW[blk] = mfma16(xr[blk][3], hn4.w, accW[blk]);
+    }
+    // G_H block on the VALU
+    const float4 hr = *reinterpret_cast<const float4*>(&sHncw[a * SX + rq]);
+    const float4 hq = *reinterpret_cast<const float4*>(&sHncw[a * SX + cq]);
+    const float hrv[4] = {hr.x, hr.y, hr.z, hr.w}, hqv[4] = {hq.x, hq.y, hq.z, hq.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pg[i][q] = fmaf(hrv[i], hqv[q], pg[i][q]);
+  }
+
+  // ---- per-workgroup partials
+  // G_H: sum the lane blocks over the 16 columns a (fixed butterfly), then waves in order
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float v = pg[i][q];
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      pg[i][q] = v;
+    }
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+  float* buf = &sWt[0][0];
+  static_assert(16 * (MPAD + 4) >= MPAD * 16, "reduction buffer");
+  float* gbuf = &sHn[0][0];
+  __syncthreads();
+  for (int turn = 3; turn >= 0; --turn) {
+    if (w == turn) {
+#pragma unroll
+      for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int idx = (16 * blk + 4 * b + i) * 16 + a;
+          buf[idx] = (turn == 3) ? accW[blk][i] : buf[idx] + accW[blk][i];
+        }
+      if (a == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int idx = (rq + i) * 8 + cq + q;
+            gbuf[idx] = (turn == 3) ? pg[i][q] : gbuf[idx] + pg[i][q];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * r; e += 256) dst[e] = buf[(e / r) * 16 + (e % r)];
+  for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * 8 + (e % r)];
+}
+
+// ------------------------------------------------------------------ fused MU pass, rows split over waves
+// Variant for larger m: the workgroup's NW wavefronts share each 16-column group, wave w
+// owning rows [16 MBW w, 16 MBW (w+1)).  Per group: every wave forms its rows' part of
+// W^T X (MFMA, K = rows); the parts are summed across waves in the fixed order 0..NW-1
+// through LDS (double-buffered by group parity, one barrier per group); every wave then
+// applies the same epilogue to the full sum (so all hold the same H_new); wave 0 stores
+// H_new and accumulates H_new H_new^T; each wave accumulates X H_new^T for its own rows,
+// so that partial needs no cross-wave reduction.  W stays in registers as MFMA operands.
+template <int RP, int MBW, int NW, bool UPDATE, bool RESID>
+__global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
+  constexpr int NH = RP / 16;
+  constexpr int SX = 20;
+  __shared__ __attribute__((aligned(16))) float sX[NW][16 * SX];
+  __shared__ __attribute__((aligned(16))) float sNH[UPDATE ? 2 : 1][UPDATE ? NW : 1][RP * 16];
+  __shared__ __attribute__((aligned(16))) float sHn[NW][RP * SX];
+  __shared__ double sRes[NW];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int row0 = w * 16 * MBW;
+
+  // W^T as the A operand of W^T X: wa[blk][h][kk] = W[row0 + 16 blk + 4b + kk][16h + a]
+  float wa[MBW][NH][4];
+  // W as the A operand of W H (residual): wr[blk][q][kk] = W[row0 + 16 blk + a][16q + 4b + kk]
+  float wr[RESID ? MBW : 1][NH][4];
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int i = row0 + 16 * blk + 4 * b + kk, c = 16 * h + a;
+        const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
+        wa[blk][h][kk] = (i < m && c < r) ? v : 0.f;
+        if (RESID) {
+          const int i2 = row0 + 16 * blk + a, c2 = 16 * h + 4 * b + kk;
+          const float v2 = p.W[(int64_t)min(i2, m - 1) * r + min(c2, r - 1)];
+          wr[blk][h][kk] = (i2 < m && c2 < r) ? v2 : 0.f;
+        }
+      }
+  float gw[NH][NH][4];
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < NH; ++q)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) gw[h][q][kk] = p.GW[(16 * h + a) * RP + 16 * q + 4 * b + kk];
+
+  v4f accW[MBW][NH];
+  v4f accG[NH][NH];
+  double res = 0.0;
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) accW[i][h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < NH; ++q) accG[h][q] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t ngroups = (k + 15) >> 4;
+  const bool vec_ok = ((k & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+  float* sXw = sX[w];
+  float* sHw = sHn[w];
+  const float* xrow[MBW];
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk) xrow[blk] = p.X + (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
+
+  int par = 0;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+    const int64_t j0 = g << 4;
+    const bool full = vec_ok && (j0 + 16 <= k);
+    float xr[MBW][4];
+    if (full) {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk) {
+        const float4 v = *reinterpret_cast<const float4*>(xrow[blk] + j0 + 4 * b);
+        const bool ok = !RESID || (row0 + 16 * blk + a < m);
+        xr[blk][0] = ok ? v.x : 0.f;
+        xr[blk][1] = ok ? v.y : 0.f;
+        xr[blk][2] = ok ? v.z : 0.f;
+        xr[blk][3] = ok ? v.w : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t col = j0 + 4 * b + q;
+          const float v = xrow[blk][min(col, k - 1)];
+          xr[blk][q] = (col < k && row0 + 16 * blk + a < m) ? v : 0.f;
+        }
+    }
+    float hv[NH][4];
+    {
+      const int64_t col = j0 + a;
+      const int64_t colc = min(col, k - 1);
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int c = 16 * h + 4 * b + kk;
+          const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
+          hv[h][kk] = (c < r && col < k) ? v : 0.f;
+        }
+    }
+    v4f nh[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) nh[h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) {
+      wave_sync();
+      *reinterpret_cast<float4*>(&sXw[a * SX + 4 * b]) =
+          make_float4(xr[blk][0], xr[blk][1], xr[blk][2], xr[blk][3]);
+      wave_sync();
+      float xt[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) xt[kk] = sXw[(4 * b + kk) * SX + a];
+      if (UPDATE) {
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) nh[h] = mfma16(wa[blk][h][kk], xt[kk], nh[h]);
+      }
+      if (RESID) {
+        v4f wh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < NH; ++q)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) wh = mfma16(wr[blk][q][kk], hv[q][kk], wh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double dlt = (double)xt[i] - (double)wh[i];
+          res += dlt * dlt;
+        }
+      }
+    }
+    if (!UPDATE) continue;
+    // sum the waves' parts of W^T X in order
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sNH[par][w][(16 * h + 4 * b + i) * 16 + a] = nh[h][i];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float s = sNH[par][0][(16 * h + 4 * b + i) * 16 + a];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) s += sNH[par][ww][(16 * h + 4 * b + i) * 16 + a];
+        nh[h][i] = s;
+      }
+    // D_H = G_W H and the epilogue (identical in every wave)
+    v4f dh[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      dh[h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < NH; ++q)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dh[h] = mfma16(gw[h][q][kk], hv[q][kk], dh[h]);
+    }
+    wave_sync();
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * h + 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(hv[h][i] * nh[h][i], dh[h][i] + p.eps));
+        sHw[c * SX + a] = (c < r) ? q : 0.f;
+      }
+    wave_sync();
+    float4 hn4[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) hn4[h] = *reinterpret_cast<const float4*>(&sHw[(16 * h + a) * SX + 4 * b]);
+    if (w == 0) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int c = 16 * h + a;
+        if (c < r) {
+          float* dst = p.H + (int64_t)c * k + j0 + 4 * b;
+          if (full) {
+            *reinterpret_cast<float4*>(dst) = hn4[h];
+          } else {
+            const float vv[4] = {hn4[h].x, hn4[h].y, hn4[h].z, hn4[h].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (j0 + 4 * b + q < k) dst[q] = vv[q];
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < NH; ++q) {
+          accG[h][q] = mfma16(hn4[h].x, hn4[q].x, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].y, hn4[q].y, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].z, hn4[q].z, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].w, hn4[q].w, accG[h][q]);
+        }
+    }
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        accW[blk][h] = mfma16(xr[blk][0], hn4[h].x, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][1], hn4[h].y, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][2], hn4[h].z, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][3], hn4[h].w, accW[blk][h]);
+      }
+  }
+
+  if (UPDATE) {
+    // this wave's rows of X H_new^T, and (wave 0) H_new H_new^T: compact m x r, r x r
+    float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = row0 + 16 * blk + 4 * b + i, c = 16 * h + a;
+          if (row < m && c < r) dst[(int64_t)row * r + c] = accW[blk][h][i];
+        }
+    if (w == 0) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < NH; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = 16 * h + 4 * b + i, cc = 16 * q + a;
+            if (c < r && cc < r) dst[(int64_t)m * r + c * r + cc] = accG[h][q][i];
+          }
+    }
+  }
+  if (RESID) {
+    res = wave_sum(res);
+    if (lane == 0) sRes[w] = res;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int ww = 0; ww < NW; ++ww) s += sRes[ww];
+      p.rpart[blockIdx.x] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ whole stage in one workgroup
+// For small unfoldings (m <= 256, k <= 16 NG <= 64, r <= 16) one workgroup of four
+// wavefronts runs `iters` MU iterations without leaving the kernel.  X stays in
+// registers (wave w owns rows 64w..64w+63, in both MFMA operand layouts), H lives in
+// LDS, W in registers.  Per iteration, for each 16-column group: W^T X by MFMA (rows
+// split over waves, parts summed in LDS in wave order), (W^T W) H and the H epilogue,
+// then X H_new^T for the wave's own rows and H_new H_new^T; after the last group the
+// wave's rows of X H^T are complete, so the W-update
+//   W <- max(0, W .* (X H^T) ./ (W (H H^T) + eps))
+// is local to each wave (W (H H^T) by MFMA), followed by W^T W summed over the waves.
+// All arithmetic is FP32 with FP32 accumulation; results are deterministic.
+template <int NG>
+__global__ __launch_bounds__(256) void k_stage_1wg(StageArgs s) {
+  constexpr int MBW = 4, SX = 20, KC = 16 * NG;
+  __shared__ __attribute__((aligned(16))) float sX[4][16 * SX];
+  __shared__ __attribute__((aligned(16))) float sNH[2][4][256];
+  __shared__ __attribute__((aligned(16))) float sH[16][KC + 4];   // H, zero padded
+  __shared__ __attribute__((aligned(16))) float sHn[4][16 * SX];  // per-wave H_new tile
+  __shared__ __attribute__((aligned(16))) float sWr[4][16 * SX];  // per-wave W transpose tile
+  __shared__ __attribute__((aligned(16))) float sG[4][256];       // Gram partials per wave
+  __shared__ __attribute__((aligned(16))) float sGW[16][17];
+  __shared__ __attribute__((aligned(16))) float sGH[16][17];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = s.m, r = s.r, k = s.k;
+  const int row0 = 64 * w;
+
+  // X in both operand layouts: xa[g][blk][q] = X[row0+16blk+a][16g+4b+q] (A of X H^T),
+  // xt[g][blk][kk] = X[row0+16blk+4b+kk][16g+a] (B of W^T X)
+  float xa[NG][MBW][4], xt[NG][MBW][4];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i1 = row0 + 16 * blk + a, c1 = 16 * g + 4 * b + q;
+        const float v1 = s.X[(int64_t)min(i1, m - 1) * k + min(c1, k - 1)];
+        xa[g][blk][q] = (i1 < m && c1 < k) ? v1 : 0.f;
+        const int i2 = row0 + 16 * blk + 4 * b + q, c2 = 16 * g + a;
+        const float v2 = s.X[(int64_t)min(i2, m - 1) * k + min(c2, k - 1)];
+        xt[g][blk][q] = (i2 < m && c2 < k) ? v2 : 0.f;
+      }
+  // W in the C layout of the 16x16 tiles: wc[blk][i] = W[row0+16blk+4b+i][a]
+  float wc[MBW][4];
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + 16 * blk + 4 * b + i;
+      const float v = s.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)];
+      wc[blk][i] = (row < m && a < r) ? v : 0.f;
+    }
+  for (int e = tid; e < 16 * (KC + 4); e += 256) {
+    const int c = e / (KC + 4), j = e % (KC + 4);
+    const float v = s.H[(int64_t)min(c, r - 1) * k + min(j, k - 1)];
+    sH[c][j] = (c < r && j < k) ? v : 0.f;
+  }
+
+  // G_W = sum over waves of sum_rows W^T W (M = N = rank, K = row): both operands are wc
+  auto gram_w = [&]() {
+    v4f gp = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) gp = mfma16(wc[blk][kk], wc[blk][kk], gp);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sG[w][(4 * b + i) * 16 + a] = gp[i];
+    __syncthreads();
+    for (int e = tid; e < 256; e += 256) {
+      sGW[e / 16][e % 16] = ((sG[0][e] + sG[1][e]) + sG[2][e]) + sG[3][e];
+    }
+    __syncthreads();
+  };
+  gram_w();
+
+  for (int it = 0; it < s.iters; ++it) {
+    // G_W as the A operand of (W^T W) H
+    float gw[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) gw[kk] = sGW[a][4 * b + kk];
+    v4f accW[MBW];
+    v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int par = g & 1;
+      float hv[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[kk] = sH[4 * b + kk][16 * g + a];
+      v4f nh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) nh = mfma16(wc[blk][kk], xt[g][blk][kk], nh);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sNH[par][w][(4 * b + i) * 16 + a] = nh[i];
+      __syncthreads();  // every wave has also read its hv for this group
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = (4 * b + i) * 16 + a;
+        nh[i] = ((sNH[par][0][e] + sNH[par][1][e]) + sNH[par][2][e]) + sNH[par][3][e];
+      }
+      v4f dh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) dh = mfma16(gw[kk], hv[kk], dh);
+      float hn[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(hv[i] * nh[i], dh[i] + s.eps));
+        hn[i] = (c < r && 16 * g + a < k) ? q : 0.f;
+      }
+      wave_sync();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sHn[w][(4 * b + i) * SX + a] = hn[i];
+      if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sH[4 * b + i][16 * g + a] = hn[i];
+      }
+      wave_sync();
+      const float4 hn4 = *reinterpret_cast<const float4*>(&sHn[w][a * SX + 4 * b]);
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk) {
+        accW[blk] = mfma16(xa[g][blk][0], hn4.x, accW[blk]);
+        accW[blk] = mfma16(xa[g][blk][1], hn4.y, accW[blk]);
+        accW[blk] = mfma16(xa[g][blk][2], hn4.z, accW[blk]);
+        accW[blk] = mfma16(xa[g][blk][3], hn4.w, accW[blk]);
+      }
+      accG = mfma16(hn4.x, hn4.x, accG);
+      accG = mfma16(hn4.y, hn4.y, accG);
+      accG = mfma16(hn4.z, hn4.z, accG);
+      accG = mfma16(hn4.w, hn4.w, accG);
+    }
+    // G_H (every wave accumulated the same H_new, so any one copy is the full sum)
+    if (w == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sGH[4 * b + i][a] = accG[i];
+    }
+    // W rows of this wave in the A layout of W (H H^T): W[row0+16blk+a][4b+kk]
+    wave_sync();
+    float wr[MBW][4];
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sWr[w][(4 * b + i) * SX + a] = wc[blk][i];
+      wave_sync();
+      const float4 t4 = *reinterpret_cast<const float4*>(&sWr[w][a * SX + 4 * b]);
+      wr[blk][0] = t4.x; wr[blk][1] = t4.y; wr[blk][2] = t4.z; wr[blk][3] = t4.w;
+      wave_sync();
+    }
+    __syncthreads();
+    float gh[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) gh[kk] = sGH[4 * b + kk][a];
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) {
+      v4f dw = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) dw = mfma16(wr[blk][kk], gh[kk], dw);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + 16 * blk + 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(wc[blk][i] * accW[blk][i], dw[i] + s.eps));
+        wc[blk][i] = (row < m && a < r) ? q : 0.f;
+      }
+    }
+    gram_w();
+  }
+
+  // write W and H back
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + 16 * blk + 4 * b + i;
+      if (row < m && a < r) s.W[(int64_t)row * r + a] = wc[blk][i];
+    }
+  for (int e = tid; e < 16 * KC; e += 256) {
+    const int c = e / KC, j = e % KC;
+    if (c < r && j < k) s.H[(int64_t)c * k + j] = sH[c][j];
+  }
+}
+
 // ------------------------------------------------------------------ generic path (any m)
 // H-update with one thread per column; W streamed through LDS in 64-row chunks.
 template <int RP, bool UPDATE, bool RESID>
@@ -621,26 +1318,39 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
 }
 
 // (2) k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
-//     and G_H = H H^T from `red`, 256 rows at a time, one thread per row (rows are
-//     independent, so the update is in place; each thread reads its whole row before
-//     writing it).  FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also
-//     go to LDS, where the block accumulates G_W' = W'^T W' (FP64) for the next
-//     H-update.  It also writes the Gram-identity monitor
+//     and G_H = H H^T, 256 rows at a time, one thread per row (rows are independent,
+//     so the update is in place; each thread reads its whole row before writing it).
+//     FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also go to LDS,
+//     where the block accumulates G_W' = W'^T W' (FP64) for the next H-update.  It also
+//     writes the Gram-identity monitor
 //       f = 1/2 (||X||^2 - 2 <W', X H^T> + <W'^T W', H H^T>)
 //     and, when this iteration accumulated one, the explicit residual objective.
-template <int RP>
+//     RB >= r bounds the loops.  FUSED: N_W and G_H are summed here from the G <= 4
+//     per-workgroup partials (in the order g = 0..G-1) instead of read from `red`.
+template <int RB, bool FUSED>
 __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
-  __shared__ double sGH[RP][RP + 1];
-  __shared__ double sGW[RP][RP + 1];
-  __shared__ float sWc[256][RP + 1];
+  constexpr int NPAIR = RB * RB;
+  constexpr int NSL = NPAIR >= 256 ? 1 : 256 / NPAIR;   // row slices of the Gram
+  constexpr int NPT = NPAIR <= 256 ? 1 : NPAIR / 256;   // Gram pairs per thread
+  __shared__ double sGH[RB][RB + 1];
+  __shared__ double sGW[RB][RB + 1];
+  __shared__ double sGp[NSL][NPAIR];
+  __shared__ float sWc[256][RB + 1];
   __shared__ double sRed[4];
   const int tid = threadIdx.x;
   const int m = f.m, r = f.r;
-  const double* NW = f.red;
-  const double* GH = f.red + (int64_t)m * r;
-  for (int pidx = tid; pidx < RP * RP; pidx += 256) {
-    const int c = pidx / RP, q = pidx % RP;
-    sGH[c][q] = (c < r && q < r) ? GH[c * r + q] : 0.0;
+  const int64_t mr = (int64_t)m * r;
+  auto entry = [&](int64_t e) -> double {
+    if (FUSED) {
+      double v = 0.0;
+      for (int g = 0; g < f.G; ++g) v += (double)f.part[(int64_t)g * f.part_stride + e];
+      return v;
+    }
+    return f.red[e];
+  };
+  for (int pidx = tid; pidx < NPAIR; pidx += 256) {
+    const int c = pidx / RB, q = pidx % RB;
+    sGH[c][q] = (c < r && q < r) ? entry(mr + c * r + q) : 0.0;
   }
   double rsum = 0.0;
   if (f.rpart && tid < 64) {
@@ -648,53 +1358,75 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
     rsum = wave_sum(rsum);
   }
   __syncthreads();
-  constexpr int NP = (RP * RP + 255) / 256;
-  double gacc[NP];
+  // Gram work split: thread -> (slice, pair) for RB <= 16, several pairs for RB = 32
+  const int slice = NSL > 1 ? tid / NPAIR : 0;
+  double gacc[NPT];
 #pragma unroll
-  for (int t = 0; t < NP; ++t) gacc[t] = 0.0;
+  for (int t = 0; t < NPT; ++t) gacc[t] = 0.0;
   double dot_wn = 0.0;
   for (int i0 = 0; i0 < m; i0 += 256) {
     const int i = i0 + tid;
     if (i < m) {
-      float wrow[RP];
-      double nrow[RP];
+      float wrow[RB];
+      double nrow[RB];
       const int64_t base = (int64_t)i * r;
 #pragma unroll
-      for (int q = 0; q < RP; ++q) {
+      for (int q = 0; q < RB; ++q) {
         const int qc = min(q, r - 1);
         const float wv = f.W[base + qc];
-        const double nv = NW[base + qc];
         wrow[q] = (q < r) ? wv : 0.f;
-        nrow[q] = (q < r) ? nv : 0.0;
       }
 #pragma unroll
-      for (int c = 0; c < RP; ++c) {
+      for (int q = 0; q < RB; ++q) nrow[q] = (q < r) ? entry(base + min(q, r - 1)) : 0.0;
+#pragma unroll
+      for (int c = 0; c < RB; ++c) {
         double dw = 0.0;
 #pragma unroll
-        for (int q = 0; q < RP; ++q) dw += (double)wrow[q] * sGH[q][c];
+        for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
         const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)f.eps));
         const float wf = (c < r) ? (float)wn : 0.f;
         sWc[tid][c] = wf;
         dot_wn += (double)wf * nrow[c];
       }
 #pragma unroll
-      for (int c = 0; c < RP; ++c)
+      for (int c = 0; c < RB; ++c)
         if (c < r) f.W[base + c] = sWc[tid][c];
     } else {
 #pragma unroll
-      for (int c = 0; c < RP; ++c) sWc[tid][c] = 0.f;
+      for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
     }
     __syncthreads();
-    gram_chunk<RP>(sWc, min(256, m - i0), gacc);
+    const int nrows = min(256, m - i0);
+    const int per = (nrows + NSL - 1) / NSL;
+    const int lo = slice * per, hi = min(nrows, lo + per);
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const int pidx = (tid % (NSL > 1 ? NPAIR : 256)) + 256 * t;
+      const int c = pidx / RB, q = pidx % RB;
+      double s = 0.0;
+      for (int ii = lo; ii < hi; ++ii) s += (double)sWc[ii][c] * (double)sWc[ii][q];
+      gacc[t] += s;
+    }
     __syncthreads();
   }
+  // combine the row slices in order
 #pragma unroll
-  for (int t = 0; t < NP; ++t) {
-    const int pidx = tid + 256 * t;
-    if (pidx < RP * RP) {
-      sGW[pidx / RP][pidx % RP] = gacc[t];
-      f.GW[pidx] = (float)gacc[t];
-    }
+  for (int t = 0; t < NPT; ++t) {
+    const int pidx = (tid % (NSL > 1 ? NPAIR : 256)) + 256 * t;
+    sGp[slice][pidx] = gacc[t];
+  }
+  __syncthreads();
+  for (int pidx = tid; pidx < NPAIR; pidx += 256) {
+    double s = 0.0;
+    for (int sl = 0; sl < NSL; ++sl) s += sGp[sl][pidx];
+    sGW[pidx / RB][pidx % RB] = s;
+  }
+  __syncthreads();
+  // next G_W, zero padded to the pass kernels' RP x RP layout
+  const int rp = r <= 16 ? 16 : 32;
+  for (int pidx = tid; pidx < rp * rp; pidx += 256) {
+    const int c = pidx / rp, q = pidx % rp;
+    f.GW[pidx] = (c < RB && q < RB) ? (float)sGW[c][q] : 0.f;
   }
   dot_wn = wave_sum(dot_wn);
   if ((tid & 63) == 0) sRed[tid >> 6] = dot_wn;
@@ -883,8 +1615,72 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
 
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              hipStream_t s) {
+  if (rp == 16 && a.r <= 8 && update && !resid) {
+    switch (mb) {
+      case 1: k_mu_pass_r8<1><<<grid, 256, 0, s>>>(a); break;
+      case 2: k_mu_pass_r8<2><<<grid, 256, 0, s>>>(a); break;
+      case 4: k_mu_pass_r8<4><<<grid, 256, 0, s>>>(a); break;
+      case 8: k_mu_pass_r8<8><<<grid, 256, 0, s>>>(a); break;
+      case 16: k_mu_pass_r8<16><<<grid, 256, 0, s>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    NTT_CHECK_LAUNCH();
+    return hipSuccess;
+  }
   return rp == 16 ? pass_fused_rp<16>(a, mb, grid, update, resid, s)
                   : pass_fused_rp<32>(a, mb, grid, update, resid, s);
+}
+
+template <int RP, int MBW, int NW>
+static hipError_t pass_L3(const PassArgs& a, int grid, bool update, bool resid, hipStream_t s) {
+  if (update && resid) k_mu_pass_L<RP, MBW, NW, true, true><<<grid, 64 * NW, 0, s>>>(a);
+  else if (update) k_mu_pass_L<RP, MBW, NW, true, false><<<grid, 64 * NW, 0, s>>>(a);
+  else k_mu_pass_L<RP, MBW, NW, false, true><<<grid, 64 * NW, 0, s>>>(a);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int RP>
+static hipError_t pass_L_rp(const PassArgs& a, int cls, int grid, bool update, bool resid, hipStream_t s) {
+  switch (cls) {
+    case 0: return pass_L3<RP, 1, 4>(a, grid, update, resid, s);   // m <= 64
+    case 1: return pass_L3<RP, 2, 4>(a, grid, update, resid, s);   // m <= 128
+    case 2: return pass_L3<RP, 4, 4>(a, grid, update, resid, s);   // m <= 256
+    case 3: return pass_L3<RP, 4, 8>(a, grid, update, resid, s);   // m <= 512
+    case 4:  // m <= 1024 (RP = 16 only: the RP = 32 instance would spill)
+      if (RP == 16) return pass_L3<16, 8, 8>(a, grid, update, resid, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int pass_L_class(int64_t m, int rp) {
+  if (m <= 64) return 0;
+  if (m <= 128) return 1;
+  if (m <= 256) return 2;
+  if (m <= 512) return 3;
+  if (m <= 1024 && rp == 16) return 4;
+  return -1;
+}
+
+int pass_L_waves(int cls) { return cls <= 2 ? 4 : 8; }
+
+hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
+                         hipStream_t s) {
+  return rp == 16 ? pass_L_rp<16>(a, cls, grid, update, resid, s)
+                  : pass_L_rp<32>(a, cls, grid, update, resid, s);
+}
+
+bool stage_1wg_ok(int64_t m, int64_t k, int r) { return m <= 256 && k <= 64 && r <= 16; }
+
+hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s) {
+  if (!stage_1wg_ok(a.m, a.k, a.r) || a.iters <= 0) return hipErrorInvalidValue;
+  const int ng = (a.k + 15) / 16;
+  if (ng == 1) k_stage_1wg<1><<<1, 256, 0, s>>>(a);
+  else if (ng == 2) k_stage_1wg<2><<<1, 256, 0, s>>>(a);
+  else k_stage_1wg<4><<<1, 256, 0, s>>>(a);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
@@ -909,15 +1705,26 @@ hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chun
   return hipSuccess;
 }
 
-hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
-  const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
-  const int nb = (int)((E + 15) / 16);
-  k_reduce_partials<<<nb, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
-  NTT_CHECK_LAUNCH();
-  if (rp == 16) k_wupdate<16><<<1, 256, 0, s>>>(f);
-  else k_wupdate<32><<<1, 256, 0, s>>>(f);
+template <int RB>
+static hipError_t launch_wupdate(const FinArgs& f, bool fused, hipStream_t s) {
+  if (fused) k_wupdate<RB, true><<<1, 256, 0, s>>>(f);
+  else k_wupdate<RB, false><<<1, 256, 0, s>>>(f);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
+  (void)rp;
+  const bool fused = f.G <= 4;
+  if (!fused) {
+    const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
+    const int nb = (int)((E + 15) / 16);
+    k_reduce_partials<<<nb, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+    NTT_CHECK_LAUNCH();
+  }
+  if (f.r <= 8) return launch_wupdate<8>(f, fused, s);
+  if (f.r <= 16) return launch_wupdate<16>(f, fused, s);
+  return launch_wupdate<32>(f, fused, s);
 }
 
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s) {

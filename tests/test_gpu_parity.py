@@ -76,8 +76,10 @@ SHAPES = [
     (16, 256, 4), (7, 33, 3), (32, 1000, 8), (45, 517, 5), (64, 130, 12), (100, 301, 16),
     (20, 64, 17), (33, 250, 24), (130, 77, 32), (256, 64, 8), (1, 50, 1), (200, 3, 3),
     (37, 2, 2),
-    # beyond the fused kernel's 256 rows: the generic path
-    (300, 200, 5), (700, 90, 20),
+    # rows split over 8 waves (m <= 512 at either padding, m <= 1024 at rank <= 16)
+    (300, 200, 5), (400, 100, 30), (600, 150, 9),
+    # beyond the fused kernels: the generic path
+    (700, 90, 20), (1100, 40, 4),
 ]
 
 
