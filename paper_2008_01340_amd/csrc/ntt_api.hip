@@ -57,6 +57,7 @@ struct Stage {
   int mb = 1;       // PASS_S: 16-row blocks
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
+  bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
 };
 
 }  // namespace
@@ -72,13 +73,14 @@ struct ntt_plan_s {
   // workspace layout (bytes)
   size_t off_h[2] = {0, 0};
   size_t off_part = 0, part_stride = 0, off_rpart = 0, off_red = 0, off_gw = 0;
-  size_t off_scal = 0, off_ints = 0, total = 0;
+  size_t off_scal = 0, off_ints = 0, off_xb = 0, total = 0;
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
   // replayable blocks of MU iterations, one per (stage, block length, buffers)
   struct GraphEntry {
     int stage, iters;
+    bool bf;
     const void *X, *H, *W, *ws;
     hipGraphExec_t exec;
   };
@@ -139,8 +141,6 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   if (cfg->precision != NTT_PREC_FP32 && cfg->precision != NTT_PREC_BF16_MIXED)
     return fail(NTT_ERR_INVALID_ARG, "unknown precision");
   if (cfg->fp32_tail_iters < 0) return fail(NTT_ERR_INVALID_ARG, "fp32_tail_iters < 0");
-  if (cfg->precision == NTT_PREC_BF16_MIXED)
-    return fail(NTT_ERR_INVALID_ARG, "BF16 mixed precision is not available in this build");
   int64_t total = 1;
   for (int i = 0; i < d; ++i) {
     if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
@@ -179,6 +179,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
 
   // stages and workspace
   size_t hsize[2] = {0, 0};
+  size_t xb_size = 0;
   size_t part_stride = 0;
   int gmax = 1;
   size_t red_max = 0;
@@ -207,6 +208,10 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
       s.kind = PASS_GENERIC;
     }
     s.fused = s.kind != PASS_GENERIC;
+    // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
+    // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
+    s.bf16 = cfg->precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
+             (s.kind == PASS_L || (s.kind == PASS_S && s.r <= 8));
     if (!s.fused) {
       const int64_t want = std::max<int64_t>(1, std::min<int64_t>((s.k + 255) / 256, 256));
       s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
@@ -221,6 +226,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
       const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
       hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
     }
+    if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
     p->total_iters += cfg->max_iters;
   }
   gmax = std::max(gmax, kSumsqBlocks);
@@ -234,6 +240,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
   p->off_scal = off; off = align_up(off + SCAL_COUNT * sizeof(double), 256);
   p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
+  p->off_xb = off; off = align_up(off + xb_size, 256);
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -271,8 +278,9 @@ struct Ctx {
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
-  PassArgs a;
+  PassArgs a{};  // every field set below; Xb (BF16 copy) stays NULL unless set by the caller
   a.X = X;
+  a.Xb = nullptr;
   a.H = H;
   a.W = W;
   a.GW = c.gw();
@@ -365,7 +373,15 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
     HIP_TRY(launch_gram_w(W, (int)st.m, st.r, st.rp, c.gw(), s));
 
     const PassArgs pa = pass_args(c, st, X, H, W, eps);
-    FinArgs fa;
+    // a8: BF16 copy of X for all but the last fp32_tail_iters iterations
+    PassArgs pa_bf = pa;
+    const int bf_iters = st.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    if (bf_iters > 0) {
+      uint16_t* xb = reinterpret_cast<uint16_t*>(c.ws + p->off_xb);
+      HIP_TRY(launch_cast_bf16(xb, X, st.m * st.k, s));
+      pa_bf.Xb = xb;
+    }
+    FinArgs fa{};
     fa.part = c.part();
     fa.part_stride = (int64_t)p->part_stride;
     fa.G = st.G;
@@ -397,9 +413,11 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
     // MU iterations (a3 + a4): each is the fused X pass (H-update and partials)
     // followed by the W-update; blocks of them replay as graphs when nothing is recorded
     const bool use_graph = !record && !profile && cfg.max_iters > 1;
-    auto graph_for = [&](int n, hipGraphExec_t* out) -> hipError_t {
+    auto graph_for = [&](int n, bool bf, hipGraphExec_t* out) -> hipError_t {
+      const PassArgs& pg = bf ? pa_bf : pa;
       for (auto& g : p->graphs)
-        if (g.stage == l && g.iters == n && g.X == X && g.H == H && g.W == W && g.ws == workspace) {
+        if (g.stage == l && g.iters == n && g.bf == bf && g.X == X && g.H == H && g.W == W &&
+            g.ws == workspace) {
           *out = g.exec;
           return hipSuccess;
         }
@@ -414,7 +432,7 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
       if (e != hipSuccess) return e;
       hipError_t le = hipSuccess;
       for (int i = 0; i < n && le == hipSuccess; ++i) {
-        le = run_pass(cc, st, pa, true, false);
+        le = run_pass(cc, st, pg, true, false);
         if (le == hipSuccess) {
           FinArgs f2 = fa;
           f2.rpart = nullptr;
@@ -437,7 +455,7 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
         (void)hipGraphExecDestroy(p->graphs.front().exec);
         p->graphs.erase(p->graphs.begin());
       }
-      p->graphs.push_back({l, n, X, H, W, workspace, exec});
+      p->graphs.push_back({l, n, bf, X, H, W, workspace, exec});
       *out = exec;
       return hipSuccess;
     };
@@ -448,8 +466,11 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
       // iterations up to the next stopping check (or the end)
       int block = cfg.max_iters - t;
       if (cfg.tol > 0.0) block = std::min(block, cfg.check_every - (t % cfg.check_every));
+      const bool bf = t < bf_iters;  // this block reads the BF16 copy of X
+      if (bf) block = std::min(block, bf_iters - t);
+      const PassArgs& pcur = bf ? pa_bf : pa;
       if (one_wg) {
-        StageArgs sa;
+        StageArgs sa{};
         sa.X = X;
         sa.W = W;
         sa.H = H;
@@ -466,7 +487,7 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
         while (block >= kGraphIters || (block > 1 && cfg.tol > 0.0)) {
           const int n = std::min(block, kGraphIters);
           hipGraphExec_t ex = nullptr;
-          HIP_TRY(graph_for(n, &ex));
+          HIP_TRY(graph_for(n, bf, &ex));
           HIP_TRY(hipGraphLaunch(ex, s));
           t += n;
           block -= n;
@@ -477,7 +498,7 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
         const bool resid = record;  // f_{t-1} of the incoming iterate
         double* slot = (resid && t >= 2) ? objective_trace + trace_off + (t - 2) : nullptr;
         if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1)], s));
-        HIP_TRY(run_pass(c, st, pa, true, resid));
+        HIP_TRY(run_pass(c, st, resid ? pa : pcur, true, resid));
         if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1) + 1], s));
         FinArgs f2 = fa;
         if (resid && !st.fused) {
@@ -572,7 +593,7 @@ static ntt_status tt_args(int32_t d, const int64_t* dims, const int64_t* ranks,
 }
 
 extern "C" ntt_status ntt_tt_workspace(int32_t d, const int64_t* dims, const int64_t* ranks, size_t* bytes) {
-  TTArgs t;
+  TTArgs t{};
   std::vector<const float*> dummy(NTT_MAX_DIMS, reinterpret_cast<const float*>(16));
   ntt_status st = tt_args(d, dims, ranks, dummy.data(), &t);
   if (st != NTT_OK) return st;
@@ -584,7 +605,7 @@ extern "C" ntt_status ntt_tt_workspace(int32_t d, const int64_t* dims, const int
 
 extern "C" ntt_status ntt_reconstruct(int32_t d, const int64_t* dims, const int64_t* ranks,
                                       const float* const* cores, float* A_out, void* stream) {
-  TTArgs t;
+  TTArgs t{};
   ntt_status st = tt_args(d, dims, ranks, cores, &t);
   if (st != NTT_OK) return st;
   if (!A_out) return fail(NTT_ERR_INVALID_ARG, "null output");
@@ -598,7 +619,7 @@ extern "C" ntt_status ntt_reconstruct(int32_t d, const int64_t* dims, const int6
 extern "C" ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_t* ranks, const float* A,
                                     const float* const* cores, void* workspace, size_t workspace_bytes,
                                     double* rel_err, void* stream) {
-  TTArgs t;
+  TTArgs t{};
   ntt_status st = tt_args(d, dims, ranks, cores, &t);
   if (st != NTT_OK) return st;
   if (!A || !rel_err) return fail(NTT_ERR_INVALID_ARG, "null A or rel_err");

@@ -16,6 +16,7 @@ enum { SCAL_NX2 = 0, SCAL_OBJ = 1, SCAL_MONITOR = 2, SCAL_OBJ0 = 3, SCAL_COUNT =
 // One MU pass over the columns of an m x k unfolding.
 struct PassArgs {
   const float* X;       // m x k, row stride k
+  const uint16_t* Xb;   // BF16 shadow of X (read instead of X when not NULL)
   float* H;             // r x k, row stride k (updated in place)
   const float* W;       // m x r
   const float* GW;      // RP x RP, W^T W zero padded
@@ -65,6 +66,7 @@ struct TTArgs {
 
 hipError_t launch_init_uniform(float* out, int64_t n, uint64_t seed, uint64_t tag, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_cast_bf16(uint16_t* dst, const float* src, int64_t n, hipStream_t s);
 hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, int* flags,
                         int validate, double* out, hipStream_t s);
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);

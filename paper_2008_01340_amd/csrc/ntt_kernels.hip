@@ -177,6 +177,30 @@ __device__ __forceinline__ float fast_div(float x, float y) {
   return fmaf(e, r, q0);
 }
 
+// X element loads: FP32 storage, or the BF16 shadow (widened exactly to FP32).
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+template <bool XBF>
+__device__ __forceinline__ float4 ldx4(const PassArgs& p, int64_t off) {
+  if (XBF) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p.Xb + off);
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  }
+  return *reinterpret_cast<const float4*>(p.X + off);
+}
+
+template <bool XBF>
+__device__ __forceinline__ float ldx(const PassArgs& p, int64_t off) {
+  return XBF ? bf16_to_f32(p.Xb[off]) : p.X[off];
+}
+
+template <bool XBF>
+__device__ __forceinline__ bool x_aligned(const PassArgs& p) {
+  return XBF ? ((reinterpret_cast<uintptr_t>(p.Xb) & 7) == 0)
+             : ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0);
+}
+
 // Variant for m <= 16*MB (MB 16-row blocks held in registers) and r <= RP.
 // Each wavefront takes 16-column groups (group g = global wave id + s * total waves).
 // UPDATE: do the H-update and accumulate X H_new^T and H_new H_new^T partials.
@@ -470,7 +494,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
 //                                              (rows 4(b&1).., cols 4(b>>1)..) of column a
 // Rows and columns beyond r are zero in G and H_new, so the 8-wide sums are exact for any
 // r <= 8.
-template <int MB>
+template <int MB, bool XBF>
 __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   constexpr int MPAD = 16 * MB;
   constexpr int SX = 20;
@@ -519,7 +543,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 
   const int64_t ngroups = (k + 15) >> 4;
   const int64_t wstride = (int64_t)gridDim.x * 4;
-  const bool vec_ok = ((k & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0) &&
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
                       ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
   float* sXw = sX[w];
   float* sHw = sHn[w];
@@ -527,9 +551,9 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   float* sHncw = sHnc[w];
   const int rq = 4 * (b & 1), cq = 4 * (b >> 1);  // G_H block of this lane
   // row pointers of this lane (clamped into the matrix)
-  const float* xrow[MB];
+  int64_t xrow[MB];  // row offsets of this lane (clamped into the matrix)
 #pragma unroll
-  for (int blk = 0; blk < MB; ++blk) xrow[blk] = p.X + (int64_t)min(16 * blk + a, m - 1) * k;
+  for (int blk = 0; blk < MB; ++blk) xrow[blk] = (int64_t)min(16 * blk + a, m - 1) * k;
   const float* hrow[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) hrow[kk] = p.H + (int64_t)min(4 * b + kk, r - 1) * k;
@@ -539,7 +563,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
     if (vec_ok && (j0 + 16 <= k)) {
 #pragma unroll
       for (int blk = 0; blk < MB; ++blk) {
-        const float4 v = *reinterpret_cast<const float4*>(xrow[blk] + j0 + 4 * b);
+        const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
         xr[blk][0] = v.x; xr[blk][1] = v.y; xr[blk][2] = v.z; xr[blk][3] = v.w;
       }
 #pragma unroll
@@ -550,7 +574,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
-          const float v = xrow[blk][min(col, k - 1)];
+          const float v = ldx<XBF>(p, xrow[blk] + min(col, k - 1));
           xr[blk][q] = col < k ? v : 0.f;
         }
       const int64_t col = j0 + a;
@@ -718,7 +742,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 // applies the same epilogue to the full sum (so all hold the same H_new); wave 0 stores
 // H_new and accumulates H_new H_new^T; each wave accumulates X H_new^T for its own rows,
 // so that partial needs no cross-wave reduction.  W stays in registers as MFMA operands.
-template <int RP, int MBW, int NW, bool UPDATE, bool RESID>
+template <int RP, int MBW, int NW, bool UPDATE, bool RESID, bool XBF>
 __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
   constexpr int NH = RP / 16;
   constexpr int SX = 20;
@@ -773,13 +797,13 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
     for (int q = 0; q < NH; ++q) accG[h][q] = v4f{0.f, 0.f, 0.f, 0.f};
 
   const int64_t ngroups = (k + 15) >> 4;
-  const bool vec_ok = ((k & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0) &&
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
                       ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
   float* sXw = sX[w];
   float* sHw = sHn[w];
-  const float* xrow[MBW];
+  int64_t xrow[MBW];  // row offsets of this lane (clamped into the matrix)
 #pragma unroll
-  for (int blk = 0; blk < MBW; ++blk) xrow[blk] = p.X + (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
+  for (int blk = 0; blk < MBW; ++blk) xrow[blk] = (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
 
   int par = 0;
   for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
@@ -789,7 +813,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
     if (full) {
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk) {
-        const float4 v = *reinterpret_cast<const float4*>(xrow[blk] + j0 + 4 * b);
+        const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
         const bool ok = !RESID || (row0 + 16 * blk + a < m);
         xr[blk][0] = ok ? v.x : 0.f;
         xr[blk][1] = ok ? v.y : 0.f;
@@ -802,7 +826,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
-          const float v = xrow[blk][min(col, k - 1)];
+          const float v = ldx<XBF>(p, xrow[blk] + min(col, k - 1));
           xr[blk][q] = (col < k && row0 + 16 * blk + a < m) ? v : 0.f;
         }
     }
@@ -1445,6 +1469,19 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
   }
 }
 
+// BF16 shadow of X: round to nearest, ties to even (NaN stays NaN).
+__global__ void k_cast_bf16(uint16_t* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const uint32_t u = __float_as_uint(src[i]);
+    uint16_t o;
+    if ((u & 0x7fffffffu) > 0x7f800000u) o = (uint16_t)((u >> 16) | 0x40u);
+    else o = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    dst[i] = o;
+  }
+}
+
 // copy helper: dst[i] = src[i]
 __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1567,6 +1604,14 @@ hipError_t launch_init_uniform(float* out, int64_t n, uint64_t seed, uint64_t ta
   return hipSuccess;
 }
 
+hipError_t launch_cast_bf16(uint16_t* dst, const float* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  k_cast_bf16<<<(int)blocks, 256, 0, s>>>(dst, src, n);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
@@ -1616,26 +1661,38 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              hipStream_t s) {
   if (rp == 16 && a.r <= 8 && update && !resid) {
+    const bool xb = a.Xb != nullptr;
     switch (mb) {
-      case 1: k_mu_pass_r8<1><<<grid, 256, 0, s>>>(a); break;
-      case 2: k_mu_pass_r8<2><<<grid, 256, 0, s>>>(a); break;
-      case 4: k_mu_pass_r8<4><<<grid, 256, 0, s>>>(a); break;
-      case 8: k_mu_pass_r8<8><<<grid, 256, 0, s>>>(a); break;
-      case 16: k_mu_pass_r8<16><<<grid, 256, 0, s>>>(a); break;
+      case 1:
+        if (xb) k_mu_pass_r8<1, true><<<grid, 256, 0, s>>>(a);
+        else k_mu_pass_r8<1, false><<<grid, 256, 0, s>>>(a);
+        break;
+      case 2:
+        if (xb) k_mu_pass_r8<2, true><<<grid, 256, 0, s>>>(a);
+        else k_mu_pass_r8<2, false><<<grid, 256, 0, s>>>(a);
+        break;
       default: return hipErrorInvalidValue;
     }
     NTT_CHECK_LAUNCH();
     return hipSuccess;
   }
+  if (a.Xb != nullptr) return hipErrorInvalidValue;  // BF16 X only in the r <= 8 and row-split passes
   return rp == 16 ? pass_fused_rp<16>(a, mb, grid, update, resid, s)
                   : pass_fused_rp<32>(a, mb, grid, update, resid, s);
 }
 
 template <int RP, int MBW, int NW>
 static hipError_t pass_L3(const PassArgs& a, int grid, bool update, bool resid, hipStream_t s) {
-  if (update && resid) k_mu_pass_L<RP, MBW, NW, true, true><<<grid, 64 * NW, 0, s>>>(a);
-  else if (update) k_mu_pass_L<RP, MBW, NW, true, false><<<grid, 64 * NW, 0, s>>>(a);
-  else k_mu_pass_L<RP, MBW, NW, false, true><<<grid, 64 * NW, 0, s>>>(a);
+  if (a.Xb != nullptr) {
+    if (!update || resid) return hipErrorInvalidValue;  // BF16 X: update passes only
+    k_mu_pass_L<RP, MBW, NW, true, false, true><<<grid, 64 * NW, 0, s>>>(a);
+  } else if (update && resid) {
+    k_mu_pass_L<RP, MBW, NW, true, true, false><<<grid, 64 * NW, 0, s>>>(a);
+  } else if (update) {
+    k_mu_pass_L<RP, MBW, NW, true, false, false><<<grid, 64 * NW, 0, s>>>(a);
+  } else {
+    k_mu_pass_L<RP, MBW, NW, false, true, false><<<grid, 64 * NW, 0, s>>>(a);
+  }
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -301,3 +301,42 @@ def test_full_size_32pow5_properties_and_sampled_parity():
     say(f"  rel err gpu {e_gpu:.6e} oracle(recon of gpu cores) {e_orc:.6e}")
     assert e_gpu == pytest.approx(e_orc, rel=1e-5)
     assert e_gpu < 0.05
+
+
+# ------------------------------------------------------------------ a8: BF16 precision mode
+BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
+
+
+@pytest.mark.parametrize("dims,gen,noise,level,T", [
+    ((16, 16, 16), (1, 4, 4, 1), "none", 0.0, 200),
+    ((48, 48, 48, 48), (1, 16, 16, 16, 1), "absnormal", 0.01, 200),
+    ((24, 30, 20, 36), (1, 6, 8, 5, 1), "mult", 0.01, 150),
+])
+def test_bf16_mode_final_error_matches_oracle(dims, gen, noise, level, T):
+    say(f"case: BF16 mode dims={dims} ranks={gen} T={T} tail=20")
+    A = S.noisy_tensor(dims, gen, seed=7, noise=noise, level=level)
+    ref = O.ntt_decompose(A, gen, T, seed=3)
+    e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+    Ad = dev(A)
+    res = ntt.decompose(Ad, gen, T, seed=3, precision=ntt.NTT_PREC_BF16_MIXED, fp32_tail_iters=20)
+    e_bf = ntt.rel_error(Ad, res.cores)
+    r32 = ntt.decompose(Ad, gen, T, seed=3)
+    e_32 = ntt.rel_error(Ad, r32.cores)
+    say(f"  rel err: oracle {e_orc:.6e}  fp32 {e_32:.6e}  bf16 {e_bf:.6e}")
+    assert abs(e_bf - e_orc) <= BF16_BAR
+    assert abs(e_32 - e_orc) <= 1e-5 * max(e_orc, 1e-3) + 1e-6
+    for c in res.cores:
+        assert float(c.min()) >= 0.0
+    # the report's explicit per-stage objectives are evaluated against FP32 X
+    assert all(np.isfinite(res.report["objective"]))
+
+
+def test_bf16_mode_with_all_iterations_fp32_equals_fp32_mode():
+    say("case: BF16 mode with fp32_tail_iters >= T is the FP32 sweep, bit for bit")
+    w = S.workload("tt16x3_r4")
+    Ad = dev(w.tensor())
+    a = ntt.decompose(Ad, w.target_ranks, 50, seed=1, precision=ntt.NTT_PREC_BF16_MIXED,
+                      fp32_tail_iters=50)
+    b = ntt.decompose(Ad, w.target_ranks, 50, seed=1)
+    for x, y in zip(a.cores, b.cores):
+        assert torch.equal(x, y)
