@@ -153,6 +153,34 @@ ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_t* ranks, c
 /* Eq.(4) for arbitrary ranks (host only). */
 double ntt_compression_ratio(int32_t d, const int64_t* dims, const int64_t* ranks);
 
+/* ---- Batched mode: many independent decompositions of uneven shape and rank.
+ * Not a step of the paper: a throughput mode over the same per-problem sweep.
+ * Stage levels advance together; unfoldings with m <= 256, k <= 64, r <= 16 run all their
+ * iterations in grouped single-workgroup launches (one workgroup per problem), the
+ * rest replay per-problem iteration graphs on a pool of streams.  Problems share no
+ * reduction, so each result is bitwise the same as when the problem is decomposed alone
+ * with ntt_decompose.  */
+typedef struct ntt_batch_s* ntt_batch_t;
+
+/* One config per problem (same rules as ntt_plan; the RECORD/PROFILE/VALIDATE flags are
+ * not accepted).  The arrays the configs point to are read during the call only. */
+ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_batch_t* out);
+
+/* Device workspace bytes for the whole batch (the sum of the problems' workspaces plus
+ * a work-list area). */
+ntt_status ntt_batch_workspace(ntt_batch_t batch, size_t* bytes);
+
+/* Decompose every problem of the batch.
+ *   A[i]       : device input of problem i (n_1...n_d floats, read only).
+ *   cores[i][k]: device core k of problem i, as in ntt_decompose.
+ *   reports    : NULL or `count` host reports.
+ * Returns after the stream has finished all problems. */
+ntt_status ntt_decompose_batch(ntt_batch_t batch, void* stream, void* workspace,
+                               const float* const* A, float* const* const* cores,
+                               ntt_report* reports);
+
+void ntt_batch_destroy(ntt_batch_t batch);
+
 void ntt_plan_destroy(ntt_plan_t plan);
 const char* ntt_status_string(ntt_status s);
 const char* ntt_last_error(void);

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,13 +86,11 @@ struct ntt_plan_s {
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
-  hipStream_t cap_stream = nullptr;
   ~ntt_plan_s() {
     for (auto e : prof_events) (void)hipEventDestroy(e);
     if (events_ready)
       for (auto e : stage_ev) (void)hipEventDestroy(e);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -238,7 +237,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_rpart = off; off = align_up(off + (size_t)gmax * sizeof(double), 256);
   p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
   p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
-  p->off_scal = off; off = align_up(off + SCAL_COUNT * sizeof(double), 256);
+  p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
   p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
   p->off_xb = off; off = align_up(off + xb_size, 256);
   p->total = off;
@@ -265,6 +264,7 @@ __global__ void k_zero_ints(int* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+// Workspace views of one problem.
 struct Ctx {
   ntt_plan_s* p;
   hipStream_t s;
@@ -273,8 +273,11 @@ struct Ctx {
   double* rpart() const { return reinterpret_cast<double*>(ws + p->off_rpart); }
   double* red() const { return reinterpret_cast<double*>(ws + p->off_red); }
   float* gw() const { return reinterpret_cast<float*>(ws + p->off_gw); }
-  double* scal() const { return reinterpret_cast<double*>(ws + p->off_scal); }
-  int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }  // [0] flags, [1] ticket
+  double* scal(int l) const {  // FP64 scalars of stage l (1-based)
+    return reinterpret_cast<double*>(ws + p->off_scal) + (size_t)SCAL_COUNT * (l - 1);
+  }
+  int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }  // [0] input flags
+  uint16_t* xb() const { return reinterpret_cast<uint16_t*>(ws + p->off_xb); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -294,270 +297,377 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
   return a;
 }
 
-hipError_t run_pass(const Ctx& c, const Stage& s, const PassArgs& a, bool update, bool resid) {
-  if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, c.s);
-  if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, c.s);
-  return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, c.s);
+hipError_t run_pass(hipStream_t q, const Stage& s, const PassArgs& a, bool update, bool resid) {
+  if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, q);
+  if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, q);
+  return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, q);
 }
 
-int resid_blocks(const Stage& s) {
-  return s.fused ? s.G : (int)((s.k + 255) / 256);
-}
+int resid_blocks(const Stage& s) { return s.fused ? s.G : (int)((s.k + 255) / 256); }
 
 }  // namespace
 
-extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace, const float* A,
-                                    float* const* cores, const float* const* init_W,
-                                    const float* const* init_H, double* objective_trace,
-                                    ntt_report* report) {
-  if (!p) return fail(NTT_ERR_INVALID_ARG, "null plan");
-  if (!workspace) return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "null workspace");
-  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-    return fail(NTT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (!A || !cores) return fail(NTT_ERR_INVALID_ARG, "null A or cores");
-  const int d = p->d;
-  for (int i = 0; i < d; ++i)
-    if (!cores[i]) return fail(NTT_ERR_INVALID_ARG, "null core pointer");
-  const ntt_config& cfg = p->cfg;
-  const bool record = (cfg.flags & NTT_RECORD_OBJECTIVE) && objective_trace;
-  const bool profile = (cfg.flags & NTT_PROFILE) && report;
-  const bool want_final = record || report || cfg.tol > 0.0;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Ctx c{p, s, reinterpret_cast<char*>(workspace)};
-  const float eps = (float)cfg.eps;
-
-  if (!p->events_ready) {
-    for (auto& e : p->stage_ev) HIP_TRY(hipEventCreate(&e));
-    p->events_ready = true;
-  }
-  if (profile && (int64_t)p->prof_events.size() < 2 * (int64_t)cfg.max_iters) {
-    const size_t need = 2 * (size_t)cfg.max_iters;
-    while (p->prof_events.size() < need) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      p->prof_events.push_back(e);
-    }
-  }
-  ntt_report rep;
-  memset(&rep, 0, sizeof(rep));
-  for (int i = 0; i <= d; ++i) rep.eff_ranks[i] = p->eff[i];
-  rep.compression_ratio = p->compression;
-
-  k_zero_ints<<<1, 64, 0, s>>>(c.ints(), 64);
-  HIP_TRY(hipGetLastError());
-
+// One decomposition in flight: the sweep as a resumable state machine (stage l,
+// iteration t), so that it can run to completion (ntt_decompose), in lock-step with
+// other problems (batched mode), or a block of iterations at a time (serving).
+struct NttJob {
+  ntt_plan_s* p = nullptr;
+  Ctx c{};
+  const float* A = nullptr;
+  std::vector<float*> cores;
+  std::vector<const float*> initW, initH;
+  double* trace = nullptr;
+  bool record = false, profile = false, want_final = false;
+  int l = 1, t = 0;
+  bool prepared = false, done = false;
   int64_t trace_off = 0;
-  for (int l = 1; l < d; ++l) {
-    const Stage& st = p->st[l - 1];
-    const float* X = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
-    float* H = (l == d - 1) ? cores[d - 1] : reinterpret_cast<float*>(c.ws + p->off_h[(l - 1) & 1]);
-    float* W = cores[l - 1];
-    const int64_t mr = st.m * st.r, rk = (int64_t)st.r * st.k;
-    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1)], s));
+  int iters[NTT_MAX_DIMS] = {};
+  // state of the current stage
+  const float* X = nullptr;
+  float* H = nullptr;
+  float* W = nullptr;
+  PassArgs pa{}, pa_bf{};
+  FinArgs fa{};
+  int bf_iters = 0;
+  bool one_wg = false, final_known = false;
+  double nx = 0.0;
+  std::vector<double> fhist;
 
-    // a1: ||X_l||^2 in FP64 (and the input check on the first unfolding)
+  const Stage& st() const { return p->st[l - 1]; }
+  int d() const { return p->d; }
+
+  ntt_status start(ntt_plan_s* plan, hipStream_t s, void* workspace, const float* A_,
+                   float* const* cores_, const float* const* iW, const float* const* iH,
+                   double* trace_, bool want_report) {
+    p = plan;
+    c = Ctx{plan, s, reinterpret_cast<char*>(workspace)};
+    A = A_;
+    cores.assign(cores_, cores_ + plan->d);
+    initW.assign(plan->d, nullptr);
+    initH.assign(plan->d, nullptr);
+    if (iW)
+      for (int i = 0; i < plan->d - 1; ++i) initW[i] = iW[i];
+    if (iH)
+      for (int i = 0; i < plan->d - 1; ++i) initH[i] = iH[i];
+    trace = trace_;
+    record = (plan->cfg.flags & NTT_RECORD_OBJECTIVE) && trace_;
+    profile = (plan->cfg.flags & NTT_PROFILE) && want_report;
+    want_final = record || want_report || plan->cfg.tol > 0.0;
+    l = 1;
+    t = 0;
+    prepared = done = false;
+    trace_off = 0;
+    k_zero_ints<<<1, 64, 0, s>>>(c.ints(), 64);
+    HIP_TRY(hipGetLastError());
+    return NTT_OK;
+  }
+
+  // a1 (norm, input check), a2 (initial factors), W^T W, and the BF16 copy (a8)
+  ntt_status prepare_stage(bool validate_now) {
+    const ntt_config& cfg = p->cfg;
+    const Stage& s = st();
+    hipStream_t q = c.s;
+    const int dd = d();
+    X = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
+    H = (l == dd - 1) ? cores[dd - 1] : reinterpret_cast<float*>(c.ws + p->off_h[(l - 1) & 1]);
+    W = cores[l - 1];
+    const int64_t mr = s.m * s.r, rk = (int64_t)s.r * s.k;
     const bool validate = (l == 1) && (cfg.flags & NTT_VALIDATE_INPUT);
-    HIP_TRY(launch_sumsq(X, st.m * st.k, c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
-                         c.scal() + SCAL_NX2, s));
-    if (validate) {
+    HIP_TRY(launch_sumsq(X, s.m * s.k, c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
+                         c.scal(l) + SCAL_NX2, q));
+    if (validate && validate_now) {
       int flag = 0;
-      HIP_TRY(hipMemcpyAsync(&flag, c.ints(), sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipMemcpyAsync(&flag, c.ints(), sizeof(int), hipMemcpyDeviceToHost, q));
+      HIP_TRY(hipStreamSynchronize(q));
       if (flag) return fail(NTT_ERR_NEGATIVE_INPUT, "input holds a negative, NaN or Inf entry");
     }
-    // a2: initial factors
-    if (init_W && init_W[l - 1]) HIP_TRY(launch_copy(W, init_W[l - 1], mr, s));
-    else HIP_TRY(launch_init_uniform(W, mr, cfg.seed, 2ull * l, s));
-    if (init_H && init_H[l - 1]) HIP_TRY(launch_copy(H, init_H[l - 1], rk, s));
-    else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, s));
-    HIP_TRY(launch_gram_w(W, (int)st.m, st.r, st.rp, c.gw(), s));
-
-    const PassArgs pa = pass_args(c, st, X, H, W, eps);
-    // a8: BF16 copy of X for all but the last fp32_tail_iters iterations
-    PassArgs pa_bf = pa;
-    const int bf_iters = st.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    if (initW[l - 1]) HIP_TRY(launch_copy(W, initW[l - 1], mr, q));
+    else HIP_TRY(launch_init_uniform(W, mr, cfg.seed, 2ull * l, q));
+    if (initH[l - 1]) HIP_TRY(launch_copy(H, initH[l - 1], rk, q));
+    else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, q));
+    one_wg = !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
+    if (!one_wg) HIP_TRY(launch_gram_w(W, (int)s.m, s.r, s.rp, c.gw(), q));
+    const float eps = (float)cfg.eps;
+    pa = pass_args(c, s, X, H, W, eps);
+    pa_bf = pa;
+    bf_iters = s.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
     if (bf_iters > 0) {
-      uint16_t* xb = reinterpret_cast<uint16_t*>(c.ws + p->off_xb);
-      HIP_TRY(launch_cast_bf16(xb, X, st.m * st.k, s));
-      pa_bf.Xb = xb;
+      HIP_TRY(launch_cast_bf16(c.xb(), X, s.m * s.k, q));
+      pa_bf.Xb = c.xb();
     }
-    FinArgs fa{};
+    fa = FinArgs{};
     fa.part = c.part();
     fa.part_stride = (int64_t)p->part_stride;
-    fa.G = st.G;
-    fa.m = (int)st.m;
-    fa.r = st.r;
+    fa.G = s.G;
+    fa.m = (int)s.m;
+    fa.r = s.r;
     fa.red = c.red();
     fa.W = W;
     fa.GW = c.gw();
-    fa.scal = c.scal();
+    fa.scal = c.scal(l);
     fa.eps = eps;
-
-    auto residual_now = [&](double* trace_slot) -> hipError_t {
-      hipError_t e = run_pass(c, st, pa, false, true);
-      if (e != hipSuccess) return e;
-      return launch_resid_sum(c.rpart(), resid_blocks(st), c.scal() + SCAL_OBJ, trace_slot, s);
-    };
-    std::vector<double> fhist;
-    double nx = 0.0;
+    t = 0;
+    final_known = false;
+    fhist.clear();
     if (cfg.tol > 0.0) {
       HIP_TRY(residual_now(nullptr));
       double h2[2];
-      HIP_TRY(hipMemcpyAsync(h2, c.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipMemcpyAsync(h2, c.scal(l), 2 * sizeof(double), hipMemcpyDeviceToHost, q));
+      HIP_TRY(hipStreamSynchronize(q));
       nx = std::sqrt(h2[SCAL_NX2]);
       fhist.push_back(h2[SCAL_OBJ]);
     }
-    int t_done = 0;
-    bool final_known = false;
-    // MU iterations (a3 + a4): each is the fused X pass (H-update and partials)
-    // followed by the W-update; blocks of them replay as graphs when nothing is recorded
+    prepared = true;
+    return NTT_OK;
+  }
+
+  hipError_t residual_now(double* slot) {
+    hipError_t e = run_pass(c.s, st(), pa, false, true);
+    if (e != hipSuccess) return e;
+    return launch_resid_sum(c.rpart(), resid_blocks(st()), c.scal(l) + SCAL_OBJ, slot, c.s);
+  }
+
+  hipError_t graph_for(int n, bool bf, hipGraphExec_t* out) {
+    const PassArgs& pg = bf ? pa_bf : pa;
+    for (auto& g : p->graphs)
+      if (g.stage == l && g.iters == n && g.bf == bf && g.X == X && g.H == H && g.W == W &&
+          g.ws == c.ws) {
+        *out = g.exec;
+        return hipSuccess;
+      }
+    // capture on one library-wide stream (graphs are then launched on any stream)
+    static std::mutex cap_mu;
+    static hipStream_t cap_stream = nullptr;
+    std::lock_guard<std::mutex> lock(cap_mu);
+    hipError_t e;
+    if (!cap_stream) {
+      e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < n && le == hipSuccess; ++i) {
+      le = run_pass(cap_stream, st(), pg, true, false);
+      if (le == hipSuccess) {
+        FinArgs f2 = fa;
+        f2.rpart = nullptr;
+        f2.trace = nullptr;
+        le = launch_finalize(f2, st().rp, cap_stream);
+      }
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap_stream, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return le;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (p->graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({l, n, bf, X, H, W, c.ws, exec});
+    *out = exec;
+    return hipSuccess;
+  }
+
+  // a3 + a4: up to `budget` MU iterations of the current stage (a stopping check of a5
+  // may end the stage early); *stage_done is set when no iterations remain.
+  ntt_status iterate(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    const Stage& s = st();
+    hipStream_t q = c.s;
     const bool use_graph = !record && !profile && cfg.max_iters > 1;
-    auto graph_for = [&](int n, bool bf, hipGraphExec_t* out) -> hipError_t {
-      const PassArgs& pg = bf ? pa_bf : pa;
-      for (auto& g : p->graphs)
-        if (g.stage == l && g.iters == n && g.bf == bf && g.X == X && g.H == H && g.W == W &&
-            g.ws == workspace) {
-          *out = g.exec;
-          return hipSuccess;
-        }
-      hipError_t e;
-      if (!p->cap_stream) {
-        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
-      }
-      Ctx cc = c;
-      cc.s = p->cap_stream;
-      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return e;
-      hipError_t le = hipSuccess;
-      for (int i = 0; i < n && le == hipSuccess; ++i) {
-        le = run_pass(cc, st, pg, true, false);
-        if (le == hipSuccess) {
-          FinArgs f2 = fa;
-          f2.rpart = nullptr;
-          f2.trace = nullptr;
-          le = launch_finalize(f2, st.rp, p->cap_stream);
-        }
-      }
-      hipGraph_t graph = nullptr;
-      e = hipStreamEndCapture(p->cap_stream, &graph);
-      if (le != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return le;
-      }
-      if (e != hipSuccess) return e;
-      hipGraphExec_t exec = nullptr;
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) return e;
-      if (p->graphs.size() >= kMaxGraphs) {
-        (void)hipGraphExecDestroy(p->graphs.front().exec);
-        p->graphs.erase(p->graphs.begin());
-      }
-      p->graphs.push_back({l, n, bf, X, H, W, workspace, exec});
-      *out = exec;
-      return hipSuccess;
-    };
-    // small unfoldings: whole blocks of iterations in one single-workgroup launch
-    const bool one_wg = !record && !profile && stage_1wg_ok(st.m, st.k, st.r);
-    int t = 0;
-    while (t < cfg.max_iters) {
-      // iterations up to the next stopping check (or the end)
-      int block = cfg.max_iters - t;
+    bool stop = false;
+    while (budget > 0 && t < cfg.max_iters && !stop) {
+      int block = std::min(budget, cfg.max_iters - t);
       if (cfg.tol > 0.0) block = std::min(block, cfg.check_every - (t % cfg.check_every));
       const bool bf = t < bf_iters;  // this block reads the BF16 copy of X
       if (bf) block = std::min(block, bf_iters - t);
       const PassArgs& pcur = bf ? pa_bf : pa;
+      int n_done = 0;
       if (one_wg) {
         StageArgs sa{};
         sa.X = X;
         sa.W = W;
         sa.H = H;
-        sa.m = (int)st.m;
-        sa.r = st.r;
-        sa.k = (int)st.k;
+        sa.m = (int)s.m;
+        sa.r = s.r;
+        sa.k = (int)s.k;
         sa.iters = block;
-        sa.eps = eps;
-        HIP_TRY(launch_stage_1wg(sa, s));
-        t += block;
-        block = 0;
-      }
-      if (use_graph) {
-        while (block >= kGraphIters || (block > 1 && cfg.tol > 0.0)) {
-          const int n = std::min(block, kGraphIters);
-          hipGraphExec_t ex = nullptr;
-          HIP_TRY(graph_for(n, bf, &ex));
-          HIP_TRY(hipGraphLaunch(ex, s));
-          t += n;
-          block -= n;
+        sa.eps = (float)cfg.eps;
+        HIP_TRY(launch_stage_1wg(sa, q));
+        n_done = block;
+      } else {
+        if (use_graph) {
+          while (block - n_done >= kGraphIters || (block - n_done > 1 && cfg.tol > 0.0)) {
+            const int n = std::min(block - n_done, kGraphIters);
+            hipGraphExec_t ex = nullptr;
+            HIP_TRY(graph_for(n, bf, &ex));
+            HIP_TRY(hipGraphLaunch(ex, q));
+            n_done += n;
+          }
+        }
+        for (; n_done < block; ++n_done) {
+          const int tt = t + n_done + 1;
+          const bool resid = record;  // f_{tt-1} of the incoming iterate
+          double* slot = (resid && tt >= 2) ? trace + trace_off + (tt - 2) : nullptr;
+          if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (tt - 1)], q));
+          HIP_TRY(run_pass(q, s, resid ? pa : pcur, true, resid));
+          if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (tt - 1) + 1], q));
+          FinArgs f2 = fa;
+          if (resid && !s.fused) {
+            HIP_TRY(launch_resid_sum(c.rpart(), resid_blocks(s), c.scal(l) + SCAL_OBJ, slot, q));
+            f2.rpart = nullptr;
+            f2.trace = nullptr;
+          } else {
+            f2.rpart = resid ? c.rpart() : nullptr;
+            f2.trace = resid ? slot : nullptr;
+          }
+          HIP_TRY(launch_finalize(f2, s.rp, q));
         }
       }
-      for (; block > 0; --block) {
-        ++t;
-        const bool resid = record;  // f_{t-1} of the incoming iterate
-        double* slot = (resid && t >= 2) ? objective_trace + trace_off + (t - 2) : nullptr;
-        if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1)], s));
-        HIP_TRY(run_pass(c, st, resid ? pa : pcur, true, resid));
-        if (profile) HIP_TRY(hipEventRecord(p->prof_events[2 * (t - 1) + 1], s));
-        FinArgs f2 = fa;
-        if (resid && !st.fused) {
-          HIP_TRY(launch_resid_sum(c.rpart(), resid_blocks(st), c.scal() + SCAL_OBJ, slot, s));
-          f2.rpart = nullptr;
-          f2.trace = nullptr;
-        } else {
-          f2.rpart = resid ? c.rpart() : nullptr;
-          f2.trace = resid ? slot : nullptr;
-        }
-        HIP_TRY(launch_finalize(f2, st.rp, s));
-      }
-      t_done = t;
+      t += block;
+      budget -= block;
       final_known = false;
       if (cfg.tol > 0.0 && t % cfg.check_every == 0) {
-        HIP_TRY(residual_now(record ? objective_trace + trace_off + (t - 1) : nullptr));
+        HIP_TRY(residual_now(record ? trace + trace_off + (t - 1) : nullptr));
         double ft = 0.0;
-        HIP_TRY(hipMemcpyAsync(&ft, c.scal() + SCAL_OBJ, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpyAsync(&ft, c.scal(l) + SCAL_OBJ, sizeof(double), hipMemcpyDeviceToHost, q));
+        HIP_TRY(hipStreamSynchronize(q));
         fhist.resize(t + 1, 0.0);
         fhist[t] = ft;
         final_known = true;
         const double fprev = fhist[t - cfg.check_every];
-        if (std::sqrt(2.0 * std::max(ft, 0.0)) / nx <= cfg.tol || (fprev - ft) <= cfg.tol * fprev) break;
+        if (std::sqrt(2.0 * std::max(ft, 0.0)) / nx <= cfg.tol || (fprev - ft) <= cfg.tol * fprev)
+          stop = true;
       }
     }
-    if (want_final && !final_known)
-      HIP_TRY(residual_now((record && t_done >= 1) ? objective_trace + trace_off + (t_done - 1) : nullptr));
-    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1) + 1], s));
-    rep.iters[l - 1] = t_done;
-    rep.gflop[l - 1] = (double)t_done * (4.0 * st.m * st.k * st.r + 4.0 * (st.m + st.k) * st.r * st.r) * 1e-9;
-    if (report) {
-      double h2[2];
-      HIP_TRY(hipMemcpyAsync(h2, c.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      rep.norm_x[l - 1] = std::sqrt(h2[SCAL_NX2]);
-      rep.objective[l - 1] = h2[SCAL_OBJ];
-      rep.stage_rel_err[l - 1] =
-          rep.norm_x[l - 1] > 0 ? std::sqrt(2.0 * std::max(h2[SCAL_OBJ], 0.0)) / rep.norm_x[l - 1] : 0.0;
-      if (profile && t_done > 0) {
-        double sum = 0.0;
-        for (int t = 0; t < t_done; ++t) {
-          float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, p->prof_events[2 * t], p->prof_events[2 * t + 1]));
-          sum += ms;
-        }
-        rep.pass_ms[l - 1] = sum / t_done;
-      }
-    }
-    trace_off += cfg.max_iters;
+    *stage_done = stop || t >= cfg.max_iters;
+    if (stop) iters[l - 1] = t;
+    return NTT_OK;
   }
+
+  // a5 at the end of the stage (explicit objective of the final iterate), then a6:
+  // W is already core l; H becomes the next unfolding (or is core d).
+  ntt_status finish_stage() {
+    const ntt_config& cfg = p->cfg;
+    if (iters[l - 1] == 0) iters[l - 1] = t;
+    if (want_final && !final_known)
+      HIP_TRY(residual_now((record && t >= 1) ? trace + trace_off + (t - 1) : nullptr));
+    trace_off += cfg.max_iters;
+    prepared = false;
+    if (l + 1 >= d()) done = true;
+    else ++l;
+    return NTT_OK;
+  }
+
+  // one stage from start to end on the job's stream
+  ntt_status run_stage() {
+    ntt_status e = prepare_stage(true);
+    if (e != NTT_OK) return e;
+    bool sd = false;
+    e = iterate(p->cfg.max_iters, &sd);
+    if (e != NTT_OK) return e;
+    return finish_stage();
+  }
+
+  // per-stage FP64 scalars (asynchronous copy; valid after the stream has synchronised)
+  hipError_t fetch_scalars(double* host) {
+    return hipMemcpyAsync(host, c.scal(1), sizeof(double) * SCAL_COUNT * (d() - 1),
+                          hipMemcpyDeviceToHost, c.s);
+  }
+
+  void fill_report(const double* sc, ntt_report* rep) const {
+    memset(rep, 0, sizeof(*rep));
+    for (int i = 0; i <= d(); ++i) rep->eff_ranks[i] = p->eff[i];
+    rep->compression_ratio = p->compression;
+    for (int ll = 1; ll < d(); ++ll) {
+      const Stage& s = p->st[ll - 1];
+      const double* v = sc + (size_t)SCAL_COUNT * (ll - 1);
+      rep->iters[ll - 1] = iters[ll - 1];
+      rep->norm_x[ll - 1] = std::sqrt(v[SCAL_NX2]);
+      rep->objective[ll - 1] = v[SCAL_OBJ];
+      rep->stage_rel_err[ll - 1] =
+          rep->norm_x[ll - 1] > 0 ? std::sqrt(2.0 * std::max(v[SCAL_OBJ], 0.0)) / rep->norm_x[ll - 1] : 0.0;
+      rep->gflop[ll - 1] = (double)iters[ll - 1] *
+                           (4.0 * s.m * s.k * s.r + 4.0 * (s.m + s.k) * s.r * s.r) * 1e-9;
+      rep->total_gflop += rep->gflop[ll - 1];
+    }
+  }
+};
+
+static ntt_status check_decompose_args(ntt_plan_s* p, void* workspace, const float* A,
+                                       float* const* cores) {
+  if (!p) return fail(NTT_ERR_INVALID_ARG, "null plan");
+  if (!workspace) return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(NTT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (!A || !cores) return fail(NTT_ERR_INVALID_ARG, "null A or cores");
+  for (int i = 0; i < p->d; ++i)
+    if (!cores[i]) return fail(NTT_ERR_INVALID_ARG, "null core pointer");
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace, const float* A,
+                                    float* const* cores, const float* const* init_W,
+                                    const float* const* init_H, double* objective_trace,
+                                    ntt_report* report) {
+  ntt_status st = check_decompose_args(p, workspace, A, cores);
+  if (st != NTT_OK) return st;
+  const ntt_config& cfg = p->cfg;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!p->events_ready) {
+    for (auto& e : p->stage_ev) HIP_TRY(hipEventCreate(&e));
+    p->events_ready = true;
+  }
+  const bool profile = (cfg.flags & NTT_PROFILE) && report;
+  if (profile && (int64_t)p->prof_events.size() < 2 * (int64_t)cfg.max_iters) {
+    while (p->prof_events.size() < 2 * (size_t)cfg.max_iters) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      p->prof_events.push_back(e);
+    }
+  }
+  NttJob job;
+  st = job.start(p, s, workspace, A, cores, init_W, init_H, objective_trace, report != nullptr);
+  if (st != NTT_OK) return st;
+  const int d = p->d;
+  std::vector<double> pass_ms(d, 0.0);
+  while (!job.done) {
+    const int l = job.l;
+    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1)], s));
+    st = job.run_stage();
+    if (st != NTT_OK) return st;
+    HIP_TRY(hipEventRecord(p->stage_ev[2 * (l - 1) + 1], s));
+    if (profile && job.iters[l - 1] > 0) {
+      HIP_TRY(hipStreamSynchronize(s));
+      double sum = 0.0;
+      for (int t = 0; t < job.iters[l - 1]; ++t) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->prof_events[2 * t], p->prof_events[2 * t + 1]));
+        sum += ms;
+      }
+      pass_ms[l - 1] = sum / job.iters[l - 1];
+    }
+  }
+  std::vector<double> sc((size_t)SCAL_COUNT * (d - 1), 0.0);
+  if (report) HIP_TRY(job.fetch_scalars(sc.data()));
   HIP_TRY(hipStreamSynchronize(s));
   if (report) {
+    ntt_report rep;
+    job.fill_report(sc.data(), &rep);
     for (int l = 1; l < d; ++l) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, p->stage_ev[2 * (l - 1)], p->stage_ev[2 * (l - 1) + 1]));
       rep.ms[l - 1] = ms;
       rep.total_ms += ms;
-      rep.total_gflop += rep.gflop[l - 1];
+      rep.pass_ms[l - 1] = pass_ms[l - 1];
     }
     *report = rep;
   }
@@ -636,5 +746,173 @@ extern "C" ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_
   HIP_TRY(hipStreamSynchronize(s));
   if (!(tot[1] > 0.0)) return fail(NTT_ERR_ZERO_NORM, "||A||_F = 0");
   *rel_err = std::sqrt(tot[0] / tot[1]);
+  return NTT_OK;
+}
+
+// ------------------------------------------------------------------ batched mode (a9)
+// Independent decompositions of uneven shape and rank, advanced stage level by stage
+// level.  At each level, unfoldings small enough for one workgroup (m <= 256, k <= 64,
+// r <= 16) run all their iterations in grouped launches (one workgroup per problem,
+// read from a device work-list); the others replay their per-problem iteration graphs
+// on a small pool of streams so that they overlap on the device.  Problems never share
+// a reduction, so each result is the same as when decomposed alone.
+struct ntt_batch_s {
+  std::vector<ntt_plan_s*> plans;
+  std::vector<size_t> ws_off;
+  size_t list_off = 0, total = 0;
+  std::vector<hipStream_t> pool;
+  hipEvent_t ev_prep = nullptr;
+  std::vector<hipEvent_t> ev_done;
+  ~ntt_batch_s() {
+    for (auto* p : plans) delete p;
+    for (auto q : pool) (void)hipStreamDestroy(q);
+    if (ev_prep) (void)hipEventDestroy(ev_prep);
+    for (auto e : ev_done) (void)hipEventDestroy(e);
+  }
+};
+
+constexpr int kBatchStreams = 4;
+
+extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_batch_t* out) {
+  if (!out || !cfgs || count < 1) return fail(NTT_ERR_INVALID_ARG, "bad batch arguments");
+  *out = nullptr;
+  auto* b = new ntt_batch_s();
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    ntt_plan_t p = nullptr;
+    if (cfgs[i].flags & (NTT_RECORD_OBJECTIVE | NTT_PROFILE | NTT_VALIDATE_INPUT)) {
+      delete b;
+      return fail(NTT_ERR_INVALID_ARG, "batched mode takes no RECORD/PROFILE/VALIDATE flags");
+    }
+    ntt_status st = ntt_plan(&cfgs[i], &p);
+    if (st != NTT_OK) {
+      delete b;
+      return st;
+    }
+    b->plans.push_back(p);
+    b->ws_off.push_back(off);
+    off = align_up(off + p->total, 256);
+  }
+  b->list_off = off;
+  off = align_up(off + (size_t)count * sizeof(StageArgs), 256);
+  b->total = off;
+  *out = b;
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_batch_workspace(ntt_batch_t b, size_t* bytes) {
+  if (!b || !bytes) return fail(NTT_ERR_INVALID_ARG, "null batch or bytes");
+  *bytes = b->total;
+  return NTT_OK;
+}
+
+extern "C" void ntt_batch_destroy(ntt_batch_t b) { delete b; }
+
+extern "C" ntt_status ntt_decompose_batch(ntt_batch_t b, void* stream, void* workspace,
+                                          const float* const* A, float* const* const* cores,
+                                          ntt_report* reports) {
+  if (!b) return fail(NTT_ERR_INVALID_ARG, "null batch");
+  if (!workspace) return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(NTT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (!A || !cores) return fail(NTT_ERR_INVALID_ARG, "null A or cores");
+  const int n = (int)b->plans.size();
+  char* ws = reinterpret_cast<char*>(workspace);
+  hipStream_t main = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < n; ++i) {
+    ntt_status st = check_decompose_args(b->plans[i], ws + b->ws_off[i], A[i], cores ? cores[i] : nullptr);
+    if (st != NTT_OK) return st;
+  }
+  if (b->pool.empty()) {
+    for (int i = 0; i < kBatchStreams; ++i) {
+      hipStream_t q;
+      HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      b->pool.push_back(q);
+      hipEvent_t e;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->ev_done.push_back(e);
+    }
+    HIP_TRY(hipEventCreateWithFlags(&b->ev_prep, hipEventDisableTiming));
+  }
+  std::vector<NttJob> jobs(n);
+  int max_level = 0;
+  for (int i = 0; i < n; ++i) {
+    ntt_status st = jobs[i].start(b->plans[i], main, ws + b->ws_off[i], A[i], cores[i], nullptr,
+                                  nullptr, nullptr, reports != nullptr);
+    if (st != NTT_OK) return st;
+    max_level = std::max(max_level, b->plans[i]->d - 1);
+  }
+  StageArgs* list_dev = reinterpret_cast<StageArgs*>(ws + b->list_off);
+  std::vector<StageArgs> lists[3];
+  for (int level = 1; level <= max_level; ++level) {
+    std::vector<int> active;
+    for (int i = 0; i < n; ++i)
+      if (!jobs[i].done && jobs[i].l == level) active.push_back(i);
+    if (active.empty()) continue;
+    for (int i : active) {
+      jobs[i].c.s = main;
+      ntt_status st = jobs[i].prepare_stage(false);
+      if (st != NTT_OK) return st;
+    }
+    HIP_TRY(hipEventRecord(b->ev_prep, main));
+    // small unfoldings: grouped single-workgroup launches, all iterations
+    for (auto& v : lists) v.clear();
+    for (int i : active) {
+      NttJob& j = jobs[i];
+      if (!j.one_wg || j.p->cfg.max_iters < 1 || j.p->cfg.tol > 0.0) continue;
+      const Stage& s = j.st();
+      StageArgs sa{};
+      sa.X = j.X;
+      sa.W = j.W;
+      sa.H = j.H;
+      sa.m = (int)s.m;
+      sa.r = s.r;
+      sa.k = (int)s.k;
+      sa.iters = j.p->cfg.max_iters;
+      sa.eps = (float)j.p->cfg.eps;
+      const int ng = stage_1wg_ng(s.k);
+      lists[ng == 1 ? 0 : (ng == 2 ? 1 : 2)].push_back(sa);
+      j.t = j.p->cfg.max_iters;
+    }
+    size_t at = 0;
+    for (int g = 0; g < 3; ++g) {
+      if (lists[g].empty()) continue;
+      HIP_TRY(hipMemcpyAsync(list_dev + at, lists[g].data(), lists[g].size() * sizeof(StageArgs),
+                             hipMemcpyHostToDevice, main));
+      HIP_TRY(launch_stage_1wg_grouped(list_dev + at, (int)lists[g].size(), g == 0 ? 1 : (g == 1 ? 2 : 4), main));
+      at += lists[g].size();
+    }
+    // the rest: per-problem iteration graphs, spread over the stream pool
+    int slot = 0;
+    for (int i : active) {
+      NttJob& j = jobs[i];
+      if (j.t >= j.p->cfg.max_iters) continue;
+      hipStream_t q = b->pool[slot++ % kBatchStreams];
+      HIP_TRY(hipStreamWaitEvent(q, b->ev_prep, 0));
+      j.c.s = q;
+      bool sd = false;
+      ntt_status st = j.iterate(j.p->cfg.max_iters, &sd);
+      if (st != NTT_OK) return st;
+    }
+    for (int i : active) {
+      ntt_status st = jobs[i].finish_stage();
+      if (st != NTT_OK) return st;
+    }
+    for (int q = 0; q < kBatchStreams; ++q) {
+      HIP_TRY(hipEventRecord(b->ev_done[q], b->pool[q]));
+      HIP_TRY(hipStreamWaitEvent(main, b->ev_done[q], 0));
+    }
+  }
+  std::vector<std::vector<double>> sc(n);
+  if (reports) {
+    for (int i = 0; i < n; ++i) {
+      sc[i].assign((size_t)SCAL_COUNT * (b->plans[i]->d - 1), 0.0);
+      jobs[i].c.s = main;
+      HIP_TRY(jobs[i].fetch_scalars(sc[i].data()));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(main));
+  if (reports)
+    for (int i = 0; i < n; ++i) jobs[i].fill_report(sc[i].data(), &reports[i]);
   return NTT_OK;
 }

@@ -78,6 +78,8 @@ hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool upda
                          hipStream_t s);
 bool stage_1wg_ok(int64_t m, int64_t k, int r);
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
+int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)
+hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);

@@ -805,12 +805,11 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 #pragma unroll
   for (int blk = 0; blk < MBW; ++blk) xrow[blk] = (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
 
-  int par = 0;
-  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+  // loads of one 16-column group: this wave's X rows and the H tile (clamped addresses,
+  // out-of-range values zeroed where they could reach a result)
+  auto load_group = [&](int64_t g, float (&xr)[MBW][4], float (&hv)[NH][4]) {
     const int64_t j0 = g << 4;
-    const bool full = vec_ok && (j0 + 16 <= k);
-    float xr[MBW][4];
-    if (full) {
+    if (vec_ok && (j0 + 16 <= k)) {
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk) {
         const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
@@ -830,19 +829,34 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
           xr[blk][q] = (col < k && row0 + 16 * blk + a < m) ? v : 0.f;
         }
     }
-    float hv[NH][4];
-    {
-      const int64_t col = j0 + a;
-      const int64_t colc = min(col, k - 1);
+    const int64_t col = j0 + a;
+    const int64_t colc = min(col, k - 1);
 #pragma unroll
-      for (int h = 0; h < NH; ++h)
+    for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int c = 16 * h + 4 * b + kk;
-          const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
-          hv[h][kk] = (c < r && col < k) ? v : 0.f;
-        }
-    }
+      for (int kk = 0; kk < 4; ++kk) {
+        const int c = 16 * h + 4 * b + kk;
+        const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
+        hv[h][kk] = (c < r && col < k) ? v : 0.f;
+      }
+  };
+
+  float xn[MBW][4], hn_[NH][4];  // next group, loaded while the current one is processed
+  if ((int64_t)blockIdx.x < ngroups) load_group(blockIdx.x, xn, hn_);
+  int par = 0;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+    const int64_t j0 = g << 4;
+    const bool full = vec_ok && (j0 + 16 <= k);
+    float xr[MBW][4], hv[NH][4];
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xr[blk][q] = xn[blk][q];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hv[h][q] = hn_[h][q];
+    if (g + gridDim.x < ngroups) load_group(g + gridDim.x, xn, hn_);
     v4f nh[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) nh[h] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -998,7 +1012,22 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 // is local to each wave (W (H H^T) by MFMA), followed by W^T W summed over the waves.
 // All arithmetic is FP32 with FP32 accumulation; results are deterministic.
 template <int NG>
+__device__ __forceinline__ void stage_1wg_body(const StageArgs& s);
+
+template <int NG>
 __global__ __launch_bounds__(256) void k_stage_1wg(StageArgs s) {
+  stage_1wg_body<NG>(s);
+}
+
+// grouped launch: workgroup i runs the stage described by list[i] (uneven shapes)
+template <int NG>
+__global__ __launch_bounds__(256) void k_stage_1wg_grouped(const StageArgs* __restrict__ list) {
+  const StageArgs s = list[blockIdx.x];
+  stage_1wg_body<NG>(s);
+}
+
+template <int NG>
+__device__ __forceinline__ void stage_1wg_body(const StageArgs& s) {
   constexpr int MBW = 4, SX = 20, KC = 16 * NG;
   __shared__ __attribute__((aligned(16))) float sX[4][16 * SX];
   __shared__ __attribute__((aligned(16))) float sNH[2][4][256];
@@ -1732,13 +1761,25 @@ bool stage_1wg_ok(int64_t m, int64_t k, int r) { return m <= 256 && k <= 64 && r
 
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s) {
   if (!stage_1wg_ok(a.m, a.k, a.r) || a.iters <= 0) return hipErrorInvalidValue;
-  const int ng = (a.k + 15) / 16;
+  const int ng = stage_1wg_ng(a.k);
   if (ng == 1) k_stage_1wg<1><<<1, 256, 0, s>>>(a);
   else if (ng == 2) k_stage_1wg<2><<<1, 256, 0, s>>>(a);
   else k_stage_1wg<4><<<1, 256, 0, s>>>(a);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
+
+hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (ng == 1) k_stage_1wg_grouped<1><<<count, 256, 0, s>>>(list_dev);
+  else if (ng == 2) k_stage_1wg_grouped<2><<<count, 256, 0, s>>>(list_dev);
+  else if (ng == 4) k_stage_1wg_grouped<4><<<count, 256, 0, s>>>(list_dev);
+  else return hipErrorInvalidValue;
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+int stage_1wg_ng(int64_t k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
 
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s) {

@@ -36,7 +36,8 @@ NTT_PROFILE = 8
 EXPORTED = [
     "ntt_plan", "ntt_plan_workspace", "ntt_decompose", "ntt_tt_workspace", "ntt_reconstruct",
     "ntt_rel_error", "ntt_compression_ratio", "ntt_plan_destroy", "ntt_status_string",
-    "ntt_last_error", "ntt_version",
+    "ntt_last_error", "ntt_version", "ntt_batch_plan", "ntt_batch_workspace",
+    "ntt_decompose_batch", "ntt_batch_destroy",
 ]
 
 
@@ -132,6 +133,15 @@ def load(path: str = LIB_PATH):
     lib.ntt_last_error.restype = C.c_char_p
     lib.ntt_version.argtypes = []
     lib.ntt_version.restype = C.c_char_p
+    lib.ntt_batch_plan.argtypes = [C.c_int32, C.POINTER(NttConfig), C.POINTER(P)]
+    lib.ntt_batch_plan.restype = C.c_int
+    lib.ntt_batch_workspace.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.ntt_batch_workspace.restype = C.c_int
+    lib.ntt_decompose_batch.argtypes = [P, P, P, C.POINTER(P), C.POINTER(C.POINTER(P)),
+                                        C.POINTER(NttReport)]
+    lib.ntt_decompose_batch.restype = C.c_int
+    lib.ntt_batch_destroy.argtypes = [P]
+    lib.ntt_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -308,3 +318,87 @@ def rel_error(A, cores, workspace=None, stream=None) -> float:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     return ntt_rel_error(dims, ranks, A.data_ptr(), [c.data_ptr() for c in cores],
                          workspace.data_ptr(), nbytes, _stream_handle(torch, stream))
+
+
+# ------------------------------------------------------------------ batched mode
+class Batch:
+    """Owns an ntt_batch_t built from one config per problem."""
+
+    def __init__(self, problems, max_iters, eps=1e-12, precision=NTT_PREC_FP32,
+                 fp32_tail_iters=20, tol=0.0, check_every=10):
+        """problems: list of (dims, ranks, seed)."""
+        lib = load()
+        self.problems = [(list(map(int, dm)), list(map(int, rk)), int(sd)) for dm, rk, sd in problems]
+        self._keep = []
+        cfgs = (NttConfig * len(self.problems))()
+        for i, (dm, rk, sd) in enumerate(self.problems):
+            a, b = _i64(dm), _i64(rk)
+            self._keep += [a, b]
+            cfgs[i] = NttConfig(len(dm), C.cast(a, C.POINTER(C.c_int64)), C.cast(b, C.POINTER(C.c_int64)),
+                                int(max_iters), float(tol), int(check_every), float(eps),
+                                sd & ((1 << 64) - 1), int(precision), int(fp32_tail_iters), 0)
+        self.handle = C.c_void_p()
+        _check(lib.ntt_batch_plan(len(self.problems), cfgs, C.byref(self.handle)), "ntt_batch_plan")
+        nbytes = C.c_size_t()
+        _check(lib.ntt_batch_workspace(self.handle, C.byref(nbytes)), "ntt_batch_workspace")
+        self.workspace_bytes = int(nbytes.value)
+        self.eff = [O_effective(dm, rk) for dm, rk, _ in self.problems]
+
+    def close(self):
+        if self.handle:
+            load().ntt_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def O_effective(dims, ranks):
+    """Effective ranks after the clamp rule of ntt_plan (host arithmetic, for allocation)."""
+    out = [1]
+    for l in range(1, len(dims)):
+        m = out[-1] * dims[l - 1]
+        k = 1
+        for n in dims[l:]:
+            k *= n
+        out.append(min(ranks[l], m, k))
+    out.append(1)
+    return out
+
+
+def ntt_decompose_batch(batch: Batch, stream: int, workspace: int, A_ptrs, core_ptrs,
+                        want_reports=True):
+    lib = load()
+    n = len(batch.problems)
+    reps = (NttReport * n)() if want_reports else None
+    rows = [_ptrs(cp) for cp in core_ptrs]
+    arr = (C.POINTER(C.c_void_p) * n)(*[C.cast(r_, C.POINTER(C.c_void_p)) for r_ in rows])
+    st = lib.ntt_decompose_batch(batch.handle, C.c_void_p(stream), C.c_void_p(workspace),
+                                 _ptrs(A_ptrs), arr, reps)
+    _check(st, "ntt_decompose_batch")
+    if not want_reports:
+        return None
+    return [reps[i].to_dict(len(batch.problems[i][0])) for i in range(n)]
+
+
+def decompose_batch(tensors, ranks_list, max_iters, seeds, *, eps=1e-12, precision=NTT_PREC_FP32,
+                    fp32_tail_iters=20, batch=None, workspace=None, cores=None, stream=None,
+                    want_reports=True):
+    """Decompose a list of float32 CUDA tensors in one batched call."""
+    import torch
+    if batch is None:
+        batch = Batch([(list(t.shape), rk, sd) for t, rk, sd in zip(tensors, ranks_list, seeds)],
+                      max_iters, eps=eps, precision=precision, fp32_tail_iters=fp32_tail_iters)
+    dev = tensors[0].device
+    if workspace is None:
+        workspace = torch.empty(max(batch.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+    if cores is None:
+        cores = [[torch.empty((e[k], t.shape[k], e[k + 1]), dtype=torch.float32, device=dev)
+                  for k in range(t.dim())] for t, e in zip(tensors, batch.eff)]
+    reps = ntt_decompose_batch(batch, _stream_handle(torch, stream), workspace.data_ptr(),
+                               [t.data_ptr() for t in tensors],
+                               [[c.data_ptr() for c in cs] for cs in cores], want_reports)
+    return cores, reps, batch

@@ -129,3 +129,14 @@ def test_workspace_scales_with_the_problem():
     # the 32^5 sweep holds H_1 (8 x 32^4 floats) in the workspace
     assert big >= 8 * 32 ** 4 * 4
     assert small < big
+
+
+def test_batch_plan_validation_and_workspace():
+    b = ntt.Batch([((4, 5, 6), (1, 2, 3, 1), 1), ((8, 8), (1, 3, 1), 2)], 10)
+    single = sum(ntt.Plan(dm, rk, 10).workspace()[0] for dm, rk, _ in b.problems)
+    assert b.workspace_bytes >= single
+    assert b.eff == [[1, 2, 3, 1], [1, 3, 1]]
+    with pytest.raises(ntt.NttError):
+        ntt.Batch([((4, 5, 6), (1, 2, 3, 2), 1)], 10)  # r_d != 1
+    lib = ntt.load()
+    assert lib.ntt_batch_plan(0, None, None) == ntt.NTT_ERR_INVALID_ARG

@@ -340,3 +340,55 @@ def test_bf16_mode_with_all_iterations_fp32_equals_fp32_mode():
     b = ntt.decompose(Ad, w.target_ranks, 50, seed=1)
     for x, y in zip(a.cores, b.cores):
         assert torch.equal(x, y)
+
+
+# ------------------------------------------------------------------ a9: batched mode
+def _mix_problems():
+    # uneven shapes and ranks: grouped single-workgroup stages and stream-pool stages
+    return [((6, 7, 5), (1, 3, 4, 1), 11), ((16, 16, 16), (1, 4, 4, 1), 1),
+            ((9, 20, 8, 6), (1, 5, 6, 3, 1), 5), ((30, 40, 12), (1, 12, 9, 1), 8),
+            ((12, 10, 11, 9, 8), (1, 4, 7, 5, 2, 1), 21), ((64, 33, 50), (1, 10, 12, 1), 3),
+            ((8, 8, 8), (1, 2, 2, 1), 13), ((40, 9, 17, 23), (1, 8, 11, 6, 1), 17)]
+
+
+def test_batched_results_equal_standalone_results_bitwise():
+    say("case: batch of 8 uneven problems vs ntt_decompose one by one")
+    probs = _mix_problems()
+    tensors = [dev(S.contract_cores(S.random_cores(dm, rk, seed=sd))) for dm, rk, sd in probs]
+    T = 60
+    cores, reps, _ = ntt.decompose_batch(tensors, [rk for _, rk, _ in probs], T,
+                                         [sd for _, _, sd in probs])
+    for (dm, rk, sd), A, cs, rep in zip(probs, tensors, cores, reps):
+        alone = ntt.decompose(A, rk, T, seed=sd)
+        for x, y in zip(cs, alone.cores):
+            assert torch.equal(x, y), (dm, rk)
+        assert rep["iters"] == [T] * (len(dm) - 1)
+        assert rep["objective"] == pytest.approx(alone.report["objective"], rel=1e-12)
+
+
+def test_batched_results_match_oracle():
+    say("case: batch of 8 uneven problems vs the oracle")
+    probs = _mix_problems()
+    host_t = [S.contract_cores(S.random_cores(dm, rk, seed=sd)) for dm, rk, sd in probs]
+    T = 40
+    cores, reps, _ = ntt.decompose_batch([dev(a) for a in host_t], [rk for _, rk, _ in probs], T,
+                                         [sd for _, _, sd in probs])
+    for (dm, rk, sd), A, cs in zip(probs, host_t, cores):
+        ref = O.ntt_decompose(A, rk, T, seed=sd)
+        for cg, co in zip(cs, ref["cores"]):
+            assert rel(host(cg), co) <= TOL, (dm, rk)
+
+
+def test_batched_bf16_mode_runs_and_matches_error_bar():
+    say("case: batch in BF16 mode")
+    probs = [((24, 30, 20, 36), (1, 6, 8, 5, 1), 7), ((40, 9, 17, 23), (1, 8, 11, 6, 1), 17)]
+    host_t = [S.contract_cores(S.random_cores(dm, rk, seed=sd)) for dm, rk, sd in probs]
+    T = 120
+    cores, _, _ = ntt.decompose_batch([dev(a) for a in host_t], [rk for _, rk, _ in probs], T,
+                                      [sd for _, _, sd in probs],
+                                      precision=ntt.NTT_PREC_BF16_MIXED, fp32_tail_iters=20)
+    for (dm, rk, sd), A, cs in zip(probs, host_t, cores):
+        ref = O.ntt_decompose(A, rk, T, seed=sd)
+        e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+        e_bf = ntt.rel_error(dev(A), cs)
+        assert abs(e_bf - e_orc) <= BF16_BAR
