@@ -181,6 +181,70 @@ ntt_status ntt_decompose_batch(ntt_batch_t batch, void* stream, void* workspace,
 
 void ntt_batch_destroy(ntt_batch_t batch);
 
+/* ---- Serving: a persistent request engine with continuous batching.
+ * Not a step of the paper: a serving mode over the same per-problem sweep.
+ * The caller gives the server a device arena (the HBM budget).  Requests (host input,
+ * ranks, iteration count) wait in a FIFO queue.  Each ntt_server_tick (non-blocking)
+ * admits queued requests while a slot is free and the request's input + cores +
+ * workspace fit in the arena (first-fit), starts the input copy on a copy stream, and
+ * advances every admitted request whose previous block of work has finished by
+ * iters_per_tick MU iterations; small unfoldings of all such requests go in one grouped
+ * launch.  Factors stay on the device; results stay in the arena until released.  A
+ * request's result does not depend on which other requests share the device. */
+typedef struct ntt_server_s* ntt_server_t;
+
+typedef struct {
+  void* arena;            /* device, 256-byte aligned, owned by the caller */
+  size_t arena_bytes;     /* HBM budget the server may use */
+  int32_t max_slots;      /* requests admitted at once, 1..64 */
+  int32_t iters_per_tick; /* MU iterations a request advances per tick (>= 1) */
+} ntt_server_config;
+
+typedef struct {
+  int32_t d;
+  const int64_t* dims;    /* host, read during ntt_server_submit */
+  const int64_t* ranks;   /* host, read during ntt_server_submit */
+  int32_t max_iters;
+  double eps;
+  uint64_t seed;
+  int32_t precision;
+  int32_t fp32_tail_iters;
+  const float* host_A;    /* host input (pinned for an overlapped copy); must stay valid
+                             until the request is running */
+} ntt_request;
+
+enum {
+  NTT_REQ_QUEUED = 0,
+  NTT_REQ_RUNNING = 1,
+  NTT_REQ_DONE = 2,
+  NTT_REQ_REJECTED = 3,   /* needs more than the whole arena */
+  NTT_REQ_CANCELLED = 4
+};
+
+typedef struct {
+  int64_t id;
+  int32_t state;
+  int32_t d;
+  double t_submit, t_admit, t_start, t_finish; /* seconds since the server was created */
+  size_t device_bytes;                         /* input + cores + workspace in the arena */
+  double gflop;                                /* algorithmic GFLOP of the request */
+  int64_t eff_ranks[NTT_MAX_DIMS + 1];
+} ntt_request_info;
+
+ntt_status ntt_server_create(const ntt_server_config* cfg, ntt_server_t* out);
+/* Queue a request (host only); *id identifies it. */
+ntt_status ntt_server_submit(ntt_server_t server, const ntt_request* req, int64_t* id);
+/* One scheduler step (never waits for the device); reports running and queued counts. */
+ntt_status ntt_server_tick(ntt_server_t server, int32_t* n_active, int32_t* n_queued);
+ntt_status ntt_server_info(ntt_server_t server, int64_t id, ntt_request_info* info);
+/* Device pointers of a finished request's d cores (valid until ntt_server_release). */
+ntt_status ntt_server_cores(ntt_server_t server, int64_t id, float** core_ptrs);
+/* Free a request's arena memory; cancels it if it is queued or running. */
+ntt_status ntt_server_release(ntt_server_t server, int64_t id);
+/* Free bytes left in the arena. */
+ntt_status ntt_server_free_bytes(ntt_server_t server, size_t* bytes);
+void ntt_server_destroy(ntt_server_t server);
+
 void ntt_plan_destroy(ntt_plan_t plan);
 const char* ntt_status_string(ntt_status s);
 const char* ntt_last_error(void);

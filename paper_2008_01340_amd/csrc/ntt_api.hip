@@ -12,7 +12,11 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -914,5 +918,411 @@ extern "C" ntt_status ntt_decompose_batch(ntt_batch_t b, void* stream, void* wor
   HIP_TRY(hipStreamSynchronize(main));
   if (reports)
     for (int i = 0; i < n; ++i) jobs[i].fill_report(sc[i].data(), &reports[i]);
+  return NTT_OK;
+}
+
+// ------------------------------------------------------------------ serving (a10)
+// A persistent request engine with continuous batching.  Requests wait in a FIFO queue;
+// a scheduler tick (non-blocking) admits the head request when a slot is free and its
+// input, cores and workspace fit in the HBM arena (first-fit), copies its input on a
+// copy stream, and advances every admitted request whose previous block of work has
+// finished by `iters_per_tick` MU iterations: small unfoldings of all such requests in
+// one grouped single-workgroup launch, the rest as per-request graph replays on slot
+// streams.  Factors stay on the device between ticks and after completion, until the
+// client releases the request.  Each request's arithmetic is independent of the mix.
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, bytes), sorted by offset
+  void init(void* b, size_t n) {
+    base = reinterpret_cast<char*>(b);
+    size = n;
+    free_list.assign(1, {0, n});
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = align_up(std::max<size_t>(n, 256), 256);
+    for (size_t i = 0; i < free_list.size(); ++i) {
+      if (free_list[i].second >= n) {
+        *off = free_list[i].first;
+        free_list[i].first += n;
+        free_list[i].second -= n;
+        if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align_up(std::max<size_t>(n, 256), 256);
+    auto it = free_list.begin();
+    while (it != free_list.end() && it->first < off) ++it;
+    it = free_list.insert(it, {off, n});
+    // merge with the next and the previous ranges
+    if (it + 1 != free_list.end() && it->first + it->second == (it + 1)->first) {
+      it->second += (it + 1)->second;
+      free_list.erase(it + 1);
+    }
+    if (it != free_list.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+      (it - 1)->second += it->second;
+      free_list.erase(it);
+    }
+  }
+};
+
+struct Request {
+  int64_t id = 0;
+  int state = NTT_REQ_QUEUED;
+  ntt_plan_s* plan = nullptr;
+  std::vector<int64_t> dims;
+  const float* host_A = nullptr;
+  size_t bytes_A = 0, bytes_cores = 0, bytes_ws = 0;
+  size_t off_c = 0, total_c = 0;  // cores: held until the client releases the request
+  size_t off_w = 0, total_w = 0;  // input + workspace: freed when the request finishes
+  std::vector<float*> cores;
+  float* A = nullptr;
+  NttJob job;
+  int slot = -1;
+  hipEvent_t ev = nullptr;  // completion of the last block of work issued for this request
+  bool started = false;
+  double t_submit = 0, t_admit = 0, t_start = 0, t_finish = 0;
+  int64_t iters_total = 0;
+  double gflop = 0.0;
+};
+
+}  // namespace
+
+struct ntt_server_s {
+  ntt_server_config cfg;
+  Arena arena;
+  std::vector<hipStream_t> streams;  // slot streams, then the copy stream, then the grouped stream
+  hipStream_t copy_stream = nullptr, group_stream = nullptr;
+  hipEvent_t group_ev = nullptr;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;  // admitted, not yet released
+  std::map<int64_t, Request*> all;
+  std::vector<int> slot_used;
+  int64_t next_id = 1;
+  double t0 = 0;
+  std::vector<StageArgs> list_host;
+  ~ntt_server_s() {
+    for (auto& kv : all) {
+      if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+      delete kv.second->plan;
+      delete kv.second;
+    }
+    for (auto q : streams) (void)hipStreamDestroy(q);
+    if (group_ev) (void)hipEventDestroy(group_ev);
+  }
+};
+
+// input + workspace and the slot go back when a request finishes; cores on release
+static void server_release_work(ntt_server_s* sv, Request* q) {
+  if (q->total_w) sv->arena.release(q->off_w, q->total_w);
+  q->total_w = 0;
+  if (q->slot >= 0) sv->slot_used[q->slot] = 0;
+  q->slot = -1;
+}
+
+static void server_release_memory(ntt_server_s* sv, Request* q) {
+  server_release_work(sv, q);
+  if (q->total_c) sv->arena.release(q->off_c, q->total_c);
+  q->total_c = 0;
+}
+
+extern "C" ntt_status ntt_server_create(const ntt_server_config* cfg, ntt_server_t* out) {
+  if (!cfg || !out) return fail(NTT_ERR_INVALID_ARG, "null config or output");
+  *out = nullptr;
+  if (!cfg->arena || cfg->arena_bytes < 4096 || cfg->max_slots < 1 || cfg->max_slots > NTT_STAGE_LIST ||
+      cfg->iters_per_tick < 1)
+    return fail(NTT_ERR_INVALID_ARG, "bad server config");
+  if ((reinterpret_cast<uintptr_t>(cfg->arena) & 255) != 0)
+    return fail(NTT_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+  auto* sv = new ntt_server_s();
+  sv->cfg = *cfg;
+  sv->arena.init(cfg->arena, cfg->arena_bytes);
+  const int nstreams = std::min(cfg->max_slots, 8);
+  for (int i = 0; i < nstreams + 2; ++i) {
+    hipStream_t q;
+    hipError_t e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete sv;
+      return fail(NTT_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    sv->streams.push_back(q);
+  }
+  sv->copy_stream = sv->streams[nstreams];
+  sv->group_stream = sv->streams[nstreams + 1];
+  if (hipEventCreateWithFlags(&sv->group_ev, hipEventDisableTiming) != hipSuccess) {
+    delete sv;
+    return fail(NTT_ERR_DEVICE, "hipEventCreate failed");
+  }
+  sv->slot_used.assign(cfg->max_slots, 0);
+  sv->t0 = now_s();
+  *out = sv;
+  return NTT_OK;
+}
+
+extern "C" void ntt_server_destroy(ntt_server_t sv) {
+  if (!sv) return;
+  for (auto q : sv->streams) (void)hipStreamSynchronize(q);
+  delete sv;
+}
+
+extern "C" ntt_status ntt_server_submit(ntt_server_t sv, const ntt_request* rq, int64_t* id) {
+  if (!sv || !rq || !id) return fail(NTT_ERR_INVALID_ARG, "null server, request or id");
+  if (!rq->host_A) return fail(NTT_ERR_INVALID_ARG, "null input");
+  ntt_config c{};
+  c.d = rq->d;
+  c.dims = rq->dims;
+  c.ranks = rq->ranks;
+  c.max_iters = rq->max_iters;
+  c.tol = 0.0;
+  c.check_every = 10;
+  c.eps = rq->eps;
+  c.seed = rq->seed;
+  c.precision = rq->precision;
+  c.fp32_tail_iters = rq->fp32_tail_iters;
+  c.flags = 0;
+  ntt_plan_t p = nullptr;
+  ntt_status st = ntt_plan(&c, &p);
+  if (st != NTT_OK) return st;
+  auto* q = new Request();
+  q->id = sv->next_id++;
+  q->plan = p;
+  q->dims.assign(rq->dims, rq->dims + rq->d);
+  q->host_A = rq->host_A;
+  int64_t n = 1;
+  for (int i = 0; i < rq->d; ++i) n *= rq->dims[i];
+  q->bytes_A = align_up((size_t)n * sizeof(float), 256);
+  size_t cb = 0;
+  for (int i = 0; i < rq->d; ++i)
+    cb += align_up((size_t)p->eff[i] * (size_t)p->dims[i] * (size_t)p->eff[i + 1] * sizeof(float), 256);
+  q->bytes_cores = cb;
+  q->bytes_ws = align_up(p->total, 256);
+  q->t_submit = now_s() - sv->t0;
+  for (int l = 1; l < p->d; ++l) {
+    const Stage& s = p->st[l - 1];
+    q->iters_total += c.max_iters;
+    q->gflop += (double)c.max_iters * (4.0 * s.m * s.k * s.r + 4.0 * (s.m + s.k) * s.r * s.r) * 1e-9;
+  }
+  if (q->bytes_A + q->bytes_cores + q->bytes_ws > sv->arena.size) q->state = NTT_REQ_REJECTED;
+  else sv->queue.push_back(q);
+  sv->all[q->id] = q;
+  *id = q->id;
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_server_tick(ntt_server_t sv, int32_t* n_active, int32_t* n_queued) {
+  if (!sv) return fail(NTT_ERR_INVALID_ARG, "null server");
+  const int K = sv->cfg.iters_per_tick;
+  // 1. admission: FIFO while a slot is free and the head request fits in the arena
+  while (!sv->queue.empty()) {
+    Request* q = sv->queue.front();
+    int slot = -1;
+    for (int i = 0; i < (int)sv->slot_used.size(); ++i)
+      if (!sv->slot_used[i]) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) break;
+    size_t off_c = 0, off_w = 0;
+    if (!sv->arena.alloc(q->bytes_cores, &off_c)) break;
+    if (!sv->arena.alloc(q->bytes_A + q->bytes_ws, &off_w)) {
+      sv->arena.release(off_c, q->bytes_cores);
+      break;
+    }
+    sv->queue.pop_front();
+    q->off_c = off_c;
+    q->total_c = q->bytes_cores;
+    q->off_w = off_w;
+    q->total_w = q->bytes_A + q->bytes_ws;
+    q->slot = slot;
+    sv->slot_used[slot] = 1;
+    char* base = sv->arena.base + off_w;
+    q->A = reinterpret_cast<float*>(base);
+    char* cp = sv->arena.base + off_c;
+    q->cores.clear();
+    for (int i = 0; i < q->plan->d; ++i) {
+      q->cores.push_back(reinterpret_cast<float*>(cp));
+      cp += align_up((size_t)q->plan->eff[i] * (size_t)q->plan->dims[i] * (size_t)q->plan->eff[i + 1] *
+                         sizeof(float), 256);
+    }
+    char* ws = base + q->bytes_A;
+    int64_t n = 1;
+    for (auto v : q->dims) n *= v;
+    hipStream_t qs = sv->streams[slot % (sv->streams.size() - 2)];
+    if (!q->ev) HIP_TRY(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
+    HIP_TRY(hipMemcpyAsync(q->A, q->host_A, (size_t)n * sizeof(float), hipMemcpyHostToDevice,
+                           sv->copy_stream));
+    HIP_TRY(hipEventRecord(q->ev, sv->copy_stream));
+    HIP_TRY(hipStreamWaitEvent(qs, q->ev, 0));
+    ntt_status st = q->job.start(q->plan, qs, ws, q->A, q->cores.data(), nullptr, nullptr, nullptr,
+                                 true);
+    if (st != NTT_OK) return st;
+    HIP_TRY(hipEventRecord(q->ev, qs));
+    q->state = NTT_REQ_RUNNING;
+    q->t_admit = now_s() - sv->t0;
+    sv->active.push_back(q);
+  }
+  // 2. advance every running request whose previous block has completed
+  sv->list_host.clear();
+  std::vector<Request*> grouped;
+  for (Request* q : sv->active) {
+    if (q->state != NTT_REQ_RUNNING) continue;
+    const hipError_t qe = hipEventQuery(q->ev);
+    if (qe == hipErrorNotReady) continue;
+    if (qe != hipSuccess) return fail(NTT_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(qe));
+    NttJob& j = q->job;
+    if (j.done) {
+      q->state = NTT_REQ_DONE;
+      q->t_finish = now_s() - sv->t0;
+      server_release_work(sv, q);  // the cores stay until the client releases them
+      continue;
+    }
+    if (!q->started) {
+      q->started = true;
+      q->t_start = now_s() - sv->t0;
+    }
+    if (!j.prepared) {
+      ntt_status st = j.prepare_stage(false);
+      if (st != NTT_OK) return st;
+    }
+    const int budget = std::min(K, j.p->cfg.max_iters - j.t);
+    if (j.one_wg && budget > 0) {
+      const Stage& s = j.st();
+      StageArgs sa{};
+      sa.X = j.X;
+      sa.W = j.W;
+      sa.H = j.H;
+      sa.m = (int)s.m;
+      sa.r = s.r;
+      sa.k = (int)s.k;
+      sa.iters = budget;
+      sa.eps = (float)j.p->cfg.eps;
+      sv->list_host.push_back(sa);
+      grouped.push_back(q);
+      j.t += budget;
+      HIP_TRY(hipEventRecord(q->ev, j.c.s));  // the grouped launch waits for this stream
+    } else {
+      bool sd = false;
+      if (budget > 0) {
+        ntt_status st = j.iterate(budget, &sd);
+        if (st != NTT_OK) return st;
+      }
+      if (j.t >= j.p->cfg.max_iters) {
+        ntt_status st = j.finish_stage();
+        if (st != NTT_OK) return st;
+      }
+      HIP_TRY(hipEventRecord(q->ev, j.c.s));
+    }
+  }
+  if (!grouped.empty()) {
+    // one grouped launch per register class for the small stages of all requests; the
+    // work-list travels as a kernel argument, so nothing on the host outlives the call
+    for (Request* q : grouped) HIP_TRY(hipStreamWaitEvent(sv->group_stream, q->ev, 0));
+    StageList lists[3];
+    for (auto& L : lists) L.count = 0;
+    for (size_t i = 0; i < grouped.size(); ++i) {
+      const int ng = stage_1wg_ng(sv->list_host[i].k);
+      StageList& L = lists[ng == 1 ? 0 : (ng == 2 ? 1 : 2)];
+      L.a[L.count++] = sv->list_host[i];
+    }
+    for (int c = 0; c < 3; ++c)
+      HIP_TRY(launch_stage_1wg_list(lists[c], c == 0 ? 1 : (c == 1 ? 2 : 4), sv->group_stream));
+    HIP_TRY(hipEventRecord(sv->group_ev, sv->group_stream));
+    for (Request* q : grouped) {
+      NttJob& j = q->job;
+      HIP_TRY(hipStreamWaitEvent(j.c.s, sv->group_ev, 0));
+      if (j.t >= j.p->cfg.max_iters) {
+        ntt_status st = j.finish_stage();
+        if (st != NTT_OK) return st;
+      }
+      HIP_TRY(hipEventRecord(q->ev, j.c.s));
+    }
+  }
+  sv->active.erase(std::remove_if(sv->active.begin(), sv->active.end(),
+                                  [](Request* q) { return q->state != NTT_REQ_RUNNING; }),
+                   sv->active.end());
+  int na = (int)sv->active.size();
+  if (n_active) *n_active = na;
+  if (n_queued) *n_queued = (int32_t)sv->queue.size();
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_server_info(ntt_server_t sv, int64_t id, ntt_request_info* info) {
+  if (!sv || !info) return fail(NTT_ERR_INVALID_ARG, "null server or info");
+  auto it = sv->all.find(id);
+  if (it == sv->all.end()) return fail(NTT_ERR_INVALID_ARG, "unknown request id");
+  const Request* q = it->second;
+  memset(info, 0, sizeof(*info));
+  info->id = q->id;
+  info->state = q->state;
+  info->t_submit = q->t_submit;
+  info->t_admit = q->t_admit;
+  info->t_start = q->t_start;
+  info->t_finish = q->t_finish;
+  info->device_bytes = q->bytes_A + q->bytes_cores + q->bytes_ws;
+  info->gflop = q->gflop;
+  info->d = q->plan->d;
+  for (int i = 0; i <= q->plan->d; ++i) info->eff_ranks[i] = q->plan->eff[i];
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_server_cores(ntt_server_t sv, int64_t id, float** core_ptrs) {
+  if (!sv || !core_ptrs) return fail(NTT_ERR_INVALID_ARG, "null server or output");
+  auto it = sv->all.find(id);
+  if (it == sv->all.end()) return fail(NTT_ERR_INVALID_ARG, "unknown request id");
+  const Request* q = it->second;
+  if (q->state != NTT_REQ_DONE) return fail(NTT_ERR_INVALID_ARG, "request not finished");
+  for (int i = 0; i < q->plan->d; ++i) core_ptrs[i] = q->cores[i];
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_server_release(ntt_server_t sv, int64_t id) {
+  if (!sv) return fail(NTT_ERR_INVALID_ARG, "null server");
+  auto it = sv->all.find(id);
+  if (it == sv->all.end()) return fail(NTT_ERR_INVALID_ARG, "unknown request id");
+  Request* q = it->second;
+  if (q->state == NTT_REQ_RUNNING) {
+    // cancellation: wait for the work already issued for it, then drop it
+    if (q->ev) HIP_TRY(hipEventSynchronize(q->ev));
+    HIP_TRY(hipStreamSynchronize(sv->group_stream));
+    HIP_TRY(hipStreamSynchronize(sv->streams[q->slot % (sv->streams.size() - 2)]));
+    q->state = NTT_REQ_CANCELLED;
+  }
+  if (q->state == NTT_REQ_QUEUED) {
+    for (auto qi = sv->queue.begin(); qi != sv->queue.end(); ++qi)
+      if (*qi == q) {
+        sv->queue.erase(qi);
+        break;
+      }
+    q->state = NTT_REQ_CANCELLED;
+  }
+  server_release_memory(sv, q);
+  for (auto ai = sv->active.begin(); ai != sv->active.end(); ++ai)
+    if (*ai == q) {
+      sv->active.erase(ai);
+      break;
+    }
+  if (q->ev) (void)hipEventDestroy(q->ev);
+  q->ev = nullptr;
+  delete q->plan;
+  q->plan = nullptr;
+  sv->all.erase(it);
+  delete q;
+  return NTT_OK;
+}
+
+extern "C" ntt_status ntt_server_free_bytes(ntt_server_t sv, size_t* bytes) {
+  if (!sv || !bytes) return fail(NTT_ERR_INVALID_ARG, "null server or bytes");
+  size_t f = 0;
+  for (auto& r : sv->arena.free_list) f += r.second;
+  *bytes = f;
   return NTT_OK;
 }

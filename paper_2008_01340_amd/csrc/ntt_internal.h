@@ -52,6 +52,14 @@ struct StageArgs {
   float eps;
 };
 
+// Work-list of up to NTT_STAGE_LIST small stages passed by value as a kernel argument.
+#define NTT_STAGE_LIST 64
+struct StageList {
+  int count;
+  StageArgs a[NTT_STAGE_LIST];
+};
+static_assert(sizeof(StageList) <= 4096, "work-list must fit the kernel argument segment");
+
 // TT expansion (Eq.(2)) over the rows of the (n_1...n_{d-1}) x n_d matrix.
 struct TTArgs {
   int d;
@@ -80,6 +88,7 @@ bool stage_1wg_ok(int64_t m, int64_t k, int r);
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
 int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)
 hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s);
+hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);

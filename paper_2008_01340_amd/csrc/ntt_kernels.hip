@@ -1026,6 +1026,13 @@ __global__ __launch_bounds__(256) void k_stage_1wg_grouped(const StageArgs* __re
   stage_1wg_body<NG>(s);
 }
 
+// grouped launch with the work-list passed by value (at most NTT_STAGE_LIST entries)
+template <int NG>
+__global__ __launch_bounds__(256) void k_stage_1wg_list(StageList L) {
+  const StageArgs s = L.a[blockIdx.x];
+  stage_1wg_body<NG>(s);
+}
+
 template <int NG>
 __device__ __forceinline__ void stage_1wg_body(const StageArgs& s) {
   constexpr int MBW = 4, SX = 20, KC = 16 * NG;
@@ -1774,6 +1781,17 @@ hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng
   if (ng == 1) k_stage_1wg_grouped<1><<<count, 256, 0, s>>>(list_dev);
   else if (ng == 2) k_stage_1wg_grouped<2><<<count, 256, 0, s>>>(list_dev);
   else if (ng == 4) k_stage_1wg_grouped<4><<<count, 256, 0, s>>>(list_dev);
+  else return hipErrorInvalidValue;
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s) {
+  if (L.count <= 0) return hipSuccess;
+  if (L.count > NTT_STAGE_LIST) return hipErrorInvalidValue;
+  if (ng == 1) k_stage_1wg_list<1><<<L.count, 256, 0, s>>>(L);
+  else if (ng == 2) k_stage_1wg_list<2><<<L.count, 256, 0, s>>>(L);
+  else if (ng == 4) k_stage_1wg_list<4><<<L.count, 256, 0, s>>>(L);
   else return hipErrorInvalidValue;
   NTT_CHECK_LAUNCH();
   return hipSuccess;

@@ -37,8 +37,12 @@ EXPORTED = [
     "ntt_plan", "ntt_plan_workspace", "ntt_decompose", "ntt_tt_workspace", "ntt_reconstruct",
     "ntt_rel_error", "ntt_compression_ratio", "ntt_plan_destroy", "ntt_status_string",
     "ntt_last_error", "ntt_version", "ntt_batch_plan", "ntt_batch_workspace",
-    "ntt_decompose_batch", "ntt_batch_destroy",
+    "ntt_decompose_batch", "ntt_batch_destroy", "ntt_server_create", "ntt_server_submit",
+    "ntt_server_tick", "ntt_server_info", "ntt_server_cores", "ntt_server_release",
+    "ntt_server_free_bytes", "ntt_server_destroy",
 ]
+
+NTT_REQ_QUEUED, NTT_REQ_RUNNING, NTT_REQ_DONE, NTT_REQ_REJECTED, NTT_REQ_CANCELLED = range(5)
 
 
 class NttConfig(C.Structure):
@@ -87,6 +91,24 @@ class NttReport(C.Structure):
             "total_gflop": self.total_gflop,
             "compression_ratio": self.compression_ratio,
         }
+
+
+class NttServerConfig(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("iters_per_tick", C.c_int32)]
+
+
+class NttRequest(C.Structure):
+    _fields_ = [("d", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("ranks", C.POINTER(C.c_int64)),
+                ("max_iters", C.c_int32), ("eps", C.c_double), ("seed", C.c_uint64),
+                ("precision", C.c_int32), ("fp32_tail_iters", C.c_int32), ("host_A", C.c_void_p)]
+
+
+class NttRequestInfo(C.Structure):
+    _fields_ = [("id", C.c_int64), ("state", C.c_int32), ("d", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double), ("t_finish", C.c_double),
+                ("device_bytes", C.c_size_t), ("gflop", C.c_double),
+                ("eff_ranks", C.c_int64 * (NTT_MAX_DIMS + 1))]
 
 
 class NttError(RuntimeError):
@@ -142,6 +164,22 @@ def load(path: str = LIB_PATH):
     lib.ntt_decompose_batch.restype = C.c_int
     lib.ntt_batch_destroy.argtypes = [P]
     lib.ntt_batch_destroy.restype = None
+    lib.ntt_server_create.argtypes = [C.POINTER(NttServerConfig), C.POINTER(P)]
+    lib.ntt_server_create.restype = C.c_int
+    lib.ntt_server_submit.argtypes = [P, C.POINTER(NttRequest), C.POINTER(C.c_int64)]
+    lib.ntt_server_submit.restype = C.c_int
+    lib.ntt_server_tick.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.ntt_server_tick.restype = C.c_int
+    lib.ntt_server_info.argtypes = [P, C.c_int64, C.POINTER(NttRequestInfo)]
+    lib.ntt_server_info.restype = C.c_int
+    lib.ntt_server_cores.argtypes = [P, C.c_int64, C.POINTER(C.c_void_p)]
+    lib.ntt_server_cores.restype = C.c_int
+    lib.ntt_server_release.argtypes = [P, C.c_int64]
+    lib.ntt_server_release.restype = C.c_int
+    lib.ntt_server_free_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.ntt_server_free_bytes.restype = C.c_int
+    lib.ntt_server_destroy.argtypes = [P]
+    lib.ntt_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -402,3 +440,79 @@ def decompose_batch(tensors, ranks_list, max_iters, seeds, *, eps=1e-12, precisi
                                [t.data_ptr() for t in tensors],
                                [[c.data_ptr() for c in cs] for cs in cores], want_reports)
     return cores, reps, batch
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """Owns an ntt_server_t over a torch-allocated device arena (the HBM budget)."""
+
+    def __init__(self, arena_bytes, max_slots=16, iters_per_tick=25, device="cuda:0"):
+        import torch
+        lib = load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        cfg = NttServerConfig(self.arena.data_ptr(), int(arena_bytes), int(max_slots), int(iters_per_tick))
+        self.handle = C.c_void_p()
+        _check(lib.ntt_server_create(C.byref(cfg), C.byref(self.handle)), "ntt_server_create")
+        self._inputs = {}  # host inputs kept alive until the request is released
+        self._shapes = {}
+
+    def submit(self, host_A, ranks, max_iters, seed=0, eps=1e-12, precision=NTT_PREC_FP32,
+               fp32_tail_iters=20) -> int:
+        """host_A: a CPU float32 torch tensor (pinned for an overlapped copy)."""
+        dims = list(host_A.shape)
+        a, b = _i64(dims), _i64(ranks)
+        rq = NttRequest(len(dims), C.cast(a, C.POINTER(C.c_int64)), C.cast(b, C.POINTER(C.c_int64)),
+                        int(max_iters), float(eps), int(seed) & ((1 << 64) - 1), int(precision),
+                        int(fp32_tail_iters), host_A.data_ptr())
+        rid = C.c_int64()
+        _check(load().ntt_server_submit(self.handle, C.byref(rq), C.byref(rid)), "ntt_server_submit")
+        self._inputs[rid.value] = host_A
+        self._shapes[rid.value] = dims
+        return rid.value
+
+    def tick(self):
+        na, nq = C.c_int32(), C.c_int32()
+        _check(load().ntt_server_tick(self.handle, C.byref(na), C.byref(nq)), "ntt_server_tick")
+        return na.value, nq.value
+
+    def info(self, rid) -> dict:
+        inf = NttRequestInfo()
+        _check(load().ntt_server_info(self.handle, int(rid), C.byref(inf)), "ntt_server_info")
+        return {"id": inf.id, "state": inf.state, "t_submit": inf.t_submit, "t_admit": inf.t_admit,
+                "t_start": inf.t_start, "t_finish": inf.t_finish, "device_bytes": inf.device_bytes,
+                "gflop": inf.gflop, "eff_ranks": list(inf.eff_ranks[: inf.d + 1])}
+
+    def cores(self, rid):
+        """Zero-copy views (into the arena) of a finished request's cores."""
+        import torch
+        dims = self._shapes[rid]
+        eff = self.info(rid)["eff_ranks"]
+        ptrs = (C.c_void_p * len(dims))()
+        _check(load().ntt_server_cores(self.handle, int(rid), ptrs), "ntt_server_cores")
+        base = self.arena.data_ptr()
+        out = []
+        for k, n in enumerate(dims):
+            cnt = eff[k] * n * eff[k + 1]
+            off = ptrs[k] - base
+            out.append(self.arena[off:off + 4 * cnt].view(torch.float32).view(eff[k], n, eff[k + 1]))
+        return out
+
+    def release(self, rid):
+        _check(load().ntt_server_release(self.handle, int(rid)), "ntt_server_release")
+        self._inputs.pop(rid, None)
+
+    def free_bytes(self) -> int:
+        v = C.c_size_t()
+        _check(load().ntt_server_free_bytes(self.handle, C.byref(v)), "ntt_server_free_bytes")
+        return int(v.value)
+
+    def close(self):
+        if self.handle:
+            load().ntt_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

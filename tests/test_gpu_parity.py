@@ -392,3 +392,71 @@ def test_batched_bf16_mode_runs_and_matches_error_bar():
         e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
         e_bf = ntt.rel_error(dev(A), cs)
         assert abs(e_bf - e_orc) <= BF16_BAR
+
+
+# ------------------------------------------------------------------ a10: serving
+def _pinned(a):
+    t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
+    t.copy_(torch.from_numpy(a))
+    return t
+
+
+def test_serving_results_equal_standalone_results_and_budget_defers_admission():
+    say("case: serving, 8 requests, arena for ~2 at a time, 25 iterations per tick")
+    probs = _mix_problems()
+    T = 80
+    host_t = [S.contract_cores(S.random_cores(dm, rk, seed=sd)) for dm, rk, sd in probs]
+    # size the arena so that only a few requests fit at once
+    need = []
+    for (dm, rk, sd) in probs:
+        plan = ntt.Plan(dm, rk, T, seed=sd)
+        ws, eff, _ = plan.workspace()
+        cb = sum(((eff[k] * dm[k] * eff[k + 1] * 4 + 255) // 256) * 256 for k in range(len(dm)))
+        need.append(ws + cb + ((int(np.prod(dm)) * 4 + 255) // 256) * 256)
+    arena = 2 * max(need) + 4096
+    srv = ntt.Server(arena, max_slots=4, iters_per_tick=25)
+    ids = [srv.submit(_pinned(a), rk, T, seed=sd) for a, (dm, rk, sd) in zip(host_t, probs)]
+    alone = [ntt.decompose(dev(A), rk, T, seed=sd) for A, (dm, rk, sd) in zip(host_t, probs)]
+    pending = dict(zip(ids, range(len(ids))))
+    max_active = 0
+    deferred = False
+    ticks = 0
+    while pending:
+        na, nq = srv.tick()
+        max_active = max(max_active, na)
+        deferred |= (nq > 0 and na > 0)
+        ticks += 1
+        for rid in list(pending):
+            inf = srv.info(rid)
+            if inf["state"] != ntt.NTT_REQ_DONE:
+                continue
+            i = pending.pop(rid)
+            for x, y in zip(srv.cores(rid), alone[i].cores):
+                assert torch.equal(x, y), probs[i]
+            assert inf["t_submit"] <= inf["t_admit"] <= inf["t_start"] <= inf["t_finish"]
+            srv.release(rid)
+        assert ticks < 500000
+    assert deferred and max_active >= 1
+    assert srv.free_bytes() == arena
+    srv.close()
+
+
+def test_serving_rejects_oversize_and_cancels():
+    say("case: serving, oversize request rejected, running request cancelled")
+    srv = ntt.Server(1 << 20, max_slots=2, iters_per_tick=5)
+    big = srv.submit(_pinned(np.ones((64, 64, 64), np.float32)), (1, 4, 4, 1), 10)
+    assert srv.info(big)["state"] == ntt.NTT_REQ_REJECTED
+    a = S.contract_cores(S.random_cores((6, 7, 5), (1, 3, 4, 1), seed=11))
+    r1 = srv.submit(_pinned(a), (1, 3, 4, 1), 400, seed=2)
+    r2 = srv.submit(_pinned(a), (1, 3, 4, 1), 30, seed=3)
+    srv.tick()
+    srv.release(r1)  # cancel while running (or queued)
+    while srv.info(r2)["state"] != ntt.NTT_REQ_DONE:
+        srv.tick()
+    alone = ntt.decompose(dev(a), (1, 3, 4, 1), 30, seed=3)
+    for x, y in zip(srv.cores(r2), alone.cores):
+        assert torch.equal(x, y)
+    srv.release(r2)
+    srv.release(big)
+    assert srv.free_bytes() == 1 << 20
+    srv.close()
