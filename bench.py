@@ -19,6 +19,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "nTT GFLOP/s & decomps/s, p50/p99 latency; BF16 vs FP32 at equal rel. error"
+
+
+def progress(msg):
+    """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -30,6 +35,10 @@ def parse():
     ap.add_argument("--workload", default="tt32x5_r8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision-mode, batched and serving measurements")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-max-mb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
@@ -61,6 +70,114 @@ def cpu_baseline(A, w, seconds):
     return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}) of the same workload, "
                       f"NumPy FP64, {el:.1f} s"}
+
+
+def precision_mode(ntt, S, torch):
+    """128^4 rank-16 workload: FP32 sweep vs BF16 mode (last 20 iterations FP32)."""
+    w = S.workload("tt128x4_r16")
+    A = torch.from_numpy(w.tensor()).cuda()
+    out = {"workload": f"{w.name}: {w.note}"}
+    progress("precision mode: 128^4 tensor generated")
+    for name, prec in (("fp32", ntt.NTT_PREC_FP32), ("bf16", ntt.NTT_PREC_BF16_MIXED)):
+        plan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed, precision=prec,
+                        fp32_tail_iters=w.fp32_tail)
+        res = ntt.decompose(A, w.target_ranks, w.iters, plan=plan, want_report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ntt.decompose(A, w.target_ranks, w.iters, plan=plan, cores=res.cores)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": ms, "gflop_per_s": res.report["total_gflop"] / (ms * 1e-3),
+                     "decomps_per_s": 1e3 / ms, "rel_error": ntt.rel_error(A, res.cores),
+                     "stage_ms": res.report["ms"]}
+        progress(f"precision mode: {name} {ms:.1f} ms")
+    out["bf16_speedup"] = out["fp32"]["ms"] / out["bf16"]["ms"]
+    out["rel_error_gap"] = abs(out["bf16"]["rel_error"] - out["fp32"]["rel_error"])
+    del A
+    return out
+
+
+def _tt_on_gpu(ntt, S, torch, w):
+    cores = [torch.from_numpy(c).cuda() for c in S.random_cores(w.dims, w.gen_ranks, w.seed)]
+    return ntt.reconstruct(cores)
+
+
+def batched(ntt, S, torch, count=256):
+    """256 tensors, d in {3,4,5}, n in [8,64], true ranks in [2,12], T = 200, FP32."""
+    mix = S.batched_mix(count)
+    tensors = [_tt_on_gpu(ntt, S, torch, w) for w in mix]
+    progress(f"batched: {count} tensors generated")
+    ranks = [w.target_ranks for w in mix]
+    seeds = [w.seed for w in mix]
+    cores, reps, b = ntt.decompose_batch(tensors, ranks, mix[0].iters, seeds)
+    torch.cuda.synchronize()
+    progress("batched: warm-up batch done")
+    t0 = time.perf_counter()
+    cores, reps, b = ntt.decompose_batch(tensors, ranks, mix[0].iters, seeds, batch=b, cores=cores)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    gflop = sum(r["total_gflop"] for r in reps)
+    out = {"problems": count, "entries": int(sum(t.numel() for t in tensors)), "s": sec,
+           "decomps_per_s": count / sec, "gflop_per_s": gflop / sec,
+           "mean_stage_rel_err": float(sum(sum(r["stage_rel_err"]) / len(r["stage_rel_err"]) for r in reps) / count)}
+    del tensors, cores
+    return out
+
+
+def serving(ntt, S, torch, n_req, max_mb, precision):
+    """Poisson stream of TT-generated requests (d in 3..6, 1 MB..max_mb log-uniform, r 4..32),
+    first saturated (all at t = 0) to find the service rate mu, then at 0.5 mu and 0.8 mu."""
+    import numpy as np
+    reqs = S.serving_stream(n_req, max_bytes=max_mb * 1e6)
+    host = []
+    for q in reqs:
+        g = _tt_on_gpu(ntt, S, torch, q.work)
+        h = torch.empty(tuple(g.shape), dtype=torch.float32, pin_memory=True)
+        h.copy_(g)
+        host.append(h)
+        del g
+    progress(f"serving: {len(reqs)} requests generated")
+    need = sum(h.numel() * 4 for h in host)
+    arena = int(min(64 << 30, 3 * need + (1 << 30)))
+
+    def run(arrivals):
+        srv = ntt.Server(arena, max_slots=16, iters_per_tick=25)
+        t_start = time.perf_counter()
+        pending, done, lat, gfl = list(range(len(reqs))), {}, [], 0.0
+        ids = {}
+        while pending or len(done) < len(reqs):
+            now = time.perf_counter() - t_start
+            while pending and arrivals[pending[0]] <= now:
+                i = pending.pop(0)
+                q = reqs[i].work
+                ids[srv.submit(host[i], q.target_ranks, q.iters, seed=q.seed, precision=precision,
+                               fp32_tail_iters=20)] = i
+            srv.tick()
+            for rid, i in list(ids.items()):
+                inf = srv.info(rid)
+                if inf["state"] == ntt.NTT_REQ_DONE:
+                    lat.append(inf["t_finish"] - inf["t_submit"])
+                    gfl += inf["gflop"]
+                    done[i] = inf["t_finish"]
+                    srv.release(rid)
+                    del ids[rid]
+                elif inf["state"] in (ntt.NTT_REQ_REJECTED, ntt.NTT_REQ_CANCELLED):
+                    raise RuntimeError("request not served")
+        span = time.perf_counter() - t_start
+        srv.close()
+        progress(f"serving run: {len(reqs)} requests in {span:.2f} s")
+        lat = np.array(lat)
+        return {"decomps_per_s": len(reqs) / span, "gflop_per_s": gfl / span,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+    sat = run([0.0] * len(reqs))
+    mu = sat["decomps_per_s"]
+    out = {"requests": n_req, "max_mb": max_mb, "saturated": sat}
+    for frac in (0.5, 0.8):
+        rate = frac * mu
+        gaps = -np.log(1.0 - S.uniform01(5, 0x301, (n_req,)).astype(np.float64)) / rate
+        out[f"rate_{frac}mu"] = run(list(np.cumsum(gaps) - gaps[0]))
+    return out
 
 
 def main():
@@ -103,6 +220,7 @@ def main():
         return ntt.ntt_rel_error(w.dims, eff, A.data_ptr(), core_ptrs, tt_ws.data_ptr(),
                                  tt_ws_bytes, stream)
 
+    progress(f"{w.name}: input resident, warm-up")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -112,6 +230,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el * 1e3 / args.steps
+    progress(f"{w.name}: {ms:.2f} ms per step")
 
     # stage shapes and algorithmic flops
     shapes = []
@@ -157,6 +276,18 @@ def main():
                      "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
                      "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
     }
+    if not args.no_extras:
+        del A
+        torch.cuda.empty_cache()
+        out["precision_mode"] = precision_mode(ntt, S, torch)
+        torch.cuda.empty_cache()
+        out["batched"] = batched(ntt, S, torch)
+        torch.cuda.empty_cache()
+        out["serving"] = {
+            "fp32": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_FP32),
+            "bf16": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_BF16_MIXED),
+            "note": f"{args.serve_requests} requests of the serving stream recipe, sizes capped at "
+                    f"{args.serve_max_mb} MB, Poisson arrivals at 0.5 and 0.8 of the saturated rate"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -63,6 +63,7 @@ struct Stage {
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
+  size_t part_stride = 0;  // floats between the per-workgroup partials of this stage
 };
 
 }  // namespace
@@ -183,8 +184,8 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   // stages and workspace
   size_t hsize[2] = {0, 0};
   size_t xb_size = 0;
-  size_t part_stride = 0;
-  int gmax = 1;
+  size_t part_floats = 0;
+  int gmax = 1, gres = 1;
   size_t red_max = 0;
   for (int l = 1; l < d; ++l) {
     Stage& s = p->st[l - 1];
@@ -216,15 +217,19 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     s.bf16 = cfg->precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
              (s.kind == PASS_L || (s.kind == PASS_S && s.r <= 8));
     if (!s.fused) {
-      const int64_t want = std::max<int64_t>(1, std::min<int64_t>((s.k + 255) / 256, 256));
+      // column chunks of the generic X H^T partials: enough for parallelism, but their
+      // G (m r + r r) floats stay within ~1/4 of the X bytes
+      const int64_t gcap_gen = std::max<int64_t>(1, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed));
+      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((s.k + 255) / 256, 256), gcap_gen));
       s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
       s.G = (int)((s.k + s.chunk - 1) / s.chunk);
     }
-    if (!s.fused) gmax = std::max<int>(gmax, (int)((s.k + 255) / 256));  // residual blocks
+    if (!s.fused) gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
     const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
-    part_stride = std::max(part_stride, align_up(E, 64));
+    s.part_stride = align_up(E, 64);
     red_max = std::max(red_max, E);
     gmax = std::max(gmax, s.G);
+    part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
     if (l < d - 1) {
       const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
       hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
@@ -232,13 +237,12 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
     p->total_iters += cfg->max_iters;
   }
-  gmax = std::max(gmax, kSumsqBlocks);
+  gres = std::max(std::max(gres, gmax), kSumsqBlocks);
   size_t off = 0;
   p->off_h[0] = off; off = align_up(off + hsize[0], 256);
   p->off_h[1] = off; off = align_up(off + hsize[1], 256);
-  p->part_stride = part_stride;
-  p->off_part = off; off = align_up(off + (size_t)gmax * part_stride * sizeof(float), 256);
-  p->off_rpart = off; off = align_up(off + (size_t)gmax * sizeof(double), 256);
+  p->off_part = off; off = align_up(off + part_floats * sizeof(float), 256);
+  p->off_rpart = off; off = align_up(off + (size_t)gres * sizeof(double), 256);
   p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
   p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
   p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
@@ -292,7 +296,7 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
   a.W = W;
   a.GW = c.gw();
   a.part = c.part();
-  a.part_stride = (int64_t)c.p->part_stride;
+  a.part_stride = (int64_t)s.part_stride;
   a.rpart = c.rpart();
   a.m = (int)s.m;
   a.r = s.r;
@@ -401,7 +405,7 @@ struct NttJob {
     }
     fa = FinArgs{};
     fa.part = c.part();
-    fa.part_stride = (int64_t)p->part_stride;
+    fa.part_stride = (int64_t)s.part_stride;
     fa.G = s.G;
     fa.m = (int)s.m;
     fa.r = s.r;
