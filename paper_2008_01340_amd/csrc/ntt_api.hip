@@ -64,7 +64,50 @@ struct Stage {
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
   size_t part_stride = 0;  // floats between the per-workgroup partials of this stage
+  // generic stages whose transposed problem (X^T = H^T W^T) fits the fused passes
+  bool trans_ok = false;
+  int G_pre = 1;          // transposed problem: column chunks of its first X H^T pass
+  int64_t chunk_pre = 0;
 };
+
+// Pass kind, row class and workgroup count of an m x k, rank-r problem.
+void classify_stage(Stage& s, int precision) {
+  s.rp = s.r <= 16 ? 16 : 32;
+  const int64_t ngroups = (s.k + 15) / 16;
+  const double Ed = (double)s.m * s.r + (double)s.r * s.r;
+  // partials cost G E floats per iteration: keep them within ~10% of the X bytes,
+  // but use at least 256 workgroups when there are that many groups
+  const int64_t gcap = std::max<int64_t>(
+      256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
+  s.cls = pass_L_class(s.m, s.rp);
+  if (s.m <= 32) {
+    s.kind = PASS_S;
+    s.mb = s.m <= 16 ? 1 : 2;
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, gcap));
+  } else if (s.cls >= 0) {
+    s.kind = PASS_L;
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
+  } else {
+    s.kind = PASS_GENERIC;
+  }
+  s.fused = s.kind != PASS_GENERIC;
+  // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
+  // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
+  s.bf16 = precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
+           (s.kind == PASS_L || (s.kind == PASS_S && s.r <= 8));
+  const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
+  s.part_stride = align_up(E, 64);
+}
+
+// Column chunks of the generic X H^T partials: enough for parallelism, while their
+// G (m r + r r) floats stay within ~1/4 of the X bytes.
+void generic_chunks(const Stage& s, int* G, int64_t* chunk) {
+  const double Ed = (double)s.m * s.r + (double)s.r * s.r;
+  const int64_t gcap_gen = std::max<int64_t>(1, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed));
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((s.k + 255) / 256, 256), gcap_gen));
+  *chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
+  *G = (int)((s.k + *chunk - 1) / *chunk);
+}
 
 }  // namespace
 
@@ -74,12 +117,14 @@ struct ntt_plan_s {
   int64_t dims[NTT_MAX_DIMS] = {};
   int64_t eff[NTT_MAX_DIMS + 1] = {};
   Stage st[NTT_MAX_DIMS];
+  Stage tst[NTT_MAX_DIMS];  // transposed problems of the stages with trans_ok
   double compression = 0.0;
   int64_t total_iters = 0;
   // workspace layout (bytes)
   size_t off_h[2] = {0, 0};
   size_t off_part = 0, part_stride = 0, off_rpart = 0, off_red = 0, off_gw = 0;
   size_t off_scal = 0, off_ints = 0, off_xb = 0, total = 0;
+  size_t off_xt = 0, off_wp = 0, off_hp = 0;  // X^T, H^T, W^T of a transposed stage
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
@@ -187,46 +232,38 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   size_t part_floats = 0;
   int gmax = 1, gres = 1;
   size_t red_max = 0;
+  size_t xt_size = 0, wp_size = 0, hp_size = 0;
   for (int l = 1; l < d; ++l) {
     Stage& s = p->st[l - 1];
     s.m = p->eff[l - 1] * p->dims[l - 1];
     s.k = 1;
     for (int j = l; j < d; ++j) s.k *= p->dims[j];
     s.r = (int)p->eff[l];
-    s.rp = s.r <= 16 ? 16 : 32;
-    const int64_t ngroups = (s.k + 15) / 16;
-    const double Ed = (double)s.m * s.r + (double)s.r * s.r;
-    // partials cost G E floats per iteration: keep them within ~10% of the X bytes,
-    // but use at least 256 workgroups when there are that many groups
-    const int64_t gcap = std::max<int64_t>(
-        256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
-    s.cls = pass_L_class(s.m, s.rp);
-    if (s.m <= 32) {
-      s.kind = PASS_S;
-      s.mb = s.m <= 16 ? 1 : 2;
-      s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, gcap));
-    } else if (s.cls >= 0) {
-      s.kind = PASS_L;
-      s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
-    } else {
-      s.kind = PASS_GENERIC;
-    }
-    s.fused = s.kind != PASS_GENERIC;
-    // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
-    // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
-    s.bf16 = cfg->precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
-             (s.kind == PASS_L || (s.kind == PASS_S && s.r <= 8));
+    classify_stage(s, cfg->precision);
     if (!s.fused) {
-      // column chunks of the generic X H^T partials: enough for parallelism, but their
-      // G (m r + r r) floats stay within ~1/4 of the X bytes
-      const int64_t gcap_gen = std::max<int64_t>(1, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed));
-      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((s.k + 255) / 256, 256), gcap_gen));
-      s.chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
-      s.G = (int)((s.k + s.chunk - 1) / s.chunk);
+      generic_chunks(s, &s.G, &s.chunk);
+      gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
+      // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
+      // this one shifted by half a step, and its rows (k) may fit the fused passes
+      Stage t{};
+      t.m = s.k;
+      t.k = s.m;
+      t.r = s.r;
+      classify_stage(t, cfg->precision);
+      if (t.fused && cfg->tol == 0.0 && cfg->max_iters >= 1 && !stage_1wg_ok(t.m, t.k, t.r)) {
+        generic_chunks(t, &t.G_pre, &t.chunk_pre);
+        s.trans_ok = true;
+        p->tst[l - 1] = t;
+        part_floats = std::max(part_floats, (size_t)std::max(t.G, t.G_pre) * t.part_stride);
+        red_max = std::max(red_max, (size_t)t.m * t.r + (size_t)t.r * t.r);
+        gres = std::max(gres, t.G);
+        xt_size = std::max(xt_size, (size_t)s.m * (size_t)s.k * sizeof(float));
+        wp_size = std::max(wp_size, (size_t)s.k * (size_t)s.r * sizeof(float));
+        hp_size = std::max(hp_size, (size_t)s.r * (size_t)s.m * sizeof(float));
+        if (t.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
+      }
     }
-    if (!s.fused) gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
     const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
-    s.part_stride = align_up(E, 64);
     red_max = std::max(red_max, E);
     gmax = std::max(gmax, s.G);
     part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
@@ -248,6 +285,9 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
   p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
   p->off_xb = off; off = align_up(off + xb_size, 256);
+  p->off_xt = off; off = align_up(off + xt_size, 256);
+  p->off_wp = off; off = align_up(off + wp_size, 256);
+  p->off_hp = off; off = align_up(off + hp_size, 256);
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -286,6 +326,9 @@ struct Ctx {
   }
   int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }  // [0] input flags
   uint16_t* xb() const { return reinterpret_cast<uint16_t*>(ws + p->off_xb); }
+  float* xt() const { return reinterpret_cast<float*>(ws + p->off_xt); }
+  float* wp() const { return reinterpret_cast<float*>(ws + p->off_wp); }
+  float* hp() const { return reinterpret_cast<float*>(ws + p->off_hp); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -335,13 +378,15 @@ struct NttJob {
   float* H = nullptr;
   float* W = nullptr;
   PassArgs pa{}, pa_bf{};
-  FinArgs fa{};
+  FinArgs fa{}, fa_pre{};
   int bf_iters = 0;
   bool one_wg = false, final_known = false;
+  bool trans = false;  // the stage iterates on X^T ~ H^T W^T (pa, fa refer to it)
   double nx = 0.0;
   std::vector<double> fhist;
 
   const Stage& st() const { return p->st[l - 1]; }
+  const Stage& es() const { return trans ? p->tst[l - 1] : p->st[l - 1]; }  // as iterated
   int d() const { return p->d; }
 
   ntt_status start(ntt_plan_s* plan, hipStream_t s, void* workspace, const float* A_,
@@ -393,27 +438,40 @@ struct NttJob {
     else HIP_TRY(launch_init_uniform(W, mr, cfg.seed, 2ull * l, q));
     if (initH[l - 1]) HIP_TRY(launch_copy(H, initH[l - 1], rk, q));
     else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, q));
-    one_wg = !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
-    if (!one_wg) HIP_TRY(launch_gram_w(W, (int)s.m, s.r, s.rp, c.gw(), q));
+    trans = s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    const Stage& e = es();
+    one_wg = !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
     const float eps = (float)cfg.eps;
-    pa = pass_args(c, s, X, H, W, eps);
+    if (trans) {
+      // X' = X^T (k x m), W' = H^T (k x r), H' = W^T (r x m); W'^T W' comes from the
+      // first W'-update
+      HIP_TRY(launch_transpose(X, c.xt(), s.m, s.k, q));
+      HIP_TRY(launch_transpose(W, c.hp(), s.m, s.r, q));
+      HIP_TRY(launch_transpose(H, c.wp(), s.r, s.k, q));
+      pa = pass_args(c, e, c.xt(), c.hp(), c.wp(), eps);
+    } else {
+      if (!one_wg) HIP_TRY(launch_gram_w(W, (int)s.m, s.r, s.rp, c.gw(), q));
+      pa = pass_args(c, s, X, H, W, eps);
+    }
     pa_bf = pa;
-    bf_iters = s.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    bf_iters = e.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
     if (bf_iters > 0) {
-      HIP_TRY(launch_cast_bf16(c.xb(), X, s.m * s.k, q));
+      HIP_TRY(launch_cast_bf16(c.xb(), pa.X, s.m * s.k, q));
       pa_bf.Xb = c.xb();
     }
     fa = FinArgs{};
     fa.part = c.part();
-    fa.part_stride = (int64_t)s.part_stride;
-    fa.G = s.G;
-    fa.m = (int)s.m;
-    fa.r = s.r;
+    fa.part_stride = (int64_t)e.part_stride;
+    fa.G = e.G;
+    fa.m = (int)e.m;
+    fa.r = e.r;
     fa.red = c.red();
-    fa.W = W;
+    fa.W = trans ? c.wp() : W;
     fa.GW = c.gw();
     fa.scal = c.scal(l);
     fa.eps = eps;
+    fa_pre = fa;
+    fa_pre.G = e.G_pre;
     t = 0;
     final_known = false;
     fhist.clear();
@@ -430,16 +488,16 @@ struct NttJob {
   }
 
   hipError_t residual_now(double* slot) {
-    hipError_t e = run_pass(c.s, st(), pa, false, true);
+    hipError_t e = run_pass(c.s, es(), pa, false, true);
     if (e != hipSuccess) return e;
-    return launch_resid_sum(c.rpart(), resid_blocks(st()), c.scal(l) + SCAL_OBJ, slot, c.s);
+    return launch_resid_sum(c.rpart(), resid_blocks(es()), c.scal(l) + SCAL_OBJ, slot, c.s);
   }
 
   hipError_t graph_for(int n, bool bf, hipGraphExec_t* out) {
     const PassArgs& pg = bf ? pa_bf : pa;
     for (auto& g : p->graphs)
-      if (g.stage == l && g.iters == n && g.bf == bf && g.X == X && g.H == H && g.W == W &&
-          g.ws == c.ws) {
+      if (g.stage == l && g.iters == n && g.bf == bf && g.X == pg.X && g.H == pg.H &&
+          g.W == pg.W && g.ws == c.ws) {
         *out = g.exec;
         return hipSuccess;
       }
@@ -456,12 +514,12 @@ struct NttJob {
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int i = 0; i < n && le == hipSuccess; ++i) {
-      le = run_pass(cap_stream, st(), pg, true, false);
+      le = run_pass(cap_stream, es(), pg, true, false);
       if (le == hipSuccess) {
         FinArgs f2 = fa;
         f2.rpart = nullptr;
         f2.trace = nullptr;
-        le = launch_finalize(f2, st().rp, cap_stream);
+        le = launch_finalize(f2, es().rp, cap_stream);
       }
     }
     hipGraph_t graph = nullptr;
@@ -479,7 +537,7 @@ struct NttJob {
       (void)hipGraphExecDestroy(p->graphs.front().exec);
       p->graphs.erase(p->graphs.begin());
     }
-    p->graphs.push_back({l, n, bf, X, H, W, c.ws, exec});
+    p->graphs.push_back({l, n, bf, pg.X, pg.H, pg.W, c.ws, exec});
     *out = exec;
     return hipSuccess;
   }
@@ -487,6 +545,7 @@ struct NttJob {
   // a3 + a4: up to `budget` MU iterations of the current stage (a stopping check of a5
   // may end the stage early); *stage_done is set when no iterations remain.
   ntt_status iterate(int budget, bool* stage_done) {
+    if (trans) return iterate_transposed(budget, stage_done);
     const ntt_config& cfg = p->cfg;
     const Stage& s = st();
     hipStream_t q = c.s;
@@ -561,6 +620,50 @@ struct NttJob {
     return NTT_OK;
   }
 
+  // The stage's T iterations on X' = X^T: H'-update of X' is the W-update of X and its
+  // W'-update the H-update, so H_1 is the W'-update of (W'_0, H'_0), each of the next
+  // T - 1 transposed iterations gives (W_t, H_{t+1}), and an H'-update alone gives W_T.
+  ntt_status iterate_transposed(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    const Stage& e = es();
+    hipStream_t q = c.s;
+    const int T = cfg.max_iters;
+    while (budget > 0 && t < T) {
+      if (t == 0) {
+        PassArgs pre = pa;
+        pre.part_stride = (int64_t)e.part_stride;
+        HIP_TRY(launch_xht_partials(pre, e.rp, e.G_pre, e.chunk_pre, q));
+        HIP_TRY(launch_finalize(fa_pre, e.rp, q));
+      }
+      const bool bf = t < bf_iters;
+      const PassArgs& pcur = bf ? pa_bf : pa;
+      if (t < T - 1) {
+        int block = std::min(budget, T - 1 - t);
+        if (bf) block = std::min(block, bf_iters - t);
+        int n_done = 0;
+        while (block - n_done >= kGraphIters) {
+          hipGraphExec_t ex = nullptr;
+          HIP_TRY(graph_for(kGraphIters, bf, &ex));
+          HIP_TRY(hipGraphLaunch(ex, q));
+          n_done += kGraphIters;
+        }
+        for (; n_done < block; ++n_done) {
+          HIP_TRY(run_pass(q, e, pcur, true, false));
+          HIP_TRY(launch_finalize(fa, e.rp, q));
+        }
+        t += block;
+        budget -= block;
+      } else {
+        HIP_TRY(run_pass(q, e, pcur, true, false));
+        t = T;
+        budget -= 1;
+      }
+      final_known = false;
+    }
+    *stage_done = t >= T;
+    return NTT_OK;
+  }
+
   // a5 at the end of the stage (explicit objective of the final iterate), then a6:
   // W is already core l; H becomes the next unfolding (or is core d).
   ntt_status finish_stage() {
@@ -568,6 +671,12 @@ struct NttJob {
     if (iters[l - 1] == 0) iters[l - 1] = t;
     if (want_final && !final_known)
       HIP_TRY(residual_now((record && t >= 1) ? trace + trace_off + (t - 1) : nullptr));
+    if (trans) {  // W = H'^T, H = W'^T
+      const Stage& s = st();
+      HIP_TRY(launch_transpose(c.hp(), W, s.r, s.m, c.s));
+      HIP_TRY(launch_transpose(c.wp(), H, s.k, s.r, c.s));
+      trans = false;
+    }
     trace_off += cfg.max_iters;
     prepared = false;
     if (l + 1 >= d()) done = true;

@@ -75,6 +75,7 @@ struct TTArgs {
 hipError_t launch_init_uniform(float* out, int64_t n, uint64_t seed, uint64_t tag, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 hipError_t launch_cast_bf16(uint16_t* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_transpose(const float* src, float* dst, int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, int* flags,
                         int validate, double* out, hipStream_t s);
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
@@ -91,6 +92,8 @@ hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng
 hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s);
+// X H^T and H H^T partials alone (column chunks of `chunk`), as the generic pass writes them
+hipError_t launch_xht_partials(const PassArgs& a, int rp, int gxht, int64_t chunk, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);

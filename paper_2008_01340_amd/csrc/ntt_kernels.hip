@@ -1518,6 +1518,26 @@ __global__ void k_cast_bf16(uint16_t* __restrict__ dst, const float* __restrict_
   }
 }
 
+// Coalesced transpose: dst (cols x rows) = src (rows x cols)^T, both row-major, through
+// 32 x 33 LDS tiles (the padding keeps the column reads free of bank conflicts).  One
+// workgroup per tile, tiles numbered row-major over a 1-D grid.
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, float* __restrict__ dst,
+                                                   int64_t rows, int64_t cols, int64_t tiles_c) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  const int64_t t = blockIdx.x;
+  const int64_t c0 = (t % tiles_c) * 32, r0 = (t / tiles_c) * 32;
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < rows && c < cols) tile[i][tx] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;  // dst row c, column r
+    if (c < cols && r < rows) dst[c * rows + r] = tile[tx][i];
+  }
+}
+
 // copy helper: dst[i] = src[i]
 __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1644,6 +1664,15 @@ hipError_t launch_cast_bf16(uint16_t* dst, const float* src, int64_t n, hipStrea
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
   k_cast_bf16<<<(int)blocks, 256, 0, s>>>(dst, src, n);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_transpose(const float* src, float* dst, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t tc = (cols + 31) / 32, tr = (rows + 31) / 32;
+  if (tc * tr > 0x7fffffffLL) return hipErrorInvalidValue;
+  k_transpose<<<(unsigned)(tc * tr), 256, 0, s>>>(src, dst, rows, cols, tc);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1812,12 +1841,15 @@ hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chun
     else k_gen_hupdate<32, false, true><<<gh, 256, 0, s>>>(a);
   }
   NTT_CHECK_LAUNCH();
-  if (update) {
-    dim3 grid(gxht, (a.m + 63) / 64);
-    if (rp == 16) k_gen_xht<16><<<grid, 256, 0, s>>>(a, chunk);
-    else k_gen_xht<32><<<grid, 256, 0, s>>>(a, chunk);
-    NTT_CHECK_LAUNCH();
-  }
+  if (update) return launch_xht_partials(a, rp, gxht, chunk, s);
+  return hipSuccess;
+}
+
+hipError_t launch_xht_partials(const PassArgs& a, int rp, int gxht, int64_t chunk, hipStream_t s) {
+  dim3 grid(gxht, (a.m + 63) / 64);
+  if (rp == 16) k_gen_xht<16><<<grid, 256, 0, s>>>(a, chunk);
+  else k_gen_xht<32><<<grid, 256, 0, s>>>(a, chunk);
+  NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
 

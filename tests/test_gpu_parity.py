@@ -78,8 +78,11 @@ SHAPES = [
     (37, 2, 2),
     # rows split over 8 waves (m <= 512 at either padding, m <= 1024 at rank <= 16)
     (300, 200, 5), (400, 100, 30), (600, 150, 9),
-    # beyond the fused kernels: the generic path
-    (700, 90, 20), (1100, 40, 4),
+    # m beyond the fused kernels, k within them: the transposed problem X^T = H^T W^T
+    # runs on the fused passes (rows split over waves, or the r <= 8 pass for k <= 32)
+    (700, 90, 20), (1100, 40, 4), (2000, 24, 6), (1500, 300, 12),
+    # m and k both beyond the fused kernels: the generic path
+    (1030, 700, 20),
 ]
 
 
@@ -171,6 +174,25 @@ def test_sweep_4way_ragged_modes():
         assert np.max(np.abs(f_gpu[l] - f_orc) / f_orc) <= TOL
     for cg, co in zip(res.cores, ref["cores"]):
         assert rel(host(cg), co) <= TOL
+
+
+def test_sweep_with_transposed_middle_stage():
+    say("case: sweep 8x160x6x5 ranks (1,8,8,4,1), T=100; stage 2 is 1280 x 30")
+    dims, ranks = (8, 160, 6, 5), (1, 8, 8, 4, 1)
+    A = S.noisy_tensor(dims, ranks, seed=31, noise="mult", level=0.01)
+    T = 100
+    ref = O.ntt_decompose(A, ranks, T, seed=4)
+    res = ntt.decompose(dev(A), ranks, T, seed=4)
+    for k, (cg, co) in enumerate(zip(res.cores, ref["cores"])):
+        assert rel(host(cg), co) <= TOL, (k, rel(host(cg), co))
+    for l in range(3):
+        st = ref["stages"][l]
+        f_orc = O.objective(st["X"], st["W"], st["H"])
+        assert obj_close(res.report["objective"][l], f_orc, st["norm_x"] ** 2), l
+    # the objective trace forces the untransposed path: same iterates within the bar
+    rec = ntt.decompose(dev(A), ranks, T, seed=4, record_objective=True)
+    for cg, cr in zip(res.cores, rec.cores):
+        assert rel(host(cg), host(cr)) <= TOL
 
 
 def test_rank_clamping_matches_oracle():
@@ -311,6 +333,7 @@ BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
     ((16, 16, 16), (1, 4, 4, 1), "none", 0.0, 200),
     ((48, 48, 48, 48), (1, 16, 16, 16, 1), "absnormal", 0.01, 200),
     ((24, 30, 20, 36), (1, 6, 8, 5, 1), "mult", 0.01, 150),
+    ((1200, 8, 8), (1, 6, 4, 1), "mult", 0.01, 150),  # stage 1 transposed (1200 x 64)
 ])
 def test_bf16_mode_final_error_matches_oracle(dims, gen, noise, level, T):
     say(f"case: BF16 mode dims={dims} ranks={gen} T={T} tail=20")
@@ -348,7 +371,8 @@ def _mix_problems():
     return [((6, 7, 5), (1, 3, 4, 1), 11), ((16, 16, 16), (1, 4, 4, 1), 1),
             ((9, 20, 8, 6), (1, 5, 6, 3, 1), 5), ((30, 40, 12), (1, 12, 9, 1), 8),
             ((12, 10, 11, 9, 8), (1, 4, 7, 5, 2, 1), 21), ((64, 33, 50), (1, 10, 12, 1), 3),
-            ((8, 8, 8), (1, 2, 2, 1), 13), ((40, 9, 17, 23), (1, 8, 11, 6, 1), 17)]
+            ((8, 8, 8), (1, 2, 2, 1), 13), ((40, 9, 17, 23), (1, 8, 11, 6, 1), 17),
+            ((1100, 6, 5), (1, 5, 4, 1), 23)]  # stage 1 (1100 x 30) iterates transposed
 
 
 def test_batched_results_equal_standalone_results_bitwise():
