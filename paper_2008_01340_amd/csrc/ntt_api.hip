@@ -230,7 +230,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   size_t hsize[2] = {0, 0};
   size_t xb_size = 0;
   size_t part_floats = 0;
-  int gmax = 1, gres = 1;
+  int gmax = 1, gres = 1, gfin = 1;
   size_t red_max = 0;
   size_t xt_size = 0, wp_size = 0, hp_size = 0;
   for (int l = 1; l < d; ++l) {
@@ -257,6 +257,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
         part_floats = std::max(part_floats, (size_t)std::max(t.G, t.G_pre) * t.part_stride);
         red_max = std::max(red_max, (size_t)t.m * t.r + (size_t)t.r * t.r);
         gres = std::max(gres, t.G);
+        gfin = std::max(gfin, std::max(t.G, t.G_pre));
         xt_size = std::max(xt_size, (size_t)s.m * (size_t)s.k * sizeof(float));
         wp_size = std::max(wp_size, (size_t)s.k * (size_t)s.r * sizeof(float));
         hp_size = std::max(hp_size, (size_t)s.r * (size_t)s.m * sizeof(float));
@@ -266,6 +267,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
     red_max = std::max(red_max, E);
     gmax = std::max(gmax, s.G);
+    gfin = std::max(gfin, s.G);
     part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
     if (l < d - 1) {
       const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
@@ -281,6 +283,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_part = off; off = align_up(off + part_floats * sizeof(float), 256);
   p->off_rpart = off; off = align_up(off + (size_t)gres * sizeof(double), 256);
   p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
+  if (gfin > 1024) return fail(NTT_ERR_INVALID_ARG, "too many partials for the W-update reduction");
   p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
   p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
   p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
@@ -308,9 +311,6 @@ void ntt_plan_destroy(ntt_plan_t p) { delete p; }
 
 namespace {
 
-__global__ void k_zero_ints(int* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
-}
 
 // Workspace views of one problem.
 struct Ctx {
@@ -410,8 +410,7 @@ struct NttJob {
     t = 0;
     prepared = done = false;
     trace_off = 0;
-    k_zero_ints<<<1, 64, 0, s>>>(c.ints(), 64);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_zero_ints(c.ints(), 64, s));
     return NTT_OK;
   }
 

@@ -95,6 +95,7 @@ hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chun
 // X H^T and H H^T partials alone (column chunks of `chunk`), as the generic pass writes them
 hipError_t launch_xht_partials(const PassArgs& a, int rp, int gxht, int64_t chunk, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s);
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
 

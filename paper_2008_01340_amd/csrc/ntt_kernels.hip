@@ -33,6 +33,7 @@
 namespace ntt {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // D[4*(l/16)+i][l%16] += sum_s A[l%16][s] * B[s][l%16]; A from lane a+16s, B from lane n+16s.
 __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
@@ -1346,98 +1347,124 @@ __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
 }
 
 // ------------------------------------------------------------------ W-update
-// (1) k_reduce_partials: red[e] = sum over g of part[g][e] in FP64, for the E = m r + r r
-//     entries of the partials (X H^T then H H^T); 16 entries per block, 16 chunk
-//     threads per entry, four interleaved accumulators per thread, then chunks 0..15
-//     in order: a fixed summation order, so results do not depend on scheduling.
-__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ part,
-                                                         int64_t stride, int G, int64_t E,
-                                                         double* __restrict__ red) {
-  __shared__ double sPart[16][17];
-  const int tid = threadIdx.x;
-  const int e_loc = tid & 15, ch = tid >> 4;
-  const int64_t e = (int64_t)blockIdx.x * 16 + e_loc;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (e < E) {
-    int g = ch;
-    for (; g + 48 < G; g += 64) {
-      a0 += (double)part[(int64_t)g * stride + e];
-      a1 += (double)part[(int64_t)(g + 16) * stride + e];
-      a2 += (double)part[(int64_t)(g + 32) * stride + e];
-      a3 += (double)part[(int64_t)(g + 48) * stride + e];
-    }
-    for (; g < G; g += 16) a0 += (double)part[(int64_t)g * stride + e];
+// Two launches after each pass with G > 4 partials, free of cross-block waits:
+// (1) k_reduce_partials, grid ceil(E / 16): block eb sums entries [16 eb, 16 eb + 16)
+//     of the E = m r + r r partial entries (X H^T then H H^T) over all G <= 1024
+//     partials: 64 lanes per entry, lane l taking partials l, l + 64, ... (all loads
+//     issued at once), then lanes in groups of eight and the groups in order, in FP64;
+// (2) k_wupdate: one block reads the sums and updates W.
+// With G <= 4, k_wupdate sums the FP32 partials itself (g = 0..G-1 in order).
+// The summation order is fixed, so results do not depend on scheduling.
+constexpr int kReduceLanes = 64;
+constexpr int kMaxReduceG = 16 * kReduceLanes;
+
+__global__ __launch_bounds__(1024) void k_reduce_partials(const float* __restrict__ part,
+                                                          int64_t stride, int G, int64_t E,
+                                                          double* __restrict__ red) {
+  __shared__ double sP[kReduceLanes][17];
+  __shared__ double sQ[8][17];
+  const int tid = threadIdx.x, el = tid & 15, lane = tid >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + el;
+  float v[kMaxReduceG / kReduceLanes];
+#pragma unroll
+  for (int i = 0; i < kMaxReduceG / kReduceLanes; ++i) {
+    const int g = lane + kReduceLanes * i;
+    v[i] = (e < E && g < G) ? part[(int64_t)g * stride + e] : 0.f;
   }
-  sPart[ch][e_loc] = (a0 + a1) + (a2 + a3);
+  double a = 0.0;
+#pragma unroll
+  for (int i = 0; i < kMaxReduceG / kReduceLanes; ++i) a += (double)v[i];
+  sP[lane][el] = a;
+  __syncthreads();
+  if (tid < 128) {
+    const int q = tid >> 4;
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) s += sP[8 * q + l][el];
+    sQ[q][el] = s;
+  }
   __syncthreads();
   if (tid < 16 && (int64_t)blockIdx.x * 16 + tid < E) {
     double s = 0.0;
-    for (int c = 0; c < 16; ++c) s += sPart[c][tid];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += sQ[q][tid];
     red[(int64_t)blockIdx.x * 16 + tid] = s;
   }
 }
 
-// (2) k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
+__device__ __forceinline__ v4d mfma16_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
 //     and G_H = H H^T, 256 rows at a time, one thread per row (rows are independent,
 //     so the update is in place; each thread reads its whole row before writing it).
 //     FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also go to LDS,
-//     where the block accumulates G_W' = W'^T W' (FP64) for the next H-update.  It also
-//     writes the Gram-identity monitor
+//     from where each wavefront accumulates its 64 rows of G_W' = W'^T W' with FP64
+//     MFMA (16 x 16 x 4 tiles; four rows per step, in row order); the four wavefront
+//     sums are added in order.  It also writes the Gram-identity monitor
 //       f = 1/2 (||X||^2 - 2 <W', X H^T> + <W'^T W', H H^T>)
 //     and, when this iteration accumulated one, the explicit residual objective.
-//     RB >= r bounds the loops.  FUSED: N_W and G_H are summed here from the G <= 4
-//     per-workgroup partials (in the order g = 0..G-1) instead of read from `red`.
+//     RB >= r bounds the loops.  Entries are read from `red` or, when FUSED (G <= 4),
+//     summed from the FP32 partials in order.  The first 256 rows, G_H and ||X||^2 are
+//     loaded in one round before the first barrier (the kernel is latency-bound).
 template <int RB, bool FUSED>
 __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
-  constexpr int NPAIR = RB * RB;
-  constexpr int NSL = NPAIR >= 256 ? 1 : 256 / NPAIR;   // row slices of the Gram
-  constexpr int NPT = NPAIR <= 256 ? 1 : NPAIR / 256;   // Gram pairs per thread
+  constexpr int NT = (RB + 15) / 16;  // 16 x 16 tiles per side of the Gram
   __shared__ double sGH[RB][RB + 1];
   __shared__ double sGW[RB][RB + 1];
-  __shared__ double sGp[NSL][NPAIR];
+  __shared__ double sGp[4][NT * NT][64][4];
   __shared__ float sWc[256][RB + 1];
   __shared__ double sRed[4];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
   const int m = f.m, r = f.r;
   const int64_t mr = (int64_t)m * r;
   auto entry = [&](int64_t e) -> double {
     if (FUSED) {
       double v = 0.0;
-      for (int g = 0; g < f.G; ++g) v += (double)f.part[(int64_t)g * f.part_stride + e];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (g < f.G) v += (double)f.part[(int64_t)g * f.part_stride + e];
       return v;
     }
     return f.red[e];
   };
-  for (int pidx = tid; pidx < NPAIR; pidx += 256) {
+  float wrow[RB];
+  double nrow[RB];
+  auto load_row = [&](int i) {
+    const int64_t base = (int64_t)i * r;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int qc = min(q, r - 1);
+      const float wv = f.W[base + qc];
+      wrow[q] = (q < r) ? wv : 0.f;
+      nrow[q] = (q < r) ? entry(base + qc) : 0.0;
+    }
+  };
+  if (tid < m) load_row(tid);
+  for (int pidx = tid; pidx < RB * RB; pidx += 256) {
     const int c = pidx / RB, q = pidx % RB;
     sGH[c][q] = (c < r && q < r) ? entry(mr + c * r + q) : 0.0;
   }
+  const double nx2 = tid == 0 ? f.scal[SCAL_NX2] : 0.0;
   double rsum = 0.0;
   if (f.rpart && tid < 64) {
     for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
     rsum = wave_sum(rsum);
   }
   __syncthreads();
-  // Gram work split: thread -> (slice, pair) for RB <= 16, several pairs for RB = 32
-  const int slice = NSL > 1 ? tid / NPAIR : 0;
-  double gacc[NPT];
+  v4d acc[NT][NT];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) gacc[t] = 0.0;
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
   double dot_wn = 0.0;
   for (int i0 = 0; i0 < m; i0 += 256) {
     const int i = i0 + tid;
     if (i < m) {
-      float wrow[RB];
-      double nrow[RB];
+      if (i0 > 0) load_row(i);
       const int64_t base = (int64_t)i * r;
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int qc = min(q, r - 1);
-        const float wv = f.W[base + qc];
-        wrow[q] = (q < r) ? wv : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < RB; ++q) nrow[q] = (q < r) ? entry(base + min(q, r - 1)) : 0.0;
 #pragma unroll
       for (int c = 0; c < RB; ++c) {
         double dw = 0.0;
@@ -1456,53 +1483,67 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
       for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
     }
     __syncthreads();
-    const int nrows = min(256, m - i0);
-    const int per = (nrows + NSL - 1) / NSL;
-    const int lo = slice * per, hi = min(nrows, lo + per);
+    // this wavefront's 64 rows of the chunk, four per MFMA step (rows past m are zero)
+#pragma unroll 4
+    for (int st = 0; st < 16; ++st) {
+      const int row = 64 * w + 4 * st + b;
+      double opnd[NT];
 #pragma unroll
-    for (int t = 0; t < NPT; ++t) {
-      const int pidx = (tid % (NSL > 1 ? NPAIR : 256)) + 256 * t;
-      const int c = pidx / RB, q = pidx % RB;
-      double s = 0.0;
-      for (int ii = lo; ii < hi; ++ii) s += (double)sWc[ii][c] * (double)sWc[ii][q];
-      gacc[t] += s;
+      for (int h = 0; h < NT; ++h) {
+        const int c = 16 * h + a;
+        opnd[h] = (c < RB) ? (double)sWc[row][c < RB ? c : 0] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < NT; ++h)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[h][q] = mfma16_f64(opnd[h], opnd[q], acc[h][q]);
     }
     __syncthreads();
   }
-  // combine the row slices in order
+  // the four wavefronts' Grams, added in order
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) {
-    const int pidx = (tid % (NSL > 1 ? NPAIR : 256)) + 256 * t;
-    sGp[slice][pidx] = gacc[t];
-  }
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sGp[w][h * NT + q][lane][i] = acc[h][q][i];
   __syncthreads();
-  for (int pidx = tid; pidx < NPAIR; pidx += 256) {
-    double s = 0.0;
-    for (int sl = 0; sl < NSL; ++sl) s += sGp[sl][pidx];
-    sGW[pidx / RB][pidx % RB] = s;
+  for (int pidx = tid; pidx < NT * NT * 256; pidx += 256) {
+    const int tq = pidx >> 8, l = (pidx >> 2) & 63, i = pidx & 3;
+    const double s = ((sGp[0][tq][l][i] + sGp[1][tq][l][i]) + sGp[2][tq][l][i]) + sGp[3][tq][l][i];
+    // FP64 16 x 16 x 4 result layout: value i of lane (a, b) is row 4 i + b, column a
+    const int row = 16 * (tq / NT) + 4 * i + (l >> 4), col = 16 * (tq % NT) + (l & 15);
+    if (row < RB && col < RB) sGW[row][col] = s;
   }
   __syncthreads();
   // next G_W, zero padded to the pass kernels' RP x RP layout
   const int rp = r <= 16 ? 16 : 32;
   for (int pidx = tid; pidx < rp * rp; pidx += 256) {
     const int c = pidx / rp, q = pidx % rp;
-    f.GW[pidx] = (c < RB && q < RB) ? (float)sGW[c][q] : 0.f;
+    f.GW[pidx] = (c < RB && q < RB && c < r && q < r) ? (float)sGW[c][q] : 0.f;
   }
+  // monitor: <W'^T W', H H^T> over the first wavefront, then one thread
+  double gg = 0.0;
+  if (tid < 64)
+    for (int pidx = tid; pidx < r * r; pidx += 64) gg += sGW[pidx / r][pidx % r] * sGH[pidx / r][pidx % r];
+  gg = wave_sum(gg);
   dot_wn = wave_sum(dot_wn);
-  if ((tid & 63) == 0) sRed[tid >> 6] = dot_wn;
+  if (lane == 0) sRed[w] = dot_wn;
   __syncthreads();
   if (tid == 0) {
     const double wn = ((sRed[0] + sRed[1]) + sRed[2]) + sRed[3];
-    double gg = 0.0;
-    for (int c = 0; c < r; ++c)
-      for (int q = 0; q < r; ++q) gg += sGW[c][q] * sGH[c][q];
-    f.scal[SCAL_MONITOR] = 0.5 * (f.scal[SCAL_NX2] - 2.0 * wn + gg);
+    f.scal[SCAL_MONITOR] = 0.5 * (nx2 - 2.0 * wn + gg);
     if (f.rpart) {
       const double obj = 0.5 * rsum;
       f.scal[SCAL_OBJ] = obj;
       if (f.trace) f.trace[0] = obj;
     }
   }
+}
+
+__global__ void k_zero_ints(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // BF16 shadow of X: round to nearest, ties to even (NaN stays NaN).
@@ -1865,14 +1906,21 @@ hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
   (void)rp;
   const bool fused = f.G <= 4;
   if (!fused) {
+    if (f.G > kMaxReduceG) return hipErrorInvalidValue;
     const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
-    const int nb = (int)((E + 15) / 16);
-    k_reduce_partials<<<nb, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+    k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
     NTT_CHECK_LAUNCH();
   }
   if (f.r <= 8) return launch_wupdate<8>(f, fused, s);
   if (f.r <= 16) return launch_wupdate<16>(f, fused, s);
   return launch_wupdate<32>(f, fused, s);
+}
+
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_zero_ints<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s) {
