@@ -53,6 +53,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// `v` where `ok`, else 0, for a value loaded from a clamped (always valid) address.
+// Written as a multiply rather than a select so that the load stays unconditional: a
+// select lets the compiler sink the load into a branch that waits for every memory
+// operation in flight, which serialises loads and defeats prefetching.
+__device__ __forceinline__ float zmask(float v, bool ok) { return v * (ok ? 1.f : 0.f); }
+__device__ __forceinline__ double zmask(double v, bool ok) { return v * (ok ? 1.0 : 0.0); }
+
 // ------------------------------------------------------------------ SplitMix64 init
 // Value i of stream `tag`: SplitMix64 finaliser of seed + GAMMA (tag 2^32 + i + 1);
 // uniform = top 24 bits * 2^-24 (exact in FP32).
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_gram_w(const float* __restrict__ W, int
     __syncthreads();
     for (int e = threadIdx.x; e < 256 * RP; e += 256) {
       const int i = e / RP, c = e % RP;
-      sW[i][c] = (i0 + i < m && c < r) ? W[(int64_t)(i0 + i) * r + c] : 0.f;
+      sW[i][c] = zmask(W[(int64_t)min(i0 + i, m - 1) * r + min(c, r - 1)], i0 + i < m && c < r);
     }
     __syncthreads();
     gram_chunk<RP>(sW, min(256, m - i0), acc);
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
       const int e = tid + 256 * t;
       const int i = e / RP, c = e % RP;
       const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
-      wtmp[t] = (e < RP * MPAD && i < m && c < r) ? v : 0.f;
+      wtmp[t] = zmask(v, e < RP * MPAD && i < m && c < r);
     }
 #pragma unroll
     for (int t = 0; t < NWL; ++t) {
@@ -298,7 +305,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
           const float v = p.X[(int64_t)min(row, m - 1) * k + min(col, k - 1)];
-          xr[blk][q] = (row < m && col < k) ? v : 0.f;
+          xr[blk][q] = zmask(v, row < m && col < k);
         }
       }
     }
@@ -310,7 +317,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
       for (int kk = 0; kk < 4; ++kk) {
         const int c = 16 * h + 4 * b + kk;
         const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
-        hv[h][kk] = (c < r && col < k) ? v : 0.f;
+        hv[h][kk] = zmask(v, c < r && col < k);
       }
   };
 
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
       const int e = tid + 256 * t;
       const int i = e / 16, c = e % 16;
       const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
-      wtmp[t] = (e < 16 * MPAD && i < m && c < r) ? v : 0.f;
+      wtmp[t] = zmask(v, e < 16 * MPAD && i < m && c < r);
     }
 #pragma unroll
     for (int t = 0; t < NWL; ++t) {
@@ -576,13 +583,13 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
           const float v = ldx<XBF>(p, xrow[blk] + min(col, k - 1));
-          xr[blk][q] = col < k ? v : 0.f;
+          xr[blk][q] = zmask(v, col < k);
         }
       const int64_t col = j0 + a;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const float v = hrow[kk][min(col, k - 1)];
-        hv[kk] = col < k ? v : 0.f;
+        hv[kk] = zmask(v, col < k);
       }
     }
   };
@@ -770,11 +777,11 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
       for (int kk = 0; kk < 4; ++kk) {
         const int i = row0 + 16 * blk + 4 * b + kk, c = 16 * h + a;
         const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
-        wa[blk][h][kk] = (i < m && c < r) ? v : 0.f;
+        wa[blk][h][kk] = zmask(v, i < m && c < r);
         if (RESID) {
           const int i2 = row0 + 16 * blk + a, c2 = 16 * h + 4 * b + kk;
           const float v2 = p.W[(int64_t)min(i2, m - 1) * r + min(c2, r - 1)];
-          wr[blk][h][kk] = (i2 < m && c2 < r) ? v2 : 0.f;
+          wr[blk][h][kk] = zmask(v2, i2 < m && c2 < r);
         }
       }
   float gw[NH][NH][4];
@@ -827,7 +834,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
           const float v = ldx<XBF>(p, xrow[blk] + min(col, k - 1));
-          xr[blk][q] = (col < k && row0 + 16 * blk + a < m) ? v : 0.f;
+          xr[blk][q] = zmask(v, col < k && row0 + 16 * blk + a < m);
         }
     }
     const int64_t col = j0 + a;
@@ -838,7 +845,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
       for (int kk = 0; kk < 4; ++kk) {
         const int c = 16 * h + 4 * b + kk;
         const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
-        hv[h][kk] = (c < r && col < k) ? v : 0.f;
+        hv[h][kk] = zmask(v, c < r && col < k);
       }
   };
 
@@ -1062,10 +1069,10 @@ __device__ __forceinline__ void stage_1wg_body(const StageArgs& s) {
       for (int q = 0; q < 4; ++q) {
         const int i1 = row0 + 16 * blk + a, c1 = 16 * g + 4 * b + q;
         const float v1 = s.X[(int64_t)min(i1, m - 1) * k + min(c1, k - 1)];
-        xa[g][blk][q] = (i1 < m && c1 < k) ? v1 : 0.f;
+        xa[g][blk][q] = zmask(v1, i1 < m && c1 < k);
         const int i2 = row0 + 16 * blk + 4 * b + q, c2 = 16 * g + a;
         const float v2 = s.X[(int64_t)min(i2, m - 1) * k + min(c2, k - 1)];
-        xt[g][blk][q] = (i2 < m && c2 < k) ? v2 : 0.f;
+        xt[g][blk][q] = zmask(v2, i2 < m && c2 < k);
       }
   // W in the C layout of the 16x16 tiles: wc[blk][i] = W[row0+16blk+4b+i][a]
   float wc[MBW][4];
@@ -1075,12 +1082,12 @@ __device__ __forceinline__ void stage_1wg_body(const StageArgs& s) {
     for (int i = 0; i < 4; ++i) {
       const int row = row0 + 16 * blk + 4 * b + i;
       const float v = s.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)];
-      wc[blk][i] = (row < m && a < r) ? v : 0.f;
+      wc[blk][i] = zmask(v, row < m && a < r);
     }
   for (int e = tid; e < 16 * (KC + 4); e += 256) {
     const int c = e / (KC + 4), j = e % (KC + 4);
     const float v = s.H[(int64_t)min(c, r - 1) * k + min(j, k - 1)];
-    sH[c][j] = (c < r && j < k) ? v : 0.f;
+    sH[c][j] = zmask(v, c < r && j < k);
   }
 
   // G_W = sum over waves of sum_rows W^T W (M = N = rank, K = row): both operands are wc
@@ -1221,8 +1228,9 @@ __global__ __launch_bounds__(256) void k_gen_hupdate(PassArgs p) {
   const int64_t j = (int64_t)blockIdx.x * 256 + tid;
   const bool act = j < k;
   float h[RP];
+  const int64_t jc = act ? j : k - 1;
 #pragma unroll
-  for (int c = 0; c < RP; ++c) h[c] = (act && c < r) ? p.H[(int64_t)c * k + j] : 0.f;
+  for (int c = 0; c < RP; ++c) h[c] = zmask(p.H[(int64_t)min(c, r - 1) * k + jc], act && c < r);
   float acc[RP];
 #pragma unroll
   for (int c = 0; c < RP; ++c) acc[c] = 0.f;
@@ -1231,12 +1239,13 @@ __global__ __launch_bounds__(256) void k_gen_hupdate(PassArgs p) {
     __syncthreads();
     for (int e = tid; e < 64 * RP; e += 256) {
       const int i = e / RP, c = e % RP;
-      sW[i][c] = (i0 + i < m && c < r) ? p.W[(int64_t)(i0 + i) * r + c] : 0.f;
+      sW[i][c] = zmask(p.W[(int64_t)min(i0 + i, m - 1) * r + min(c, r - 1)], i0 + i < m && c < r);
     }
     __syncthreads();
     const int iend = min(64, m - i0);
+#pragma unroll 8
     for (int i = 0; i < iend; ++i) {
-      const float x = act ? p.X[(int64_t)(i0 + i) * k + j] : 0.f;
+      const float x = zmask(p.X[(int64_t)(i0 + i) * k + jc], act);
       if (UPDATE) {
 #pragma unroll
         for (int c = 0; c < RP; ++c) acc[c] = fmaf(sW[i][c], x, acc[c]);
@@ -1294,12 +1303,12 @@ __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
       const int i = e >> 6, jj = e & 63;
       const int gi = 64 * rb + i;
       const int64_t gj = j0 + jj;
-      sX[i][jj] = (gi < m && gj < c1) ? p.X[(int64_t)gi * k + gj] : 0.f;
+      sX[i][jj] = zmask(p.X[(int64_t)min(gi, m - 1) * k + min(gj, c1 - 1)], gi < m && gj < c1);
     }
     for (int e = tid; e < RP * 64; e += 256) {
       const int c = e >> 6, jj = e & 63;
       const int64_t gj = j0 + jj;
-      sH[c][jj] = (c < r && gj < c1) ? p.H[(int64_t)c * k + gj] : 0.f;
+      sH[c][jj] = zmask(p.H[(int64_t)min(c, r - 1) * k + min(gj, c1 - 1)], c < r && gj < c1);
     }
     __syncthreads();
 #pragma unroll 1
@@ -1369,7 +1378,7 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const float* __restric
 #pragma unroll
   for (int i = 0; i < kMaxReduceG / kReduceLanes; ++i) {
     const int g = lane + kReduceLanes * i;
-    v[i] = (e < E && g < G) ? part[(int64_t)g * stride + e] : 0.f;
+    v[i] = zmask(part[(int64_t)min(g, G - 1) * stride + min(e, E - 1)], e < E && g < G);
   }
   double a = 0.0;
 #pragma unroll
@@ -1425,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
       double v = 0.0;
 #pragma unroll
       for (int g = 0; g < 4; ++g)
-        if (g < f.G) v += (double)f.part[(int64_t)g * f.part_stride + e];
+        v += (double)zmask(f.part[(int64_t)min(g, f.G - 1) * f.part_stride + e], g < f.G);
       return v;
     }
     return f.red[e];
@@ -1438,16 +1447,16 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
     for (int q = 0; q < RB; ++q) {
       const int qc = min(q, r - 1);
       const float wv = f.W[base + qc];
-      wrow[q] = (q < r) ? wv : 0.f;
-      nrow[q] = (q < r) ? entry(base + qc) : 0.0;
+      wrow[q] = zmask(wv, q < r);
+      nrow[q] = zmask(entry(base + qc), q < r);
     }
   };
-  if (tid < m) load_row(tid);
+  load_row(min(tid, m - 1));  // rows past m are loaded but not used
   for (int pidx = tid; pidx < RB * RB; pidx += 256) {
     const int c = pidx / RB, q = pidx % RB;
-    sGH[c][q] = (c < r && q < r) ? entry(mr + c * r + q) : 0.0;
+    sGH[c][q] = zmask(entry(mr + min(c, r - 1) * r + min(q, r - 1)), c < r && q < r);
   }
-  const double nx2 = tid == 0 ? f.scal[SCAL_NX2] : 0.0;
+  const double nx2 = f.scal[SCAL_NX2];
   double rsum = 0.0;
   if (f.rpart && tid < 64) {
     for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
@@ -1615,7 +1624,7 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
     const int rk = t.ranks[1];
     for (int e = tid; e < 64 * rk; e += 256) {
       const int rr = e / rk, c = e % rk;
-      sP[0][rr][c] = (rr < nrow) ? t.cores[0][(int64_t)sIdx[rr][0] * rk + c] : 0.f;
+      sP[0][rr][c] = zmask(t.cores[0][(int64_t)sIdx[min(rr, nrow - 1)][0] * rk + c], rr < nrow);
     }
   }
   __syncthreads();
