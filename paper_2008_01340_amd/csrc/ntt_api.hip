@@ -51,15 +51,17 @@ constexpr size_t kMaxGraphs = 64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-enum PassKind { PASS_S = 0, PASS_L = 1, PASS_GENERIC = 2 };
+enum PassKind { PASS_S = 0, PASS_L = 1, PASS_GENERIC = 2, PASS_C = 3 };
 
 struct Stage {
   int64_t m = 0, k = 0;
   int r = 0, rp = 16;
-  bool fused = true;  // one X pass per iteration (PASS_S or PASS_L)
+  bool fused = true;  // one X pass per iteration whose workgroups also sum the residual
+                      // (PASS_S or PASS_L)
   int kind = PASS_S;
   int cls = 0;      // PASS_L: row class
   int mb = 1;       // PASS_S: 16-row blocks
+  int nch = 0;      // PASS_C: row chunks
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
@@ -87,14 +89,18 @@ void classify_stage(Stage& s, int precision) {
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
+  } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
+    s.kind = PASS_C;
+    s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
   } else {
     s.kind = PASS_GENERIC;
   }
-  s.fused = s.kind != PASS_GENERIC;
+  s.fused = s.kind == PASS_S || s.kind == PASS_L;
   // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
   // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
   s.bf16 = precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
-           (s.kind == PASS_L || (s.kind == PASS_S && s.r <= 8));
+           (s.kind == PASS_L || s.kind == PASS_C || (s.kind == PASS_S && s.r <= 8));
   const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
   s.part_stride = align_up(E, 64);
 }
@@ -125,6 +131,7 @@ struct ntt_plan_s {
   size_t off_part = 0, part_stride = 0, off_rpart = 0, off_red = 0, off_gw = 0;
   size_t off_scal = 0, off_ints = 0, off_xb = 0, total = 0;
   size_t off_xt = 0, off_wp = 0, off_hp = 0;  // X^T, H^T, W^T of a transposed stage
+  size_t off_s = 0;  // row-chunked stages: W^T X per row chunk, then a copy of H
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
@@ -232,7 +239,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   size_t part_floats = 0;
   int gmax = 1, gres = 1, gfin = 1;
   size_t red_max = 0;
-  size_t xt_size = 0, wp_size = 0, hp_size = 0;
+  size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0;
   for (int l = 1; l < d; ++l) {
     Stage& s = p->st[l - 1];
     s.m = p->eff[l - 1] * p->dims[l - 1];
@@ -240,9 +247,15 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     for (int j = l; j < d; ++j) s.k *= p->dims[j];
     s.r = (int)p->eff[l];
     classify_stage(s, cfg->precision);
-    if (!s.fused) {
+    if (s.kind == PASS_GENERIC) {
       generic_chunks(s, &s.G, &s.chunk);
       gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
+    }
+    if (s.kind == PASS_C) {
+      gres = std::max(gres, s.G * s.nch);
+      s_size = std::max(s_size, (size_t)(s.nch + 1) * (size_t)s.r * (size_t)s.k * sizeof(float));
+    }
+    if (!s.fused) {
       // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
       // this one shifted by half a step, and its rows (k) may fit the fused passes
       Stage t{};
@@ -291,6 +304,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_xt = off; off = align_up(off + xt_size, 256);
   p->off_wp = off; off = align_up(off + wp_size, 256);
   p->off_hp = off; off = align_up(off + hp_size, 256);
+  p->off_s = off; off = align_up(off + s_size, 256);
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -329,6 +343,7 @@ struct Ctx {
   float* xt() const { return reinterpret_cast<float*>(ws + p->off_xt); }
   float* wp() const { return reinterpret_cast<float*>(ws + p->off_wp); }
   float* hp() const { return reinterpret_cast<float*>(ws + p->off_hp); }
+  float* sbuf() const { return reinterpret_cast<float*>(ws + p->off_s); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -345,16 +360,23 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
   a.r = s.r;
   a.k = s.k;
   a.eps = eps;
+  a.S = s.kind == PASS_C ? c.sbuf() : nullptr;
+  a.nchunks = s.nch;
+  a.Hs = s.kind == PASS_C ? c.sbuf() + (size_t)s.nch * s.r * s.k : nullptr;
   return a;
 }
 
 hipError_t run_pass(hipStream_t q, const Stage& s, const PassArgs& a, bool update, bool resid) {
   if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, q);
   if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, q);
+  if (s.kind == PASS_C) return launch_pass_C(a, s.rp, s.G, update, resid, q);
   return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, q);
 }
 
-int resid_blocks(const Stage& s) { return s.fused ? s.G : (int)((s.k + 255) / 256); }
+int resid_blocks(const Stage& s) {
+  if (s.kind == PASS_C) return s.G * s.nch;
+  return s.fused ? s.G : (int)((s.k + 255) / 256);
+}
 
 }  // namespace
 

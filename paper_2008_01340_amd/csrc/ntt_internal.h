@@ -26,6 +26,9 @@ struct PassArgs {
   int m, r;
   int64_t k;
   float eps;
+  float* S;             // row-chunked pass: W^T X of each row chunk, nchunks x r x k floats
+  int nchunks;          // row-chunked pass: number of row chunks
+  float* Hs;            // row-chunked pass: copy of H taken in phase 1, read in phase 2 (r x k)
 };
 
 // Reduction of the pass partials and the W-update.
@@ -85,6 +88,11 @@ int pass_L_class(int64_t m, int rp);  // -1 when m is beyond the row-split varia
 int pass_L_waves(int cls);
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
                          hipStream_t s);
+// Row-chunked pass (m beyond one workgroup): rows per chunk, and the launches of one
+// iteration (phase 1, chunk sum, phase 2) or of the residual (phase 0) on a
+// (G, nchunks) grid.  S holds nchunks x r x k floats, Hs r x k.
+int pass_C_rows(int rp);
+hipError_t launch_pass_C(const PassArgs& a, int rp, int G, bool update, bool resid, hipStream_t s);
 bool stage_1wg_ok(int64_t m, int64_t k, int r);
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
 int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)

@@ -1008,6 +1008,329 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
   }
 }
 
+// ------------------------------------------------------------------ row-chunked MU pass
+// For m beyond one workgroup: rows are cut into chunks of CR = 16 MBW NW rows, chunk y
+// taken by the workgroups with blockIdx.y = y, which visit the same 16-column groups for
+// every chunk.  One MU iteration is two launches, each reading X once:
+//   phase 1: per group, the chunk's part of W^T X (waves as in the row-split pass, summed
+//            over the workgroup's waves in order) is stored to S[y] (r x k); chunk 0
+//            also copies the group's H to Hs;
+//   (k_sum_chunks between them: S[0] <- S[0] + S[1] + ..., in chunk order;)
+//   phase 2: per group, N_H = S[0], the H-update epilogue in every wave (H read from Hs:
+//            the workgroups of the other chunks may still be reading a group whose H
+//            chunk 0 has already replaced), H_new stored and H_new H_new^T accumulated by
+//            wave 0 of chunk 0, X H_new^T accumulated for each wave's own rows.  Workgroup (x, y) writes the chunk-y rows of partial x
+//            (chunk 0 also its H H^T part), so the gridDim.x partials are complete, as
+//            after the fused passes;
+//   phase 0: the residual of the wave's rows, to rpart[y gridDim.x + x].
+template <int RP, int MBW, int NW, int PH, bool XBF>
+__global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
+  constexpr int NH = RP / 16;
+  constexpr int SX = 20;
+  constexpr int CR = 16 * MBW * NW;
+  __shared__ __attribute__((aligned(16))) float sX[NW][16 * SX];
+  __shared__ __attribute__((aligned(16))) float sNH[PH == 1 ? 2 : 1][PH == 1 ? NW : 1][RP * 16];
+  __shared__ __attribute__((aligned(16))) float sHn[NW][RP * SX];
+  __shared__ double sRes[NW];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int y = blockIdx.y;
+  const int row0 = y * CR + w * 16 * MBW;
+  const int64_t ngroups = (k + 15) >> 4;
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+
+  // phase 1: W^T as the A operand of W^T X; phase 0: W as the A operand of W H
+  float wa[PH == 1 ? MBW : 1][NH][4];
+  float wr[PH == 0 ? MBW : 1][NH][4];
+#pragma unroll
+  for (int blk = 0; blk < (PH == 2 ? 0 : MBW); ++blk)
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        if (PH == 1) {
+          const int i = row0 + 16 * blk + 4 * b + kk, c = 16 * h + a;
+          wa[blk][h][kk] = zmask(p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)], i < m && c < r);
+        } else {
+          const int i2 = row0 + 16 * blk + a, c2 = 16 * h + 4 * b + kk;
+          wr[blk][h][kk] = zmask(p.W[(int64_t)min(i2, m - 1) * r + min(c2, r - 1)], i2 < m && c2 < r);
+        }
+      }
+  float gw[PH == 2 ? NH : 1][PH == 2 ? NH : 1][4];
+  if (PH == 2) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < NH; ++q)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) gw[h][q][kk] = p.GW[(16 * h + a) * RP + 16 * q + 4 * b + kk];
+  }
+  v4f accW[PH == 2 ? MBW : 1][NH];
+  v4f accG[NH][NH];
+#pragma unroll
+  for (int i = 0; i < (PH == 2 ? MBW : 1); ++i)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) accW[i][h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < NH; ++q) accG[h][q] = v4f{0.f, 0.f, 0.f, 0.f};
+  double res = 0.0;
+
+  float* sXw = sX[w];
+  float* sHw = sHn[w];
+  int64_t xrow[MBW];
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk) xrow[blk] = (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
+
+  // X rows of the wave (rows past m: zero in phase 0, unused otherwise), the H tile
+  // (phases 0 and 2) and the summed W^T X (phase 2) of group g
+  auto load_group = [&](int64_t g, float (&xr)[MBW][4], float (&hv)[NH][4], float (&sv)[NH][4]) {
+    const int64_t j0 = g << 4;
+    if (vec_ok && (j0 + 16 <= k)) {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk) {
+        const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
+        if (PH == 0) {
+          const bool ok = row0 + 16 * blk + a < m;
+          xr[blk][0] = zmask(v.x, ok);
+          xr[blk][1] = zmask(v.y, ok);
+          xr[blk][2] = zmask(v.z, ok);
+          xr[blk][3] = zmask(v.w, ok);
+        } else {
+          xr[blk][0] = v.x;
+          xr[blk][1] = v.y;
+          xr[blk][2] = v.z;
+          xr[blk][3] = v.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t col = j0 + 4 * b + q;
+          const float v = ldx<XBF>(p, xrow[blk] + min(col, k - 1));
+          xr[blk][q] = zmask(v, col < k && row0 + 16 * blk + a < m);
+        }
+    }
+    const int64_t col = j0 + a;
+    const int64_t colc = min(col, k - 1);
+    if (PH != 1 || (y == 0 && w == 0)) {
+      const float* Hsrc = PH == 2 ? p.Hs : p.H;
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int c = 16 * h + 4 * b + kk;
+          hv[h][kk] = zmask(Hsrc[(int64_t)min(c, r - 1) * k + colc], c < r && col < k);
+        }
+    }
+    if (PH == 2) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int c = 16 * h + 4 * b + kk;
+          sv[h][kk] = zmask(p.S[(int64_t)min(c, r - 1) * k + colc], c < r && col < k);
+        }
+    }
+  };
+
+  float xn[MBW][4], hn_[NH][4], sn[NH][4];
+  if ((int64_t)blockIdx.x < ngroups) load_group(blockIdx.x, xn, hn_, sn);
+  int par = 0;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+    const int64_t j0 = g << 4;
+    const bool full = vec_ok && (j0 + 16 <= k);
+    float xr[MBW][4], hv[NH][4], sv[NH][4];
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xr[blk][q] = xn[blk][q];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hv[h][q] = hn_[h][q];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sv[h][q] = sn[h][q];
+    if (g + gridDim.x < ngroups) load_group(g + gridDim.x, xn, hn_, sn);
+
+    if (PH != 2) {
+      v4f nh[NH];
+#pragma unroll
+      for (int h = 0; h < NH; ++h) nh[h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk) {
+        wave_sync();
+        *reinterpret_cast<float4*>(&sXw[a * SX + 4 * b]) =
+            make_float4(xr[blk][0], xr[blk][1], xr[blk][2], xr[blk][3]);
+        wave_sync();
+        float xt[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xt[kk] = sXw[(4 * b + kk) * SX + a];
+        if (PH == 1) {
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) nh[h] = mfma16(wa[blk][h][kk], xt[kk], nh[h]);
+        } else {
+          v4f wh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < NH; ++q)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) wh = mfma16(wr[blk][q][kk], hv[q][kk], wh);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double dlt = (double)xt[i] - (double)wh[i];
+            res += dlt * dlt;
+          }
+        }
+      }
+      if (PH == 1) {
+        if (y == 0 && w == 0) {  // H of the group, for phase 2
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const int c = 16 * h + 4 * b + kk;
+              if (c < r && j0 + a < k) p.Hs[(int64_t)c * k + j0 + a] = hv[h][kk];
+            }
+        }
+        // sum the waves' parts in order; wave 0 stores the chunk's W^T X of the group
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sNH[par][w][(16 * h + 4 * b + i) * 16 + a] = nh[h][i];
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              float sum = sNH[par][0][(16 * h + 4 * b + i) * 16 + a];
+#pragma unroll
+              for (int ww = 1; ww < NW; ++ww) sum += sNH[par][ww][(16 * h + 4 * b + i) * 16 + a];
+              const int c = 16 * h + 4 * b + i;
+              if (c < r && j0 + a < k) p.S[((int64_t)y * r + c) * k + j0 + a] = sum;
+            }
+        }
+      }
+      continue;
+    }
+
+    // phase 2: N_H, D_H = G_W H, the epilogue (identical in every wave)
+    v4f nh[NH], dh[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nh[h][i] = sv[h][i];
+      dh[h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < NH; ++q)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dh[h] = mfma16(gw[h][q][kk], hv[q][kk], dh[h]);
+    }
+    wave_sync();
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * h + 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(hv[h][i] * nh[h][i], dh[h][i] + p.eps));
+        sHw[c * SX + a] = (c < r) ? q : 0.f;
+      }
+    wave_sync();
+    float4 hn4[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) hn4[h] = *reinterpret_cast<const float4*>(&sHw[(16 * h + a) * SX + 4 * b]);
+    if (y == 0 && w == 0) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int c = 16 * h + a;
+        if (c < r) {
+          float* dst = p.H + (int64_t)c * k + j0 + 4 * b;
+          if (full) {
+            *reinterpret_cast<float4*>(dst) = hn4[h];
+          } else {
+            const float vv[4] = {hn4[h].x, hn4[h].y, hn4[h].z, hn4[h].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (j0 + 4 * b + q < k) dst[q] = vv[q];
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < NH; ++q) {
+          accG[h][q] = mfma16(hn4[h].x, hn4[q].x, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].y, hn4[q].y, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].z, hn4[q].z, accG[h][q]);
+          accG[h][q] = mfma16(hn4[h].w, hn4[q].w, accG[h][q]);
+        }
+    }
+#pragma unroll
+    for (int blk = 0; blk < (PH == 2 ? MBW : 0); ++blk)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        accW[blk][h] = mfma16(xr[blk][0], hn4[h].x, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][1], hn4[h].y, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][2], hn4[h].z, accW[blk][h]);
+        accW[blk][h] = mfma16(xr[blk][3], hn4[h].w, accW[blk][h]);
+      }
+  }
+
+  if (PH == 2) {
+    float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = row0 + 16 * blk + 4 * b + i, c = 16 * h + a;
+          if (row < m && c < r) dst[(int64_t)row * r + c] = accW[blk][h][i];
+        }
+    if (y == 0 && w == 0) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < NH; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = 16 * h + 4 * b + i, cc = 16 * q + a;
+            if (c < r && cc < r) dst[(int64_t)m * r + c * r + cc] = accG[h][q][i];
+          }
+    }
+  }
+  if (PH == 0) {
+    res = wave_sum(res);
+    if (lane == 0) sRes[w] = res;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int ww = 0; ww < NW; ++ww) s += sRes[ww];
+      p.rpart[(int64_t)y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// S[0][e] <- S[0][e] + S[1][e] + ... + S[n-1][e] (chunk order), e < r k.
+__global__ __launch_bounds__(256) void k_sum_chunks(float* __restrict__ S, int64_t n_el, int nch) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_el) return;
+  float s = S[e];
+  for (int y = 1; y < nch; ++y) s += S[(int64_t)y * n_el + e];
+  S[e] = s;
+}
+
 // ------------------------------------------------------------------ whole stage in one workgroup
 // For small unfoldings (m <= 256, k <= 16 NG <= 64, r <= 16) one workgroup of four
 // wavefronts runs `iters` MU iterations without leaving the kernel.  X stays in
@@ -1844,6 +2167,41 @@ hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool upda
 }
 
 bool stage_1wg_ok(int64_t m, int64_t k, int r) { return m <= 256 && k <= 64 && r <= 16; }
+
+// Row-chunked pass: chunks of 512 rows, 8 waves of 64 rows (both paddings).
+int pass_C_rows(int rp) {
+  (void)rp;
+  return 512;
+}
+
+template <int RP>
+static hipError_t pass_C_rp(const PassArgs& a, int G, bool update, bool resid, hipStream_t s) {
+  dim3 grid((unsigned)G, (unsigned)a.nchunks);
+  if (resid) {
+    k_mu_pass_C<RP, 4, 8, 0, false><<<grid, 512, 0, s>>>(a);
+    NTT_CHECK_LAUNCH();
+  }
+  if (update) {
+    const int64_t n_el = (int64_t)a.r * a.k;
+    if (a.Xb != nullptr) k_mu_pass_C<RP, 4, 8, 1, true><<<grid, 512, 0, s>>>(a);
+    else k_mu_pass_C<RP, 4, 8, 1, false><<<grid, 512, 0, s>>>(a);
+    NTT_CHECK_LAUNCH();
+    k_sum_chunks<<<(unsigned)((n_el + 255) / 256), 256, 0, s>>>(a.S, n_el, a.nchunks);
+    NTT_CHECK_LAUNCH();
+    if (a.Xb != nullptr) k_mu_pass_C<RP, 4, 8, 2, true><<<grid, 512, 0, s>>>(a);
+    else k_mu_pass_C<RP, 4, 8, 2, false><<<grid, 512, 0, s>>>(a);
+    NTT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_pass_C(const PassArgs& a, int rp, int G, bool update, bool resid, hipStream_t s) {
+  if (a.nchunks < 1 || a.nchunks > 65535 || !a.S || !a.Hs ||
+      (int64_t)a.nchunks * pass_C_rows(rp) < a.m || G < 1)
+    return hipErrorInvalidValue;
+  if (a.Xb != nullptr && resid) return hipErrorInvalidValue;  // BF16 X: update passes only
+  return rp == 16 ? pass_C_rp<16>(a, G, update, resid, s) : pass_C_rp<32>(a, G, update, resid, s);
+}
 
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s) {
   if (!stage_1wg_ok(a.m, a.k, a.r) || a.iters <= 0) return hipErrorInvalidValue;

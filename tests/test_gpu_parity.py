@@ -81,8 +81,9 @@ SHAPES = [
     # m beyond the fused kernels, k within them: the transposed problem X^T = H^T W^T
     # runs on the fused passes (rows split over waves, or the r <= 8 pass for k <= 32)
     (700, 90, 20), (1100, 40, 4), (2000, 24, 6), (1500, 300, 12),
-    # m and k both beyond the fused kernels: the generic path
-    (1030, 700, 20),
+    # m and k both beyond the fused kernels: rows in chunks of 512, two X passes per
+    # iteration (3 chunks at rank padding 32; 3 and 6 chunks at padding 16)
+    (1030, 700, 20), (1500, 1100, 7), (2600, 1500, 16),
 ]
 
 
@@ -193,6 +194,28 @@ def test_sweep_with_transposed_middle_stage():
     rec = ntt.decompose(dev(A), ranks, T, seed=4, record_objective=True)
     for cg, cr in zip(res.cores, rec.cores):
         assert rel(host(cg), host(cr)) <= TOL
+
+
+def test_sweep_with_row_chunked_stage():
+    say("case: sweep 64x40x40x30 ranks (1,32,16,8,1), T=80; stage 2 is 1280 x 1200")
+    dims, ranks = (64, 40, 40, 30), (1, 32, 16, 8, 1)
+    A = S.noisy_tensor(dims, ranks, seed=41, noise="absnormal", level=0.01)
+    T = 80
+    ref = O.ntt_decompose(A, ranks, T, seed=6, record_objective=True)
+    res = ntt.decompose(dev(A), ranks, T, seed=6, record_objective=True)
+    f_gpu = host(res.trace).reshape(3, T)
+    for l in range(3):
+        st = ref["stages"][l]
+        assert np.all(obj_close(f_gpu[l], st["objective"][1:], st["norm_x"] ** 2)), l
+    for k, (cg, co) in enumerate(zip(res.cores, ref["cores"])):
+        assert rel(host(cg), co) <= TOL, (k, rel(host(cg), co))
+    # without the trace: stages 1-2 run the same kernels (bitwise equal cores); stage 3
+    # (640 x 30) iterates transposed, within the bar
+    fast = ntt.decompose(dev(A), ranks, T, seed=6)
+    for cg, cf in zip(res.cores[:2], fast.cores[:2]):
+        assert torch.equal(cg, cf)
+    for cg, cf in zip(res.cores[2:], fast.cores[2:]):
+        assert rel(host(cf), host(cg)) <= TOL
 
 
 def test_rank_clamping_matches_oracle():
