@@ -62,6 +62,7 @@ struct Stage {
   int cls = 0;      // PASS_L: row class
   int mb = 1;       // PASS_S: 16-row blocks
   int nch = 0;      // PASS_C: row chunks
+  bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
@@ -85,14 +86,19 @@ void classify_stage(Stage& s, int precision) {
   if (s.m <= 32) {
     s.kind = PASS_S;
     s.mb = s.m <= 16 ? 1 : 2;
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, gcap));
+    // the r <= 8 pass keeps three workgroups per CU resident: a grid of one full round
+    // (768 on 256 CUs) avoids a partly filled second round
+    const int64_t cap = s.r <= 8 ? std::min<int64_t>(gcap, 768) : gcap;
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, cap));
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
+    s.pairs = ngroups >= 512;  // column groups in pairs once there are enough of them
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
     s.kind = PASS_C;
     s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, gcap));
+    s.pairs = ngroups >= 512;
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap));
   } else {
     s.kind = PASS_GENERIC;
   }
@@ -363,6 +369,7 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
   a.S = s.kind == PASS_C ? c.sbuf() : nullptr;
   a.nchunks = s.nch;
   a.Hs = s.kind == PASS_C ? c.sbuf() + (size_t)s.nch * s.r * s.k : nullptr;
+  a.pair_groups = s.pairs ? 1 : 0;
   return a;
 }
 

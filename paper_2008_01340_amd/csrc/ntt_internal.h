@@ -29,6 +29,7 @@ struct PassArgs {
   float* S;             // row-chunked pass: W^T X of each row chunk, nchunks x r x k floats
   int nchunks;          // row-chunked pass: number of row chunks
   float* Hs;            // row-chunked pass: copy of H taken in phase 1, read in phase 2 (r x k)
+  int pair_groups;      // row-split and row-chunked passes: take column groups in pairs
 };
 
 // Reduction of the pass partials and the W-update.

@@ -850,9 +850,18 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
   };
 
   float xn[MBW][4], hn_[NH][4];  // next group, loaded while the current one is processed
-  if ((int64_t)blockIdx.x < ngroups) load_group(blockIdx.x, xn, hn_);
+  // with pair_groups, groups in pairs (2p, 2p + 1), one after the other: both halves of a
+  // 128-byte line of X (and H) are then read by the same workgroup, so the line is
+  // fetched once; small stages keep one group per workgroup for parallelism
+  const bool pairs = p.pair_groups != 0;
+  auto group_of = [&](int64_t it) -> int64_t {
+    return pairs ? 2 * ((int64_t)blockIdx.x + (it >> 1) * (int64_t)gridDim.x) + (it & 1)
+                 : (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
+  };
+  int64_t it = 0;
+  if (group_of(0) < ngroups) load_group(group_of(0), xn, hn_);
   int par = 0;
-  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+  for (int64_t g = group_of(0); g < ngroups; g = group_of(++it), par ^= 1) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
     float xr[MBW][4], hv[NH][4];
@@ -864,7 +873,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) hv[h][q] = hn_[h][q];
-    if (g + gridDim.x < ngroups) load_group(g + gridDim.x, xn, hn_);
+    if (group_of(it + 1) < ngroups) load_group(group_of(it + 1), xn, hn_);
     v4f nh[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) nh[h] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1142,9 +1151,18 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
   };
 
   float xn[MBW][4], hn_[NH][4], sn[NH][4];
-  if ((int64_t)blockIdx.x < ngroups) load_group(blockIdx.x, xn, hn_, sn);
+  // with pair_groups, groups in pairs (2p, 2p + 1), one after the other: both halves of a
+  // 128-byte line of X (and H) are then read by the same workgroup, so the line is
+  // fetched once; small stages keep one group per workgroup for parallelism
+  const bool pairs = p.pair_groups != 0;
+  auto group_of = [&](int64_t it) -> int64_t {
+    return pairs ? 2 * ((int64_t)blockIdx.x + (it >> 1) * (int64_t)gridDim.x) + (it & 1)
+                 : (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
+  };
+  int64_t it = 0;
+  if (group_of(0) < ngroups) load_group(group_of(0), xn, hn_, sn);
   int par = 0;
-  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x, par ^= 1) {
+  for (int64_t g = group_of(0); g < ngroups; g = group_of(++it), par ^= 1) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
     float xr[MBW][4], hv[NH][4], sv[NH][4];
@@ -1160,7 +1178,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[h][q] = sn[h][q];
-    if (g + gridDim.x < ngroups) load_group(g + gridDim.x, xn, hn_, sn);
+    if (group_of(it + 1) < ngroups) load_group(group_of(it + 1), xn, hn_, sn);
 
     if (PH != 2) {
       v4f nh[NH];

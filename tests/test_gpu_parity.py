@@ -84,6 +84,9 @@ SHAPES = [
     # m and k both beyond the fused kernels: rows in chunks of 512, two X passes per
     # iteration (3 chunks at rank padding 32; 3 and 6 chunks at padding 16)
     (1030, 700, 20), (1500, 1100, 7), (2600, 1500, 16),
+    # enough column groups (>= 512, an odd count) for workgroups to take them in pairs:
+    # rows split over waves, and rows in chunks
+    (100, 9000, 12), (1100, 8200, 5),
 ]
 
 
