@@ -25,6 +25,11 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8<2> on 768
+# workgroups): rocprofv3 FETCH_SIZE (84,958.6 KiB) and WRITE_SIZE (35,142.5 KiB) per
+# dispatch, scaled by what the same counters read for a plain 1 GiB copy (x2.00, x1.00).
+# Taken on the current pass kernel; re-measure whenever that kernel changes.
+MEASURED_TRAFFIC = {"tt32x5_r8": 173.995e6 + 35.986e6}
 
 
 def parse():
@@ -272,7 +277,7 @@ def main():
         "rel_error": err,
         "stage_ms": rep_graph["ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(w.name),
                      "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
                      "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
     }
