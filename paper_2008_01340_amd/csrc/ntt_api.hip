@@ -62,6 +62,7 @@ struct Stage {
   int cls = 0;      // PASS_L: row class
   int mb = 1;       // PASS_S: 16-row blocks
   int nch = 0;      // PASS_C: row chunks
+  bool pro_ok = false;  // the update pass can apply the W-update in its prologue (r <= 8 pass)
   bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
@@ -103,6 +104,7 @@ void classify_stage(Stage& s, int precision) {
     s.kind = PASS_GENERIC;
   }
   s.fused = s.kind == PASS_S || s.kind == PASS_L;
+  s.pro_ok = s.kind == PASS_S && s.r <= 8;
   // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
   // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
   s.bf16 = precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
@@ -138,6 +140,7 @@ struct ntt_plan_s {
   size_t off_scal = 0, off_ints = 0, off_xb = 0, total = 0;
   size_t off_xt = 0, off_wp = 0, off_hp = 0;  // X^T, H^T, W^T of a transposed stage
   size_t off_s = 0;  // row-chunked stages: W^T X per row chunk, then a copy of H
+  size_t off_wb = 0;  // prologue-mode stages: the second W buffer
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
@@ -145,6 +148,7 @@ struct ntt_plan_s {
   struct GraphEntry {
     int stage, iters;
     bool bf;
+    int variant;  // 0: pass + W-update; 1, 2: prologue mode from the first / a later iteration
     const void *X, *H, *W, *ws;
     hipGraphExec_t exec;
   };
@@ -245,7 +249,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   size_t part_floats = 0;
   int gmax = 1, gres = 1, gfin = 1;
   size_t red_max = 0;
-  size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0;
+  size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0, wb_size = 0;
   for (int l = 1; l < d; ++l) {
     Stage& s = p->st[l - 1];
     s.m = p->eff[l - 1] * p->dims[l - 1];
@@ -293,6 +297,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
       hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
     }
     if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
+    if (s.pro_ok) wb_size = std::max(wb_size, (size_t)s.m * (size_t)s.r * sizeof(float));
     p->total_iters += cfg->max_iters;
   }
   gres = std::max(std::max(gres, gmax), kSumsqBlocks);
@@ -311,6 +316,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_wp = off; off = align_up(off + wp_size, 256);
   p->off_hp = off; off = align_up(off + hp_size, 256);
   p->off_s = off; off = align_up(off + s_size, 256);
+  p->off_wb = off; off = align_up(off + wb_size, 256);
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -350,6 +356,7 @@ struct Ctx {
   float* wp() const { return reinterpret_cast<float*>(ws + p->off_wp); }
   float* hp() const { return reinterpret_cast<float*>(ws + p->off_hp); }
   float* sbuf() const { return reinterpret_cast<float*>(ws + p->off_s); }
+  float* wb() const { return reinterpret_cast<float*>(ws + p->off_wb); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -411,6 +418,10 @@ struct NttJob {
   int bf_iters = 0;
   bool one_wg = false, final_known = false;
   bool trans = false;  // the stage iterates on X^T ~ H^T W^T (pa, fa refer to it)
+  // prologue mode: each pass applies the previous iteration's W-update (W_j alternates
+  // between the core buffer, j even, and the workspace buffer, j odd); one W-update
+  // launch at the end of the stage puts W_T into the core
+  bool pro = false, pro_done = false;
   double nx = 0.0;
   std::vector<double> fhist;
 
@@ -469,6 +480,8 @@ struct NttJob {
     trans = s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     const Stage& e = es();
     one_wg = !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
+    pro = s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    pro_done = false;
     const float eps = (float)cfg.eps;
     if (trans) {
       // X' = X^T (k x m), W' = H^T (k x r), H' = W^T (r x m); W'^T W' comes from the
@@ -521,11 +534,28 @@ struct NttJob {
     return launch_resid_sum(c.rpart(), resid_blocks(es()), c.scal(l) + SCAL_OBJ, slot, c.s);
   }
 
-  hipError_t graph_for(int n, bool bf, hipGraphExec_t* out) {
+  float* wbuf(int j) const { return (j & 1) ? c.wb() : W; }
+
+  // one prologue-mode iteration (0-based `it`): the pass, then the reduction of its partials
+  hipError_t pro_iter(hipStream_t q, int it, bool bf) {
+    PassArgs a = bf ? pa_bf : pa;
+    if (it > 0) {
+      a.Wprev = wbuf(it - 1);
+      a.Wout = wbuf(it);
+      a.red = c.red();
+    }
+    hipError_t e = run_pass(q, st(), a, true, false);
+    if (e != hipSuccess) return e;
+    return launch_reduce(fa, q);
+  }
+
+  hipError_t graph_for(int n, bool bf, int it0, hipGraphExec_t* out) {
     const PassArgs& pg = bf ? pa_bf : pa;
+    const int variant = pro ? (it0 == 0 ? 1 : 2) : 0;
+    const void* wkey = variant == 2 ? (const void*)wbuf(it0 - 1) : (const void*)pg.W;
     for (auto& g : p->graphs)
-      if (g.stage == l && g.iters == n && g.bf == bf && g.X == pg.X && g.H == pg.H &&
-          g.W == pg.W && g.ws == c.ws) {
+      if (g.stage == l && g.iters == n && g.bf == bf && g.variant == variant && g.X == pg.X &&
+          g.H == pg.H && g.W == wkey && g.ws == c.ws) {
         *out = g.exec;
         return hipSuccess;
       }
@@ -542,6 +572,10 @@ struct NttJob {
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int i = 0; i < n && le == hipSuccess; ++i) {
+      if (pro) {
+        le = pro_iter(cap_stream, it0 + i, bf);
+        continue;
+      }
       le = run_pass(cap_stream, es(), pg, true, false);
       if (le == hipSuccess) {
         FinArgs f2 = fa;
@@ -565,7 +599,7 @@ struct NttJob {
       (void)hipGraphExecDestroy(p->graphs.front().exec);
       p->graphs.erase(p->graphs.begin());
     }
-    p->graphs.push_back({l, n, bf, pg.X, pg.H, pg.W, c.ws, exec});
+    p->graphs.push_back({l, n, bf, variant, pg.X, pg.H, wkey, c.ws, exec});
     *out = exec;
     return hipSuccess;
   }
@@ -574,6 +608,7 @@ struct NttJob {
   // may end the stage early); *stage_done is set when no iterations remain.
   ntt_status iterate(int budget, bool* stage_done) {
     if (trans) return iterate_transposed(budget, stage_done);
+    if (pro) return iterate_prologue(budget, stage_done);
     const ntt_config& cfg = p->cfg;
     const Stage& s = st();
     hipStream_t q = c.s;
@@ -603,7 +638,7 @@ struct NttJob {
           while (block - n_done >= kGraphIters || (block - n_done > 1 && cfg.tol > 0.0)) {
             const int n = std::min(block - n_done, kGraphIters);
             hipGraphExec_t ex = nullptr;
-            HIP_TRY(graph_for(n, bf, &ex));
+            HIP_TRY(graph_for(n, bf, t + n_done, &ex));
             HIP_TRY(hipGraphLaunch(ex, q));
             n_done += n;
           }
@@ -648,6 +683,40 @@ struct NttJob {
     return NTT_OK;
   }
 
+  // The stage's T iterations in prologue mode (no stopping checks), then W_T.
+  ntt_status iterate_prologue(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    hipStream_t q = c.s;
+    const int T = cfg.max_iters;
+    while (budget > 0 && t < T) {
+      const bool bf = t < bf_iters;
+      int block = std::min(budget, T - t);
+      if (bf) block = std::min(block, bf_iters - t);
+      int n_done = 0;
+      while (block - n_done >= kGraphIters) {
+        hipGraphExec_t ex = nullptr;
+        HIP_TRY(graph_for(kGraphIters, bf, t + n_done, &ex));
+        HIP_TRY(hipGraphLaunch(ex, q));
+        n_done += kGraphIters;
+      }
+      for (; n_done < block; ++n_done) HIP_TRY(pro_iter(q, t + n_done, bf));
+      t += block;
+      budget -= block;
+      final_known = false;
+    }
+    if (t >= T && !pro_done) {
+      FinArgs ff = fa;
+      ff.W = wbuf(T - 1);
+      ff.Wout = ff.W == W ? nullptr : W;
+      ff.rpart = nullptr;
+      ff.trace = nullptr;
+      HIP_TRY(launch_wupdate_red(ff, q));
+      pro_done = true;
+    }
+    *stage_done = t >= T;
+    return NTT_OK;
+  }
+
   // The stage's T iterations on X' = X^T: H'-update of X' is the W-update of X and its
   // W'-update the H-update, so H_1 is the W'-update of (W'_0, H'_0), each of the next
   // T - 1 transposed iterations gives (W_t, H_{t+1}), and an H'-update alone gives W_T.
@@ -671,7 +740,7 @@ struct NttJob {
         int n_done = 0;
         while (block - n_done >= kGraphIters) {
           hipGraphExec_t ex = nullptr;
-          HIP_TRY(graph_for(kGraphIters, bf, &ex));
+          HIP_TRY(graph_for(kGraphIters, bf, t + n_done, &ex));
           HIP_TRY(hipGraphLaunch(ex, q));
           n_done += kGraphIters;
         }

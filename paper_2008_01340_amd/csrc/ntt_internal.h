@@ -30,6 +30,13 @@ struct PassArgs {
   int nchunks;          // row-chunked pass: number of row chunks
   float* Hs;            // row-chunked pass: copy of H taken in phase 1, read in phase 2 (r x k)
   int pair_groups;      // row-split and row-chunked passes: take column groups in pairs
+  // W-update in the prologue (r <= 8 pass): when Wprev is not NULL, the pass first forms
+  // W = max(0, Wprev .* N_W ./ (Wprev G_H + eps)) and G_W = W^T W from red (N_W = X H^T as
+  // m x r, then G_H = H H^T as r x r, FP64) and uses them instead of W and GW; workgroup 0
+  // also stores W to Wout.
+  const float* Wprev;
+  float* Wout;
+  const double* red;
 };
 
 // Reduction of the pass partials and the W-update.
@@ -45,6 +52,7 @@ struct FinArgs {
   const double* rpart;  // residual partials of this pass (NULL when none)
   double* trace;   // where to store the residual objective (NULL: do not store)
   float eps;
+  float* Wout;     // where the new W goes (NULL: W is updated in place)
 };
 
 // A whole stage of MU iterations in one workgroup (small unfoldings).
@@ -104,6 +112,11 @@ hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chun
 // X H^T and H H^T partials alone (column chunks of `chunk`), as the generic pass writes them
 hipError_t launch_xht_partials(const PassArgs& a, int rp, int gxht, int64_t chunk, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s);
+// The partial reduction of launch_finalize alone (into f.red), for passes that apply the
+// W-update in their prologue.
+hipError_t launch_reduce(const FinArgs& f, hipStream_t s);
+// The W-update of launch_finalize alone, from the reduced partials in f.red.
+hipError_t launch_wupdate_red(const FinArgs& f, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s);
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);

@@ -60,6 +60,53 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ float zmask(float v, bool ok) { return v * (ok ? 1.f : 0.f); }
 __device__ __forceinline__ double zmask(double v, bool ok) { return v * (ok ? 1.0 : 0.0); }
 
+__device__ __forceinline__ v4d mfma16_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One row of the W-update in FP64 on FP32 data (shared by k_wupdate and the pass
+// prologues, so that both give the same bits): out[c] = max(0, w[c] n[c] / (sum_q w[q]
+// G_H[q][c] + eps)) for c < r, 0 beyond; *dot accumulates <out, n>.
+template <int RB>
+__device__ __forceinline__ void wupdate_row(const float (&wrow)[RB], const double (&nrow)[RB],
+                                            const double (*sGH)[RB + 1], int r, float eps,
+                                            float* out, double* dot) {
+#pragma unroll
+  for (int c = 0; c < RB; ++c) {
+    double dw = 0.0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
+    const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)eps));
+    const float wf = (c < r) ? (float)wn : 0.f;
+    out[c] = wf;
+    *dot += (double)wf * nrow[c];
+  }
+}
+
+// Wavefront w's part of the Gram of the rows in LDS (FP64 MFMA, 16 x 16 x 4 tiles): rows
+// 64 w + 4 st + (0..3) for st = 0, 1, ..., in order, stopping at NROWS (rows from the
+// first zero row on contribute exact zeros, so stopping early does not change the bits).
+template <int RB, int NT, int NROWS>
+__device__ __forceinline__ void gram_rows_f64(const float (*sWc)[RB + 1], v4d (&acc)[NT][NT],
+                                              int w, int a, int b) {
+#pragma unroll 4
+  for (int st = 0; st < 16; ++st) {
+    if (64 * w + 4 * st >= NROWS) break;
+    const int row = 64 * w + 4 * st + b;
+    double opnd[NT];
+#pragma unroll
+    for (int h = 0; h < NT; ++h) {
+      const int c = 16 * h + a;
+      opnd[h] = (c < RB) ? (double)sWc[row][c < RB ? c : 0] : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < NT; ++h)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[h][q] = mfma16_f64(opnd[h], opnd[q], acc[h][q]);
+  }
+}
+
+
 // ------------------------------------------------------------------ SplitMix64 init
 // Value i of stream `tag`: SplitMix64 finaliser of seed + GAMMA (tag 2^32 + i + 1);
 // uniform = top 24 bits * 2^-24 (exact in FP32).
@@ -518,37 +565,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   const int m = p.m, r = p.r;
   const int64_t k = p.k;
 
-  {
-    constexpr int NWL = (16 * MPAD + 255) / 256;
-    float wtmp[NWL];
-#pragma unroll
-    for (int t = 0; t < NWL; ++t) {
-      const int e = tid + 256 * t;
-      const int i = e / 16, c = e % 16;
-      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
-      wtmp[t] = zmask(v, e < 16 * MPAD && i < m && c < r);
-    }
-#pragma unroll
-    for (int t = 0; t < NWL; ++t) {
-      const int e = tid + 256 * t;
-      if (e < 16 * MPAD) sWt[e % 16][e / 16] = wtmp[t];
-    }
-    if (tid < 64) {
-      const int c = tid >> 3, q = tid & 7;
-      sG[c][q] = p.GW[c * 16 + q];  // zero beyond r
-    }
-  }
-  __syncthreads();
-
-  v4f accW[MB];     // X H_new^T: lane (a,b) reg i -> row 16*blk+4b+i, rank a
-  float pg[4][4];   // G_H block of this lane
-#pragma unroll
-  for (int i = 0; i < MB; ++i) accW[i] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pg[i][q] = 0.f;
-
+  // first group's loads go out before the W set-up, whose latency they then overlap
   const int64_t ngroups = (k + 15) >> 4;
   const int64_t wstride = (int64_t)gridDim.x * 4;
   const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
@@ -599,6 +616,93 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   float xn[MB][4], hn_[4];
   if (g < ngroups) load_group(g, xn, hn_);
 #endif
+  if (p.Wprev) {
+    // W-update of the previous iteration (the rows of k_wupdate, one thread per row; the
+    // Gram by wavefront 0, which holds every row since m <= 64), then W^T and G_W to LDS
+    __shared__ float sWc[MPAD][9];
+    __shared__ double sGH[8][9];
+    __shared__ double sGW[8][9];
+    float wrow[8];
+    double nrow[8];
+    {
+      const int64_t base = (int64_t)min(tid, m - 1) * r;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int qc = min(q, r - 1);
+        wrow[q] = zmask(p.Wprev[base + qc], q < r);
+        nrow[q] = zmask(p.red[base + qc], q < r);
+      }
+    }
+    const int64_t mr = (int64_t)m * r;
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sGH[c][q] = zmask(p.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
+    }
+    __syncthreads();
+    if (tid < MPAD) {
+      if (tid < m) {
+        double dot = 0.0;
+        wupdate_row<8>(wrow, nrow, sGH, r, p.eps, sWc[tid], &dot);
+        if (blockIdx.x == 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (c < r) p.Wout[(int64_t)tid * r + c] = sWc[tid][c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sWc[tid][c] = 0.f;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      v4d acc[1][1] = {{v4d{0.0, 0.0, 0.0, 0.0}}};
+      gram_rows_f64<8, 1, MPAD>(sWc, acc, 0, a, b);
+      // the other wavefronts of k_wupdate add exact zeros; value i of lane (a, b) is
+      // row 4 i + b, column a
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * i + b < 8 && a < 8) sGW[4 * i + b][a] = acc[0][0][i];
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * MPAD; e += 256) {
+      const int i = e / 16, c = e % 16;
+      sWt[c][i] = c < 8 ? sWc[i][c < 8 ? c : 0] : 0.f;
+    }
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sG[c][q] = (c < r && q < r) ? (float)sGW[c][q] : 0.f;
+    }
+  } else {
+    constexpr int NWL = (16 * MPAD + 255) / 256;
+    float wtmp[NWL];
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      const int i = e / 16, c = e % 16;
+      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
+      wtmp[t] = zmask(v, e < 16 * MPAD && i < m && c < r);
+    }
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      if (e < 16 * MPAD) sWt[e % 16][e / 16] = wtmp[t];
+    }
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sG[c][q] = p.GW[c * 16 + q];  // zero beyond r
+    }
+  }
+  __syncthreads();
+
+  v4f accW[MB];     // X H_new^T: lane (a,b) reg i -> row 16*blk+4b+i, rank a
+  float pg[4][4];   // G_H block of this lane
+#pragma unroll
+  for (int i = 0; i < MB; ++i) accW[i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pg[i][q] = 0.f;
+
   for (; g < ngroups; g += wstride) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
@@ -1742,9 +1846,6 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const float* __restric
   }
 }
 
-__device__ __forceinline__ v4d mfma16_f64(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
 //     and G_H = H H^T, 256 rows at a time, one thread per row (rows are independent,
@@ -1815,39 +1916,18 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
     if (i < m) {
       if (i0 > 0) load_row(i);
       const int64_t base = (int64_t)i * r;
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        double dw = 0.0;
-#pragma unroll
-        for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
-        const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)f.eps));
-        const float wf = (c < r) ? (float)wn : 0.f;
-        sWc[tid][c] = wf;
-        dot_wn += (double)wf * nrow[c];
-      }
+      wupdate_row<RB>(wrow, nrow, sGH, r, f.eps, sWc[tid], &dot_wn);
+      float* wdst = f.Wout ? f.Wout : f.W;
 #pragma unroll
       for (int c = 0; c < RB; ++c)
-        if (c < r) f.W[base + c] = sWc[tid][c];
+        if (c < r) wdst[base + c] = sWc[tid][c];
     } else {
 #pragma unroll
       for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
     }
     __syncthreads();
     // this wavefront's 64 rows of the chunk, four per MFMA step (rows past m are zero)
-#pragma unroll 4
-    for (int st = 0; st < 16; ++st) {
-      const int row = 64 * w + 4 * st + b;
-      double opnd[NT];
-#pragma unroll
-      for (int h = 0; h < NT; ++h) {
-        const int c = 16 * h + a;
-        opnd[h] = (c < RB) ? (double)sWc[row][c < RB ? c : 0] : 0.0;
-      }
-#pragma unroll
-      for (int h = 0; h < NT; ++h)
-#pragma unroll
-        for (int q = 0; q < NT; ++q) acc[h][q] = mfma16_f64(opnd[h], opnd[q], acc[h][q]);
-    }
+    gram_rows_f64<RB, NT, 256>(sWc, acc, w, a, b);
     __syncthreads();
   }
   // the four wavefronts' Grams, added in order
@@ -2299,6 +2379,20 @@ hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
   if (f.r <= 8) return launch_wupdate<8>(f, fused, s);
   if (f.r <= 16) return launch_wupdate<16>(f, fused, s);
   return launch_wupdate<32>(f, fused, s);
+}
+
+hipError_t launch_wupdate_red(const FinArgs& f, hipStream_t s) {
+  if (f.r <= 8) return launch_wupdate<8>(f, false, s);
+  if (f.r <= 16) return launch_wupdate<16>(f, false, s);
+  return launch_wupdate<32>(f, false, s);
+}
+
+hipError_t launch_reduce(const FinArgs& f, hipStream_t s) {
+  if (f.G < 1 || f.G > kMaxReduceG) return hipErrorInvalidValue;
+  const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
+  k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
