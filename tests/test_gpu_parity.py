@@ -332,7 +332,24 @@ def test_full_size_32pow5_properties_and_sampled_parity():
         assert rel(host(b.cores[0]).reshape(32, 8), W1) <= TOL
         d3 = ntt.decompose(dev(X.astype(np.float32)), (1, 8, 1), t + 1, init_W=[dev(W0)], init_H=[dev(H0)])
         assert rel(host(d3.cores[1]).reshape(8, -1), H1) <= TOL
+    # stage 2 as the benchmark runs it (256 x 32768: rows split over waves, the W-update
+    # applied in the next pass's prologue): the same one-step check from the GPU's iterates
+    s1 = ntt.decompose(dev(X.astype(np.float32)), (1, 8, 1), w.iters,
+                       init_W=[dev(O.init_factors(w.seed, 1, 32, 8, X.shape[1])[0])],
+                       init_H=[dev(O.init_factors(w.seed, 1, 32, 8, X.shape[1])[1])])
+    X2 = host(s1.cores[1]).reshape(256, -1)
+    W20, H20 = O.init_factors(w.seed, 2, 256, 8, X2.shape[1])
+    X2d = dev(X2.astype(np.float32))
+    for t in (1, 30):
+        a2 = ntt.decompose(X2d, (1, 8, 1), t, init_W=[dev(W20)], init_H=[dev(H20)])
+        b2 = ntt.decompose(X2d, (1, 8, 1), t + 1, init_W=[dev(W20)], init_H=[dev(H20)])
+        W1, H1 = O.mu_step(X2, host(a2.cores[0]).reshape(256, 8), host(a2.cores[1]).reshape(8, -1), w.eps)
+        assert rel(host(b2.cores[0]).reshape(256, 8), W1) <= TOL, t
+        assert rel(host(b2.cores[1]).reshape(8, -1), H1) <= TOL, t
     res = ntt.decompose(Ad, w.target_ranks, w.iters, seed=w.seed, record_objective=True)
+    fast = ntt.decompose(Ad, w.target_ranks, w.iters, seed=w.seed)
+    for cr, cf in zip(res.cores, fast.cores):
+        assert rel(host(cf), host(cr)) <= 1e-4  # 500 iterations per stage, chained
     f = host(res.trace).reshape(4, w.iters)
     for l in range(4):
         assert np.all(np.diff(f[l]) <= 1e-6 * f[l][:-1]), l
