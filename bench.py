@@ -26,10 +26,10 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8<2> on 768
-# workgroups): rocprofv3 FETCH_SIZE (84,958.6 KiB) and WRITE_SIZE (35,142.5 KiB) per
-# dispatch, scaled by what the same counters read for a plain 1 GiB copy (x2.00, x1.00).
-# Taken on the current pass kernel; re-measure whenever that kernel changes.
-MEASURED_TRAFFIC = {"tt32x5_r8": 173.995e6 + 35.986e6}
+# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (84,245.1 KiB) and WRITE_SIZE
+# (35,238.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
+# copy (x2.00, x1.00).  Taken on the current pass kernel; re-measure when it changes.
+MEASURED_TRAFFIC = {"tt32x5_r8": 172.534e6 + 36.084e6}
 
 
 def parse():
