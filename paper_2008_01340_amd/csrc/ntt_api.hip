@@ -84,17 +84,26 @@ void classify_stage(Stage& s, int precision) {
   const int64_t gcap = std::max<int64_t>(
       256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
   s.cls = pass_L_class(s.m, s.rp);
-  if (s.m <= 32) {
+  if (s.m <= 32 || (s.m <= 128 && s.rp == 16 && ngroups >= 1024)) {
+    // one wavefront per 16-column group with all rows in registers: faster than splitting
+    // the rows over wavefronts up to 128 rows (no per-group barrier or cross-wave sum),
+    // once there are enough groups to occupy the GPU with one wavefront each
     s.kind = PASS_S;
-    s.mb = s.m <= 16 ? 1 : 2;
-    // the r <= 8 pass keeps three workgroups per CU resident: a grid of one full round
-    // (768 on 256 CUs) avoids a partly filled second round
-    const int64_t cap = s.r <= 8 ? std::min<int64_t>(gcap, 768) : gcap;
+    s.mb = s.m <= 16 ? 1 : (s.m <= 32 ? 2 : (s.m <= 64 ? 4 : 8));
+    // a grid of one resident round (workgroups per CU x 256 CUs) avoids a partly filled
+    // second round: three per CU for the r <= 8 pass and for 4 row blocks, two for 8
+    int64_t cap = gcap;
+    if (s.mb <= 2 && s.r <= 8) cap = std::min<int64_t>(gcap, 768);
+    if (s.mb == 4) cap = std::min<int64_t>(gcap, 768);
+    if (s.mb == 8) cap = std::min<int64_t>(gcap, 512);
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, cap));
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
     s.pairs = ngroups >= 512;  // column groups in pairs once there are enough of them
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap));
+    // measured best near 512 workgroups; partials up to ~25% of the X bytes
+    const int64_t gcap_l = std::max<int64_t>(
+        256, std::min<int64_t>(512, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_l));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
     s.kind = PASS_C;
     s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
@@ -104,11 +113,12 @@ void classify_stage(Stage& s, int precision) {
     s.kind = PASS_GENERIC;
   }
   s.fused = s.kind == PASS_S || s.kind == PASS_L;
-  s.pro_ok = s.kind == PASS_S && s.r <= 8;
-  // BF16 X is read by the r <= 8 pass (m <= 32) and the row-split pass; stages the
-  // single-workgroup kernel takes (small unfoldings) and the generic path stay FP32
+  s.pro_ok = s.kind == PASS_S && s.r <= 8 && s.m <= 32;
+  // BF16 X is read by the S passes at rank padding 16, the row-split and the row-chunked
+  // passes; stages the single-workgroup kernel takes (small unfoldings), the S pass at
+  // padding 32 and the generic path stay FP32
   s.bf16 = precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
-           (s.kind == PASS_L || s.kind == PASS_C || (s.kind == PASS_S && s.r <= 8));
+           (s.kind == PASS_L || s.kind == PASS_C || (s.kind == PASS_S && s.rp == 16));
   const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
   s.part_stride = align_up(E, 64);
 }

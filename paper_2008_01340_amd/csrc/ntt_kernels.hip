@@ -262,7 +262,7 @@ __device__ __forceinline__ bool x_aligned(const PassArgs& p) {
 // RESID : accumulate sum (X - W H_in)^2 in FP64 over the incoming W, H.
 // Per-workgroup partial (written when UPDATE): X H_new^T as m x r, then H_new H_new^T
 // as r x r, both row-major and compact.
-template <int RP, int MB, bool UPDATE, bool RESID>
+template <int RP, int MB, bool UPDATE, bool RESID, bool XBF = false>
 __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   constexpr int NH = RP / 16;  // 16-row halves of the padded rank
   constexpr int MPAD = 16 * MB;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
 
   const int64_t ngroups = (k + 15) >> 4;
   const int64_t wstride = (int64_t)gridDim.x * 4;
-  const bool vec_ok = ((k & 3) == 0) && ((reinterpret_cast<uintptr_t>(p.X) & 15) == 0) &&
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
                       ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
   float* sXw = sX[w];
   float* sHw = sHn[w];
@@ -337,12 +337,12 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
 #pragma unroll
       for (int blk = 0; blk < MB; ++blk) {
         const int row = 16 * blk + a;
-        const float4 v = *reinterpret_cast<const float4*>(p.X + (int64_t)min(row, m - 1) * k + j0 + 4 * b);
+        const float4 v = ldx4<XBF>(p, (int64_t)min(row, m - 1) * k + j0 + 4 * b);
         const bool ok = row < m;
-        xr[blk][0] = ok ? v.x : 0.f;
-        xr[blk][1] = ok ? v.y : 0.f;
-        xr[blk][2] = ok ? v.z : 0.f;
-        xr[blk][3] = ok ? v.w : 0.f;
+        xr[blk][0] = zmask(v.x, ok);
+        xr[blk][1] = zmask(v.y, ok);
+        xr[blk][2] = zmask(v.z, ok);
+        xr[blk][3] = zmask(v.w, ok);
       }
     } else {
 #pragma unroll
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t col = j0 + 4 * b + q;
-          const float v = p.X[(int64_t)min(row, m - 1) * k + min(col, k - 1)];
+          const float v = ldx<XBF>(p, (int64_t)min(row, m - 1) * k + min(col, k - 1));
           xr[blk][q] = zmask(v, row < m && col < k);
         }
       }
@@ -2174,7 +2174,14 @@ hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStre
 
 template <int RP, int MB>
 static hipError_t pass_fused_mb(const PassArgs& a, int grid, bool update, bool resid, hipStream_t s) {
-  if (update && resid) k_mu_pass<RP, MB, true, true><<<grid, 256, 0, s>>>(a);
+  if (a.Xb != nullptr) {
+    if constexpr (RP == 16) {
+      if (!update || resid) return hipErrorInvalidValue;  // BF16 X: update passes only
+      k_mu_pass<RP, MB, true, false, true><<<grid, 256, 0, s>>>(a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (update && resid) k_mu_pass<RP, MB, true, true><<<grid, 256, 0, s>>>(a);
   else if (update) k_mu_pass<RP, MB, true, false><<<grid, 256, 0, s>>>(a);
   else k_mu_pass<RP, MB, false, true><<<grid, 256, 0, s>>>(a);
   NTT_CHECK_LAUNCH();
@@ -2196,7 +2203,7 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
 
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              hipStream_t s) {
-  if (rp == 16 && a.r <= 8 && update && !resid) {
+  if (rp == 16 && a.r <= 8 && mb <= 2 && update && !resid) {
     const bool xb = a.Xb != nullptr;
     switch (mb) {
       case 1:
@@ -2212,9 +2219,10 @@ hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool u
     NTT_CHECK_LAUNCH();
     return hipSuccess;
   }
-  if (a.Xb != nullptr) return hipErrorInvalidValue;  // BF16 X only in the r <= 8 and row-split passes
-  return rp == 16 ? pass_fused_rp<16>(a, mb, grid, update, resid, s)
-                  : pass_fused_rp<32>(a, mb, grid, update, resid, s);
+  if (a.Wprev != nullptr) return hipErrorInvalidValue;  // W-update prologue: r <= 8 pass only
+  if (rp == 16) return pass_fused_rp<16>(a, mb, grid, update, resid, s);
+  if (a.Xb != nullptr) return hipErrorInvalidValue;  // BF16 X: rank padding 16 only
+  return pass_fused_rp<32>(a, mb, grid, update, resid, s);
 }
 
 template <int RP, int MBW, int NW>

@@ -87,6 +87,8 @@ SHAPES = [
     # enough column groups (>= 512, an odd count) for workgroups to take them in pairs:
     # rows split over waves, and rows in chunks
     (100, 9000, 12), (1100, 8200, 5),
+    # one wavefront per group with 4 and 8 row blocks (33..128 rows, >= 1024 groups)
+    (60, 17000, 7), (120, 16500, 14),
 ]
 
 
