@@ -151,6 +151,7 @@ struct ntt_plan_s {
   size_t off_xt = 0, off_wp = 0, off_hp = 0;  // X^T, H^T, W^T of a transposed stage
   size_t off_s = 0;  // row-chunked stages: W^T X per row chunk, then a copy of H
   size_t off_wb = 0;  // prologue-mode stages: the second W buffer
+  size_t off_gpart = 0;  // W-update over row blocks: per-block Gram parts
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
@@ -260,6 +261,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   int gmax = 1, gres = 1, gfin = 1;
   size_t red_max = 0;
   size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0, wb_size = 0;
+  int64_t m_max = 1;
   for (int l = 1; l < d; ++l) {
     Stage& s = p->st[l - 1];
     s.m = p->eff[l - 1] * p->dims[l - 1];
@@ -299,6 +301,8 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     }
     const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
     red_max = std::max(red_max, E);
+    m_max = std::max(m_max, s.m);
+    if (s.trans_ok) m_max = std::max(m_max, p->tst[l - 1].m);
     gmax = std::max(gmax, s.G);
     gfin = std::max(gfin, s.G);
     part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
@@ -327,6 +331,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_hp = off; off = align_up(off + hp_size, 256);
   p->off_s = off; off = align_up(off + s_size, 256);
   p->off_wb = off; off = align_up(off + wb_size, 256);
+  p->off_gpart = off; off = align_up(off + (size_t)((m_max + 255) / 256) * (32 * 32 + 1) * sizeof(double), 256);
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -367,6 +372,7 @@ struct Ctx {
   float* hp() const { return reinterpret_cast<float*>(ws + p->off_hp); }
   float* sbuf() const { return reinterpret_cast<float*>(ws + p->off_s); }
   float* wb() const { return reinterpret_cast<float*>(ws + p->off_wb); }
+  double* gpart() const { return reinterpret_cast<double*>(ws + p->off_gpart); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -517,6 +523,7 @@ struct NttJob {
     fa.m = (int)e.m;
     fa.r = e.r;
     fa.red = c.red();
+    fa.gpart = c.gpart();
     fa.W = trans ? c.wp() : W;
     fa.GW = c.gw();
     fa.scal = c.scal(l);

@@ -53,6 +53,7 @@ struct FinArgs {
   double* trace;   // where to store the residual objective (NULL: do not store)
   float eps;
   float* Wout;     // where the new W goes (NULL: W is updated in place)
+  double* gpart;   // m > 256: per-block parts of W'^T W' and <W', X H^T>, ceil(m/256) x (32*32+1)
 };
 
 // A whole stage of MU iterations in one workgroup (small unfoldings).

@@ -1971,6 +1971,118 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
   }
 }
 
+// W-update for m > 256 rows, over blocks: block j updates rows [256 j, 256 j + 256) as
+// k_wupdate does (same row code), and writes its part of G_W' = W'^T W' (FP64 MFMA over
+// its rows by four wavefronts, added in order) and of <W', N_W> to gpart[j]
+// (RB RB + 1 doubles); k_wupdate_gram then adds the blocks' parts in block order and
+// writes G_W and the monitor.  Entries are read from `red`.
+template <int RB>
+__global__ __launch_bounds__(256) void k_wupdate_rows(FinArgs f, double* __restrict__ gpart) {
+  constexpr int NT = (RB + 15) / 16;
+  __shared__ double sGH[RB][RB + 1];
+  __shared__ double sGp[4][NT * NT][64][4];
+  __shared__ float sWc[256][RB + 1];
+  __shared__ double sRed[4];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = f.m, r = f.r;
+  const int64_t mr = (int64_t)m * r;
+  const int i = blockIdx.x * 256 + tid;
+  float wrow[RB];
+  double nrow[RB];
+  {
+    const int64_t base = (int64_t)min(i, m - 1) * r;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int qc = min(q, r - 1);
+      wrow[q] = zmask(f.W[base + qc], q < r);
+      nrow[q] = zmask(f.red[base + qc], q < r);
+    }
+  }
+  for (int pidx = tid; pidx < RB * RB; pidx += 256) {
+    const int c = pidx / RB, q = pidx % RB;
+    sGH[c][q] = zmask(f.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
+  }
+  __syncthreads();
+  double dot_wn = 0.0;
+  if (i < m) {
+    wupdate_row<RB>(wrow, nrow, sGH, r, f.eps, sWc[tid], &dot_wn);
+    float* wdst = f.Wout ? f.Wout : f.W;
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+      if (c < r) wdst[(int64_t)i * r + c] = sWc[tid][c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
+  }
+  __syncthreads();
+  v4d acc[NT][NT];
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  gram_rows_f64<RB, NT, 256>(sWc, acc, w, a, b);
+#pragma unroll
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) sGp[w][h * NT + q][lane][ii] = acc[h][q][ii];
+  dot_wn = wave_sum(dot_wn);
+  if (lane == 0) sRed[w] = dot_wn;
+  __syncthreads();
+  double* dst = gpart + (int64_t)blockIdx.x * (RB * RB + 1);
+  for (int pidx = tid; pidx < NT * NT * 256; pidx += 256) {
+    const int tq = pidx >> 8, l = (pidx >> 2) & 63, ii = pidx & 3;
+    const double sg = ((sGp[0][tq][l][ii] + sGp[1][tq][l][ii]) + sGp[2][tq][l][ii]) + sGp[3][tq][l][ii];
+    // FP64 16 x 16 x 4 result layout: value ii of lane (a, b) is row 4 ii + b, column a
+    const int row = 16 * (tq / NT) + 4 * ii + (l >> 4), col = 16 * (tq % NT) + (l & 15);
+    if (row < RB && col < RB) dst[row * RB + col] = sg;
+  }
+  if (tid == 0) dst[RB * RB] = ((sRed[0] + sRed[1]) + sRed[2]) + sRed[3];
+}
+
+template <int RB>
+__global__ __launch_bounds__(256) void k_wupdate_gram(FinArgs f, const double* __restrict__ gpart, int nb) {
+  __shared__ double sGW[RB * RB];
+  __shared__ double sDot;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r = f.r;
+  const int64_t mr = (int64_t)f.m * r;
+  for (int pidx = tid; pidx < RB * RB + 1; pidx += 256) {
+    double sg = 0.0;
+    for (int j = 0; j < nb; ++j) sg += gpart[(int64_t)j * (RB * RB + 1) + pidx];
+    if (pidx < RB * RB) sGW[pidx] = sg;
+    else sDot = sg;
+  }
+  double rsum = 0.0;
+  if (f.rpart && tid < 64) {
+    for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
+    rsum = wave_sum(rsum);
+  }
+  __syncthreads();
+  const int rp = r <= 16 ? 16 : 32;
+  for (int pidx = tid; pidx < rp * rp; pidx += 256) {
+    const int c = pidx / rp, q = pidx % rp;
+    f.GW[pidx] = (c < RB && q < RB && c < r && q < r) ? (float)sGW[c * RB + q] : 0.f;
+  }
+  // monitor: <W'^T W', H H^T> over the first wavefront
+  double gg = 0.0;
+  if (tid < 64)
+    for (int pidx = tid; pidx < r * r; pidx += 64)
+      gg += sGW[(pidx / r) * RB + (pidx % r)] * f.red[mr + pidx];
+  gg = wave_sum(gg);
+  if (tid == 0) {
+    f.scal[SCAL_MONITOR] = 0.5 * (f.scal[SCAL_NX2] - 2.0 * sDot + gg);
+    if (f.rpart) {
+      const double obj = 0.5 * rsum;
+      f.scal[SCAL_OBJ] = obj;
+      if (f.trace) f.trace[0] = obj;
+    }
+  }
+  (void)lane;
+}
+
 __global__ void k_zero_ints(int* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -2375,14 +2487,31 @@ static hipError_t launch_wupdate(const FinArgs& f, bool fused, hipStream_t s) {
   return hipSuccess;
 }
 
+template <int RB>
+static hipError_t launch_wupdate_blocks(const FinArgs& f, hipStream_t s) {
+  const int nb = (f.m + 255) / 256;
+  k_wupdate_rows<RB><<<nb, 256, 0, s>>>(f, f.gpart);
+  NTT_CHECK_LAUNCH();
+  k_wupdate_gram<RB><<<1, 256, 0, s>>>(f, f.gpart, nb);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
   (void)rp;
-  const bool fused = f.G <= 4;
+  const bool blocks = f.m > 256;  // rows over blocks (the one-block update loops otherwise)
+  const bool fused = f.G <= 4 && !blocks;
   if (!fused) {
     if (f.G > kMaxReduceG) return hipErrorInvalidValue;
     const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
     k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
     NTT_CHECK_LAUNCH();
+  }
+  if (blocks) {
+    if (!f.gpart) return hipErrorInvalidValue;
+    if (f.r <= 8) return launch_wupdate_blocks<8>(f, s);
+    if (f.r <= 16) return launch_wupdate_blocks<16>(f, s);
+    return launch_wupdate_blocks<32>(f, s);
   }
   if (f.r <= 8) return launch_wupdate<8>(f, fused, s);
   if (f.r <= 16) return launch_wupdate<16>(f, fused, s);
