@@ -223,6 +223,44 @@ def test_sweep_with_row_chunked_stage():
         assert rel(host(cf), host(cg)) <= TOL
 
 
+@pytest.mark.parametrize("m,k,r", [
+    (1, 5000, 1),     # one row (S pass, r <= 8)
+    (5000, 1, 1),     # one column: transposed stage of one row
+    (3, 7, 3),        # r = m: the whole stage in one workgroup
+    (2, 40000, 2),    # a single 16-row block, two ranks, many groups
+    (1500, 3, 2),     # tall and very thin: transposed, one column group
+])
+def test_degenerate_shapes_match_oracle(m, k, r):
+    say(f"case: degenerate d=2 NMF m={m} k={k} r={r}")
+    rng = np.random.default_rng(m + 7 * k)
+    X = (rng.random((m, k)) + 0.05).astype(np.float32)
+    W0, H0 = O.init_factors(3, 1, m, r, k)
+    T = 40
+    ref = O.mu_nmf(X.astype(np.float64), W0, H0, T)
+    res = ntt.decompose(dev(X), (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)])
+    assert rel(host(res.cores[0]).reshape(m, r), ref["W"]) <= TOL
+    assert rel(host(res.cores[1]).reshape(r, k), ref["H"]) <= TOL
+
+
+def test_zero_rows_and_columns_match_oracle():
+    say("case: X with all-zero rows and columns (factor entries driven to 0 by the clamp)")
+    rng = np.random.default_rng(11)
+    m, k, r = 48, 3000, 6
+    X = (rng.random((m, k)) + 0.05).astype(np.float32)
+    X[[3, 17, 40], :] = 0.0
+    X[:, ::7] = 0.0
+    W0, H0 = O.init_factors(5, 1, m, r, k)
+    T = 60
+    ref = O.mu_nmf(X.astype(np.float64), W0, H0, T, record_objective=True)
+    res = ntt.decompose(dev(X), (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)], record_objective=True)
+    f_gpu = host(res.trace)
+    assert np.all(obj_close(f_gpu, ref["objective"][1:], ref["norm_x"] ** 2))
+    Wg = host(res.cores[0]).reshape(m, r)
+    assert rel(Wg, ref["W"]) <= TOL
+    assert np.all(Wg[[3, 17, 40], :] == 0.0)  # zero numerator, exact zero after one update
+    assert rel(host(res.cores[1]).reshape(r, k), ref["H"]) <= TOL
+
+
 def test_rank_clamping_matches_oracle():
     say("case: clamped ranks 3x4x5 requested (1,9,9,1)")
     dims = (3, 4, 5)
@@ -379,6 +417,8 @@ BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
     ((48, 48, 48, 48), (1, 16, 16, 16, 1), "absnormal", 0.01, 200),
     ((24, 30, 20, 36), (1, 6, 8, 5, 1), "mult", 0.01, 150),
     ((1200, 8, 8), (1, 6, 4, 1), "mult", 0.01, 150),  # stage 1 transposed (1200 x 64)
+    ((40, 40, 40, 30), (1, 32, 16, 8, 1), "mult", 0.01, 100),  # stage 2 row-chunked (1280 x 1200)
+    ((64, 32, 40, 40), (1, 16, 8, 6, 1), "mult", 0.01, 120),   # stage 1 on the S pass, 4 row blocks
 ])
 def test_bf16_mode_final_error_matches_oracle(dims, gen, noise, level, T):
     say(f"case: BF16 mode dims={dims} ranks={gen} T={T} tail=20")
