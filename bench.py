@@ -102,6 +102,30 @@ def precision_mode(ntt, S, torch):
     return out
 
 
+def paper_workload(ntt, S, torch):
+    """The paper's workload size on one GPU: 256^4 FP32 (17 GB) from rank-10 TT cores,
+    ranks 10, 100 MU iterations per stage; then the rank sweep r in {2, 4, 8, 16}."""
+    w = S.workload("tt256x4_r10")
+    A = _tt_on_gpu(ntt, S, torch, w)
+    progress("paper workload: 256^4 tensor formed on the device")
+    out = {"workload": f"{w.name}: {w.note}"}
+    for r in (10, 2, 4, 8, 16):
+        ranks = (1, r, r, r, 1)
+        plan = ntt.Plan(w.dims, ranks, w.iters, eps=w.eps, seed=w.seed)
+        res = ntt.decompose(A, ranks, w.iters, plan=plan, want_report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ntt.decompose(A, ranks, w.iters, plan=plan, cores=res.cores)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[f"r{r}"] = {"ms": ms, "gflop_per_s": res.report["total_gflop"] / (ms * 1e-3),
+                        "gflop": res.report["total_gflop"], "rel_error": ntt.rel_error(A, res.cores),
+                        "stage_ms": res.report["ms"], "compression": res.report["compression_ratio"]}
+        progress(f"paper workload: ranks {r}: {ms:.1f} ms")
+    del A
+    return out
+
+
 def _tt_on_gpu(ntt, S, torch, w):
     cores = [torch.from_numpy(c).cuda() for c in S.random_cores(w.dims, w.gen_ranks, w.seed)]
     return ntt.reconstruct(cores)
@@ -287,6 +311,8 @@ def main():
         del A
         torch.cuda.empty_cache()
         out["precision_mode"] = precision_mode(ntt, S, torch)
+        torch.cuda.empty_cache()
+        out["paper_workload"] = paper_workload(ntt, S, torch)
         torch.cuda.empty_cache()
         out["batched"] = batched(ntt, S, torch)
         torch.cuda.empty_cache()

@@ -110,10 +110,22 @@ def objective(X, W, H) -> float:
     return 0.5 * float(np.sum(R * R))
 
 
+def update_H(X, W, H, eps):
+    """The H half of a MU iteration.  Column j of the result depends only on column j
+    of X and of H, so it may be applied to any subset of the columns."""
+    return np.maximum(0.0, H * (W.T @ X) / ((W.T @ W) @ H + eps))
+
+
+def update_W(XHt, HHt, W, eps):
+    """The W half of a MU iteration, from the products X H^T (m x r) and H H^T (r x r)
+    of the already updated H; X enters only through X H^T."""
+    return np.maximum(0.0, W * XHt / (W @ HHt + eps))
+
+
 def mu_step(X, W, H, eps):
     """One Lee-Seung MU iteration, H first then W, with max(0, .) and additive eps."""
-    H = np.maximum(0.0, H * (W.T @ X) / ((W.T @ W) @ H + eps))
-    W = np.maximum(0.0, W * (X @ H.T) / (W @ (H @ H.T) + eps))
+    H = update_H(X, W, H, eps)
+    W = update_W(X @ H.T, H @ H.T, W, eps)
     return W, H
 
 

@@ -45,6 +45,12 @@ ntt_status fail(ntt_status s, const std::string& msg) {
 #define NTT_MAX_PASS_BLOCKS 1024
 #endif
 constexpr int kMaxPassBlocks = NTT_MAX_PASS_BLOCKS;  // persistent grid of the fused pass
+#ifndef NTT_L_MAX_BLOCKS
+#define NTT_L_MAX_BLOCKS 768
+#endif
+// grid cap of the row-split pass with 4 waves (three 256-thread workgroups per CU are
+// resident at its register use: one full round on 256 CUs); 8-wave classes keep 512
+constexpr int kMaxLBlocks = NTT_L_MAX_BLOCKS;
 constexpr int kSumsqBlocks = 1024;
 constexpr int kGraphIters = 25;     // MU iterations per replayed graph
 constexpr size_t kMaxGraphs = 64;
@@ -100,9 +106,10 @@ void classify_stage(Stage& s, int precision) {
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
     s.pairs = ngroups >= 512;  // column groups in pairs once there are enough of them
-    // measured best near 512 workgroups; partials up to ~25% of the X bytes
+    // one resident round of workgroups; partials up to ~25% of the X bytes
     const int64_t gcap_l = std::max<int64_t>(
-        256, std::min<int64_t>(512, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
+        256, std::min<int64_t>(s.cls <= 2 ? kMaxLBlocks : 512,
+                               (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_l));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
     s.kind = PASS_C;

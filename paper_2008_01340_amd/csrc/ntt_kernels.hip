@@ -329,8 +329,12 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   float* sHw = sHn[w];
 
   // Loads of a 16-column group: X rows 16*blk + a, columns j0+4b .. j0+4b+3 (the A
-  // operand of X H^T) and H[16h+4b+kk][j0+a].  Addresses are clamped into the arrays
-  // and out-of-range values replaced by zero, so interior groups need no branches.
+  // operand of X H^T) and H[16h+4b+kk][j0+a].  Addresses are clamped into the arrays, so
+  // interior groups need no branches; their values are stored as loaded and the entries
+  // out of range are zeroed only when the group is processed (mask_group), so that no
+  // instruction waits on a prefetch still in flight.  (The two load paths must differ:
+  // identical plain loads in both would let the compiler merge them into one path of
+  // scalar loads.)
   auto load_group = [&](int64_t g, float (&xr)[MB][4], float (&hv)[NH][4]) {
     const int64_t j0 = g << 4;
     if (vec_ok && (j0 + 16 <= k)) {
@@ -338,13 +342,12 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
       for (int blk = 0; blk < MB; ++blk) {
         const int row = 16 * blk + a;
         const float4 v = ldx4<XBF>(p, (int64_t)min(row, m - 1) * k + j0 + 4 * b);
-        const bool ok = row < m;
-        xr[blk][0] = zmask(v.x, ok);
-        xr[blk][1] = zmask(v.y, ok);
-        xr[blk][2] = zmask(v.z, ok);
-        xr[blk][3] = zmask(v.w, ok);
+        xr[blk][0] = v.x;
+        xr[blk][1] = v.y;
+        xr[blk][2] = v.z;
+        xr[blk][3] = v.w;
       }
-    } else {
+    } else {  // ragged or unaligned group (rare): masked here
 #pragma unroll
       for (int blk = 0; blk < MB; ++blk) {
         const int row = 16 * blk + a;
@@ -356,21 +359,44 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
         }
       }
     }
-    const int64_t col = j0 + a;
-    const int64_t colc = min(col, k - 1);
+    const int64_t colc = min(j0 + a, k - 1);
 #pragma unroll
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int c = 16 * h + 4 * b + kk;
-        const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
-        hv[h][kk] = zmask(v, c < r && col < k);
+        hv[h][kk] = p.H[(int64_t)min(c, r - 1) * k + colc];
       }
   };
+  // zero the entries of a loaded group that lie outside X (rows >= m; a ragged group is
+  // masked as it is loaded) or H (rows >= r, columns >= k)
+  auto mask_group = [&](int64_t j0, bool full, float (&xr)[MB][4], float (&hv)[NH][4]) {
+    if (full) {
+#pragma unroll
+      for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xr[blk][q] = zmask(xr[blk][q], 16 * blk + a < m);
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        hv[h][kk] = zmask(hv[h][kk], 16 * h + 4 * b + kk < r && (full || j0 + a < k));
+  };
 
-  auto process_group = [&](int64_t g, const float (&xr)[MB][4], const float (&hv)[NH][4]) {
+  auto process_group = [&](int64_t g, const float (&xin)[MB][4], const float (&hin)[NH][4]) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
+    float xr[MB][4], hv[NH][4];
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xr[blk][q] = xin[blk][q];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hv[h][q] = hin[h][q];
+    mask_group(j0, full, xr, hv);
     // N_H = W^T X (M = rank, N = column, K = row) and the residual X - W H
     v4f nh[NH];
 #pragma unroll
@@ -917,21 +943,21 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 #pragma unroll
   for (int blk = 0; blk < MBW; ++blk) xrow[blk] = (int64_t)min(row0 + 16 * blk + a, m - 1) * k;
 
-  // loads of one 16-column group: this wave's X rows and the H tile (clamped addresses,
-  // out-of-range values zeroed where they could reach a result)
+  // loads of one 16-column group: this wave's X rows and the H tile, at clamped
+  // addresses; the values are kept as loaded until the group is processed (mask_group
+  // zeroes the out-of-range ones), so that no instruction waits on a prefetch in flight
   auto load_group = [&](int64_t g, float (&xr)[MBW][4], float (&hv)[NH][4]) {
     const int64_t j0 = g << 4;
     if (vec_ok && (j0 + 16 <= k)) {
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk) {
         const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
-        const bool ok = !RESID || (row0 + 16 * blk + a < m);
-        xr[blk][0] = ok ? v.x : 0.f;
-        xr[blk][1] = ok ? v.y : 0.f;
-        xr[blk][2] = ok ? v.z : 0.f;
-        xr[blk][3] = ok ? v.w : 0.f;
+        xr[blk][0] = v.x;
+        xr[blk][1] = v.y;
+        xr[blk][2] = v.z;
+        xr[blk][3] = v.w;
       }
-    } else {
+    } else {  // ragged or unaligned group (rare): masked here, so the two paths differ
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk)
 #pragma unroll
@@ -941,16 +967,26 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
           xr[blk][q] = zmask(v, col < k && row0 + 16 * blk + a < m);
         }
     }
-    const int64_t col = j0 + a;
-    const int64_t colc = min(col, k - 1);
+    const int64_t colc = min(j0 + a, k - 1);
 #pragma unroll
     for (int h = 0; h < NH; ++h)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int c = 16 * h + 4 * b + kk;
-        const float v = p.H[(int64_t)min(c, r - 1) * k + colc];
-        hv[h][kk] = zmask(v, c < r && col < k);
-      }
+      for (int kk = 0; kk < 4; ++kk) hv[h][kk] = p.H[(int64_t)min(16 * h + 4 * b + kk, r - 1) * k + colc];
+  };
+  // Out-of-range X rows reach a result only through the residual (a ragged group is
+  // masked as it is loaded); H entries past r or k are zeroed always.
+  auto mask_group = [&](int64_t j0, bool full, float (&xr)[MBW][4], float (&hv)[NH][4]) {
+    if (RESID && full) {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xr[blk][q] = zmask(xr[blk][q], row0 + 16 * blk + a < m);
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        hv[h][kk] = zmask(hv[h][kk], 16 * h + 4 * b + kk < r && (full || j0 + a < k));
   };
 
   float xn[MBW][4], hn_[NH][4];  // next group, loaded while the current one is processed
@@ -978,6 +1014,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) hv[h][q] = hn_[h][q];
     if (group_of(it + 1) < ngroups) load_group(group_of(it + 1), xn, hn_);
+    mask_group(j0, full, xr, hv);
     v4f nh[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) nh[h] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1202,26 +1239,20 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
 
   // X rows of the wave (rows past m: zero in phase 0, unused otherwise), the H tile
   // (phases 0 and 2) and the summed W^T X (phase 2) of group g
+  // (loaded values are kept as they are until the group is processed: mask_group then
+  // zeroes the out-of-range ones, so no instruction waits on a prefetch in flight)
   auto load_group = [&](int64_t g, float (&xr)[MBW][4], float (&hv)[NH][4], float (&sv)[NH][4]) {
     const int64_t j0 = g << 4;
     if (vec_ok && (j0 + 16 <= k)) {
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk) {
         const float4 v = ldx4<XBF>(p, xrow[blk] + j0 + 4 * b);
-        if (PH == 0) {
-          const bool ok = row0 + 16 * blk + a < m;
-          xr[blk][0] = zmask(v.x, ok);
-          xr[blk][1] = zmask(v.y, ok);
-          xr[blk][2] = zmask(v.z, ok);
-          xr[blk][3] = zmask(v.w, ok);
-        } else {
-          xr[blk][0] = v.x;
-          xr[blk][1] = v.y;
-          xr[blk][2] = v.z;
-          xr[blk][3] = v.w;
-        }
+        xr[blk][0] = v.x;
+        xr[blk][1] = v.y;
+        xr[blk][2] = v.z;
+        xr[blk][3] = v.w;
       }
-    } else {
+    } else {  // ragged or unaligned group (rare): masked here, so the two paths differ
 #pragma unroll
       for (int blk = 0; blk < MBW; ++blk)
 #pragma unroll
@@ -1231,27 +1262,38 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
           xr[blk][q] = zmask(v, col < k && row0 + 16 * blk + a < m);
         }
     }
-    const int64_t col = j0 + a;
-    const int64_t colc = min(col, k - 1);
+    const int64_t colc = min(j0 + a, k - 1);
     if (PH != 1 || (y == 0 && w == 0)) {
       const float* Hsrc = PH == 2 ? p.Hs : p.H;
 #pragma unroll
       for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int c = 16 * h + 4 * b + kk;
-          hv[h][kk] = zmask(Hsrc[(int64_t)min(c, r - 1) * k + colc], c < r && col < k);
-        }
+        for (int kk = 0; kk < 4; ++kk) hv[h][kk] = Hsrc[(int64_t)min(16 * h + 4 * b + kk, r - 1) * k + colc];
     }
     if (PH == 2) {
 #pragma unroll
       for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int c = 16 * h + 4 * b + kk;
-          sv[h][kk] = zmask(p.S[(int64_t)min(c, r - 1) * k + colc], c < r && col < k);
-        }
+        for (int kk = 0; kk < 4; ++kk) sv[h][kk] = p.S[(int64_t)min(16 * h + 4 * b + kk, r - 1) * k + colc];
     }
+  };
+  // X rows >= m matter to the residual (phase 0; a ragged group is masked as it is
+  // loaded); the H and S tiles past r or k are zeroed always
+  auto mask_group = [&](int64_t j0, bool full, float (&xr)[MBW][4], float (&hv)[NH][4], float (&sv)[NH][4]) {
+    if (PH == 0 && full) {
+#pragma unroll
+      for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xr[blk][q] = zmask(xr[blk][q], row0 + 16 * blk + a < m);
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const bool ok = 16 * h + 4 * b + kk < r && (full || j0 + a < k);
+        if (PH != 1 || (y == 0 && w == 0)) hv[h][kk] = zmask(hv[h][kk], ok);
+        if (PH == 2) sv[h][kk] = zmask(sv[h][kk], ok);
+      }
   };
 
   float xn[MBW][4], hn_[NH][4], sn[NH][4];
@@ -1283,6 +1325,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[h][q] = sn[h][q];
     if (group_of(it + 1) < ngroups) load_group(group_of(it + 1), xn, hn_, sn);
+    mask_group(j0, full, xr, hv, sv);
 
     if (PH != 2) {
       v4f nh[NH];

@@ -159,6 +159,11 @@ WORKLOADS = {
     "tt128x4_r16": Workload("tt128x4_r16", (128,) * 4, (1, 16, 16, 16, 1), (1, 16, 16, 16, 1),
                             200, 3, noise="absnormal", level=0.01, fp32_tail=20,
                             note="128^4 from U[0,1) rank-16 cores, +|N(0,0.01^2)|, T=200"),
+    # The paper's single-tensor workload size (Sec. IV): 256^4 in FP32 (16 GiB), TT ranks 10,
+    # 100 MU iterations per stage.  Generated exactly (no noise) from U[0,1) cores; the
+    # entries are best formed on the device from the cores (17 GB).
+    "tt256x4_r10": Workload("tt256x4_r10", (256,) * 4, (1, 10, 10, 10, 1), (1, 10, 10, 10, 1),
+                            100, 6, note="256^4 from U[0,1) rank-10 cores, T=100"),
 }
 
 

@@ -408,6 +408,83 @@ def test_full_size_32pow5_properties_and_sampled_parity():
     assert e_gpu < 0.05
 
 
+@pytest.mark.timeout(900)
+def test_full_size_256pow4_paper_workload_sampled_parity():
+    """The paper's workload size, 256^4 FP32 (2^32 entries: every flat index is past
+    32 bits), ranks 10, T = 100, launched as the benchmark launches it.
+
+    The oracle cannot hold this tensor in FP64 per test run, so stage 1 (256 x 2^24)
+    is checked one MU step at a time from the GPU's own iterate t: H_{t+1} on a sample
+    of columns (the H half acts on each column alone) and W_{t+1} from X H_{t+1}^T and
+    H_{t+1} H_{t+1}^T summed on the host in FP64 over column blocks.  Then the sweep:
+    non-increasing objective trace, non-negative cores, sampled reconstruction entries
+    (the corners included) equal to the Eq.(2) sum, and the fused Eq.(3) equal to an
+    FP64 sum over the whole tensor.
+    """
+    say("case: full size 256^4 ranks 10, T=100")
+    w = S.workload("tt256x4_r10")
+    gen = S.random_cores(w.dims, w.gen_ranks, w.seed)
+    Ad = ntt.reconstruct([dev(c) for c in gen])
+    n, r = 256, 10
+    k = n ** 3
+    X2 = Ad.view(n, k)
+    rng = np.random.default_rng(7)
+    cols = np.sort(rng.choice(k, 512, replace=False))
+    cols[0], cols[-1] = 0, k - 1
+    XJ = host(X2[:, torch.from_numpy(cols).to(DEV)])
+    for t in (1, 20):
+        a = ntt.decompose(X2, (1, r, 1), t, seed=w.seed)
+        full4 = ntt.decompose(Ad, w.target_ranks, t, seed=w.seed)
+        Wt = host(a.cores[0]).reshape(n, r)
+        assert np.array_equal(host(full4.cores[0]).reshape(n, r), Wt)
+        del full4
+        HtJ = host(a.cores[1].view(r, k)[:, torch.from_numpy(cols).to(DEV)])
+        del a
+        b = ntt.decompose(X2, (1, r, 1), t + 1, seed=w.seed)
+        H1 = b.cores[1].view(r, k)
+        H1J = host(H1[:, torch.from_numpy(cols).to(DEV)])
+        e_h = rel(H1J, O.update_H(XJ, Wt, HtJ, w.eps))
+        XHt = np.zeros((n, r))
+        HHt = np.zeros((r, r))
+        step = 1 << 20
+        for c0 in range(0, k, step):
+            xc = X2[:, c0:c0 + step].contiguous().cpu().double().numpy()
+            hc = H1[:, c0:c0 + step].contiguous().cpu().double().numpy()
+            XHt += xc @ hc.T
+            HHt += hc @ hc.T
+        e_w = rel(host(b.cores[0]).reshape(n, r), O.update_W(XHt, HHt, Wt, w.eps))
+        say(f"  t={t}: H sample rel {e_h:.3e}, W rel {e_w:.3e}")
+        assert e_h <= TOL and e_w <= TOL, t
+        del b, H1
+    res = ntt.decompose(Ad, w.target_ranks, w.iters, seed=w.seed, record_objective=True)
+    fast = ntt.decompose(Ad, w.target_ranks, w.iters, seed=w.seed)
+    for cr, cf in zip(res.cores, fast.cores):
+        assert rel(host(cf), host(cr)) <= 1e-4
+    del fast
+    f = host(res.trace).reshape(3, w.iters)
+    for l in range(3):
+        assert np.all(np.diff(f[l]) <= 1e-6 * f[l][:-1]), l
+    for c in res.cores:
+        assert float(c.min()) >= 0.0
+    cores = [host(c) for c in res.cores]
+    R = ntt.reconstruct(res.cores)
+    idxs = [(0, 0, 0, 0), (255, 255, 255, 255), (255, 0, 255, 0), (128, 255, 1, 254)]
+    idxs += [tuple(int(v) for v in rng.integers(0, n, 4)) for _ in range(4)]
+    for idx in idxs:
+        assert float(R[idx]) == pytest.approx(O.tt_element(cores, idx), rel=1e-5), idx
+    num = den = 0.0
+    A1, R1 = Ad.view(-1, 1 << 24), R.view(-1, 1 << 24)
+    for i in range(A1.shape[0]):
+        ad = A1[i].double()
+        num += float(((ad - R1[i].double()) ** 2).sum())
+        den += float((ad * ad).sum())
+    del R
+    e_gpu = ntt.rel_error(Ad, res.cores)
+    say(f"  rel err gpu {e_gpu:.6e} fp64 sum {math.sqrt(num / den):.6e}")
+    assert e_gpu == pytest.approx(math.sqrt(num / den), rel=1e-6)
+    assert e_gpu < 1.0
+
+
 # ------------------------------------------------------------------ a8: BF16 precision mode
 BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
 

@@ -212,6 +212,27 @@ def test_mu_h_first_order():
             assert math.isclose(W1[i, j], W0[i, j] * N[i, j] / (D[i, j] + 1e-12), rel_tol=1e-14)
 
 
+def test_mu_halves_are_column_separable_and_product_only():
+    # Sampled parity at sizes the oracle cannot hold relies on two facts of the MU rule:
+    # the H half acts on each column alone (column j of W^T X and of (W^T W) H involve
+    # column j only), and the W half sees X only through X H^T, which may be summed over
+    # column blocks.  Check both by entries on a small case.
+    X = _nonneg(7, 40, 11)
+    W0, H0 = O.init_factors(9, 1, 7, 3, 40)
+    W1, H1 = O.mu_step(X, W0, H0, 1e-12)
+    cols = [0, 5, 17, 39]
+    np.testing.assert_array_equal(O.update_H(X[:, cols], W0, H0[:, cols], 1e-12), H1[:, cols])
+    WtW = W0.T @ W0
+    for j in cols:
+        for c in range(3):
+            num = sum(W0[i, c] * X[i, j] for i in range(7))
+            den = sum(WtW[c, q] * H0[q, j] for q in range(3)) + 1e-12
+            assert math.isclose(H1[c, j], max(0.0, H0[c, j] * num / den), rel_tol=1e-13)
+    XHt = sum(X[:, c0:c0 + 8] @ H1[:, c0:c0 + 8].T for c0 in range(0, 40, 8))
+    HHt = sum(H1[:, c0:c0 + 8] @ H1[:, c0:c0 + 8].T for c0 in range(0, 40, 8))
+    np.testing.assert_allclose(O.update_W(XHt, HHt, W0, 1e-12), W1, rtol=1e-13)
+
+
 def test_gram_identity_equals_explicit_residual():
     X = _nonneg(15, 22, 8)
     W, H = _rng(9).random((15, 4)), _rng(10).random((4, 22))
