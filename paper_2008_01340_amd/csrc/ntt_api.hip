@@ -51,6 +51,10 @@ constexpr int kMaxPassBlocks = NTT_MAX_PASS_BLOCKS;  // persistent grid of the f
 // grid cap of the row-split pass with 4 waves (three 256-thread workgroups per CU are
 // resident at its register use: one full round on 256 CUs); 8-wave classes keep 512
 constexpr int kMaxLBlocks = NTT_L_MAX_BLOCKS;
+#ifndef NTT_LW_MIN_STEPS
+#define NTT_LW_MIN_STEPS 256
+#endif
+constexpr int64_t kLWMinSteps = NTT_LW_MIN_STEPS;
 constexpr int kSumsqBlocks = 1024;
 constexpr int kGraphIters = 25;     // MU iterations per replayed graph
 constexpr size_t kMaxGraphs = 64;
@@ -70,6 +74,7 @@ struct Stage {
   int nch = 0;      // PASS_C: row chunks
   bool pro_ok = false;  // the update pass can apply the W-update in its prologue (r <= 8 pass)
   bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
+  bool wide = false;   // PASS_L: update passes by the wide pass (64-column steps)
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
@@ -90,7 +95,10 @@ void classify_stage(Stage& s, int precision) {
   const int64_t gcap = std::max<int64_t>(
       256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
   s.cls = pass_L_class(s.m, s.rp);
-  if (s.m <= 32 || (s.m <= 128 && s.rp == 16 && ngroups >= 1024)) {
+#ifndef NTT_S_UPTO
+#define NTT_S_UPTO 32
+#endif
+  if (s.m <= 32 || (s.m <= NTT_S_UPTO && s.rp == 16 && ngroups >= 1024)) {
     // one wavefront per 16-column group with all rows in registers: faster than splitting
     // the rows over wavefronts up to 128 rows (no per-group barrier or cross-wave sum),
     // once there are enough groups to occupy the GPU with one wavefront each
@@ -105,12 +113,18 @@ void classify_stage(Stage& s, int precision) {
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, cap));
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
-    s.pairs = ngroups >= 512;  // column groups in pairs once there are enough of them
+    // the batched update pass takes B whole groups per step; otherwise column groups
+    // in pairs once there are enough of them
+    // (the wide pass's 64-column steps leave too few workgroups below ~256 steps)
+    const int nb = ngroups >= 4 * kLWMinSteps ? pass_L_batch(s.cls, s.rp) : 0;
+    s.wide = nb > 0;
+    s.pairs = nb == 0 && ngroups >= 512;
+    const int64_t units = nb > 0 ? (ngroups + nb - 1) / nb : (s.pairs ? (ngroups + 1) / 2 : ngroups);
     // one resident round of workgroups; partials up to ~25% of the X bytes
     const int64_t gcap_l = std::max<int64_t>(
         256, std::min<int64_t>(s.cls <= 2 ? kMaxLBlocks : 512,
                                (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_l));
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, gcap_l));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
     s.kind = PASS_C;
     s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
@@ -409,7 +423,7 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
 
 hipError_t run_pass(hipStream_t q, const Stage& s, const PassArgs& a, bool update, bool resid) {
   if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, q);
-  if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, q);
+  if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, s.wide, q);
   if (s.kind == PASS_C) return launch_pass_C(a, s.rp, s.G, update, resid, q);
   return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, q);
 }

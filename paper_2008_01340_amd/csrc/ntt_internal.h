@@ -96,8 +96,13 @@ hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool u
                              hipStream_t s);
 int pass_L_class(int64_t m, int rp);  // -1 when m is beyond the row-split variant
 int pass_L_waves(int cls);
+// 16-column groups per step of the wide row-split update pass for a row class (0: the
+// class has no wide pass); a wide stage's grid takes ceil(groups / 4) steps.
+int pass_L_batch(int cls, int rp);
+// wide: update passes by the wide pass (a residual with them runs the per-group pass
+// first); otherwise every pass by the per-group row-split pass
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
-                         hipStream_t s);
+                         bool wide, hipStream_t s);
 // Row-chunked pass (m beyond one workgroup): rows per chunk, and the launches of one
 // iteration (phase 1, chunk sum, phase 2) or of the residual (phase 0) on a
 // (G, nchunks) grid.  S holds nchunks x r x k floats, Hs r x k.

@@ -1158,6 +1158,231 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
   }
 }
 
+// ------------------------------------------------------------------ wide row-split pass
+// UPDATE-only row-split pass (rank padding 16) that reads X in steps of 64 columns with
+// every load instruction covering 4 rows x 256 contiguous bytes.  (Loads of 16 rows x
+// 64 bytes, the layout the MFMA A operand of X H^T wants, reach well under half of the
+// HBM bandwidth that 256-byte row runs do.)  Lane (a, b) of wave w loads
+// X[row0 + 4i + b][j0 + 4a .. 4a+3] for row quads i, which is directly the B operand of
+// W^T X (K = row, N = column) for the four column sets {j0 + 4a + q}, q = 0..3; only the
+// X H^T product needs X transposed, through a per-wave LDS tile.  Per step:
+//   A: each wave forms its rows' part of W^T X for the 4 column sets; parts to LDS;
+//   B: wave q < 4 sums the NW parts of column set q in the order 0..NW-1, forms
+//      D_H = G_W H (MFMA) and H_new, and writes H_new to an LDS tile of the step;
+//   C: the workgroup stores H_new (rows of 256 bytes); wave g < 4 accumulates
+//      H_new H_new^T over columns 16g..16g+15; each wave accumulates X H_new^T for its
+//      rows (X from registers through the transposition tile).
+// Partials as in k_mu_pass_L (the H H^T parts of waves 0..3 summed in that order).
+#ifndef NTT_LW_MIN_WAVES
+#define NTT_LW_MIN_WAVES 1
+#endif
+template <int MBW, int NW, bool PF, bool XBF>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NTT_LW_MIN_WAVES)))
+void k_mu_pass_LW(PassArgs p) {
+  constexpr int NQ = 4 * MBW;  // row quads per wave
+  constexpr int SN = 20;       // row stride of the W^T X parts: [column index][rank]
+  constexpr int ST = 68;       // row stride of the 64-column LDS tiles
+  static_assert(NW >= 4, "four waves take the four column sets of the epilogue");
+  __shared__ __attribute__((aligned(16))) float sNH[4][NW][16 * SN];
+  __shared__ __attribute__((aligned(16))) float sHn[16 * ST];
+  __shared__ __attribute__((aligned(16))) float sT[NW][16 * ST];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int row0 = w * 16 * MBW;
+
+  // W^T as the A operand of W^T X: wa[i] = W[row0 + 4i + b][a]
+  float wa[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int row = row0 + 4 * i + b;
+    wa[i] = zmask(p.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)], row < m && a < r);
+  }
+  float gw[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) gw[kk] = p.GW[a * 16 + 4 * b + kk];
+
+  v4f accW[MBW];
+  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nsteps = (k + 63) >> 6;
+  const int64_t nblk = gridDim.x;
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+  int64_t xrow[NQ];  // row offsets of this lane (clamped into the matrix)
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) xrow[i] = (int64_t)min(row0 + 4 * i + b, m - 1) * k;
+  const float* hrow[4];  // H rows 4b + kk (clamped), read by the epilogue waves
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) hrow[kk] = p.H + (int64_t)min(4 * b + kk, r - 1) * k;
+  float* sTw = sT[w];
+
+  // loads of a step: X[row0 + 4i + b][j0 + 4a .. 4a + 3]; wave q < 4 also
+  // H[4b + kk][j0 + 4a + q] (values as loaded; the ragged path masks X here)
+  auto load_step = [&](int64_t st, float4 (&x)[NQ], float (&hv)[4]) {
+    const int64_t j0 = st << 6;
+    if (vec_ok && (j0 + 64 <= k)) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = ldx4<XBF>(p, xrow[i] + j0 + 4 * a);
+    } else {  // ragged or unaligned step (rare)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t col = j0 + 4 * a + q;
+          v[q] = zmask(ldx<XBF>(p, xrow[i] + min(col, k - 1)), col < k && row0 + 4 * i + b < m);
+        }
+        x[i] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+    if (w < 4) {
+      const int64_t colc = min(j0 + 4 * a + w, k - 1);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[kk] = hrow[kk][colc];
+    }
+  };
+  float4 xn[NQ];  // next step's loads in flight while one is processed (PF)
+  float hnx[4];
+  if constexpr (PF) {
+    if ((int64_t)blockIdx.x < nsteps) load_step(blockIdx.x, xn, hnx);
+  }
+
+  for (int64_t st = blockIdx.x; st < nsteps; st += nblk) {
+    const int64_t j0 = st << 6;
+    const bool full = vec_ok && (j0 + 64 <= k);
+    float4 x[NQ];
+    float hv[4];
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = xn[i];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[kk] = hnx[kk];
+      if (st + nblk < nsteps) load_step(st + nblk, xn, hnx);
+    } else {
+      load_step(st, x, hv);
+    }
+
+    // A: parts of W^T X of the four column sets, stored as [a][rank 4b + i]
+    {
+      v4f nh[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nh[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        nh[0] = mfma16(wa[i], x[i].x, nh[0]);
+        nh[1] = mfma16(wa[i], x[i].y, nh[1]);
+        nh[2] = mfma16(wa[i], x[i].z, nh[2]);
+        nh[3] = mfma16(wa[i], x[i].w, nh[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<float4*>(&sNH[q][w][a * SN + 4 * b]) =
+            make_float4(nh[q][0], nh[q][1], nh[q][2], nh[q][3]);
+    }
+    __syncthreads();
+
+    // B: the epilogue of column set q = w: columns j0 + 4a + q
+    if (w < 4) {
+      float4 n4 = *reinterpret_cast<const float4*>(&sNH[w][0][a * SN + 4 * b]);
+#pragma unroll
+      for (int ww = 1; ww < NW; ++ww) {
+        const float4 v = *reinterpret_cast<const float4*>(&sNH[w][ww][a * SN + 4 * b]);
+        n4.x += v.x;
+        n4.y += v.y;
+        n4.z += v.z;
+        n4.w += v.w;
+      }
+      const float nv[4] = {n4.x, n4.y, n4.z, n4.w};
+      const int64_t col = j0 + 4 * a + w;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[kk] = zmask(hv[kk], 4 * b + kk < r && col < k);
+      v4f dh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) dh = mfma16(gw[kk], hv[kk], dh);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * b + i;
+        const float q = fmaxf(0.f, fast_div(hv[i] * nv[i], dh[i] + p.eps));
+        sHn[c * ST + 4 * a + w] = (c < r) ? q : 0.f;
+      }
+    }
+    __syncthreads();
+
+    // C: store H_new; H_new H_new^T (wave g < 4: columns 16g ..); X H_new^T per row block
+    if (tid < 256) {
+      const int c = tid >> 4, cq = 4 * (tid & 15);
+      if (c < r) {
+        const float4 v = *reinterpret_cast<const float4*>(&sHn[c * ST + cq]);
+        float* dst = p.H + (int64_t)c * k + j0 + cq;
+        if (full) {
+          *reinterpret_cast<float4*>(dst) = v;
+        } else {
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (j0 + cq + q < k) dst[q] = vv[q];
+        }
+      }
+    }
+    float4 hn4[4];  // H_new[a][16g + 4b .. 4b + 3]: the B operand of X H_new^T
+#pragma unroll
+    for (int g = 0; g < 4; ++g) hn4[g] = *reinterpret_cast<const float4*>(&sHn[a * ST + 16 * g + 4 * b]);
+    if (w < 4) {  // (read from LDS: indexing hn4 by the wave would put it in scratch)
+      const float4 h = *reinterpret_cast<const float4*>(&sHn[a * ST + 16 * w + 4 * b]);
+      accG = mfma16(h.x, h.x, accG);
+      accG = mfma16(h.y, h.y, accG);
+      accG = mfma16(h.z, h.z, accG);
+      accG = mfma16(h.w, h.w, accG);
+    }
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) {
+      // tile rows 4j + b <- row quad 4 blk + j: X[row0 + 16 blk + rho][j0 + col]
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<float4*>(&sTw[(4 * j + b) * ST + 4 * a]) = x[4 * blk + j];
+      wave_sync();
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 xa = *reinterpret_cast<const float4*>(&sTw[a * ST + 16 * g + 4 * b]);
+        accW[blk] = mfma16(xa.x, hn4[g].x, accW[blk]);
+        accW[blk] = mfma16(xa.y, hn4[g].y, accW[blk]);
+        accW[blk] = mfma16(xa.z, hn4[g].z, accW[blk]);
+        accW[blk] = mfma16(xa.w, hn4[g].w, accW[blk]);
+      }
+    }
+    // the next step's phase B rewrites sHn only after its first barrier, which every
+    // wave reaches after these reads
+  }
+
+  // partials: this wave's rows of X H_new^T; H_new H_new^T summed over waves 0..3
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + 16 * blk + 4 * b + i;
+      if (row < m && a < r) dst[(int64_t)row * r + a] = accW[blk][i];
+    }
+  __syncthreads();
+  float* gbuf = &sNH[0][0][0];  // 4 x 256 floats, free after the last step
+  if (w < 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gbuf[w * 256 + (4 * b + i) * 16 + a] = accG[i];
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += 64 * NW) {
+    const int c = e / r, cc = e % r;
+    dst[(int64_t)m * r + e] = ((gbuf[c * 16 + cc] + gbuf[256 + c * 16 + cc]) + gbuf[512 + c * 16 + cc]) +
+                              gbuf[768 + c * 16 + cc];
+  }
+}
+
 // ------------------------------------------------------------------ row-chunked MU pass
 // For m beyond one workgroup: rows are cut into chunks of CR = 16 MBW NW rows, chunk y
 // taken by the workgroups with blockIdx.y = y, which visit the same 16-column groups for
@@ -2421,8 +2646,39 @@ int pass_L_class(int64_t m, int rp) {
 
 int pass_L_waves(int cls) { return cls <= 2 ? 4 : 8; }
 
+int pass_L_batch(int cls, int rp) { return (rp == 16 && cls >= 0 && cls <= 3) ? 4 : 0; }
+
+#ifndef NTT_LW_PF
+#define NTT_LW_PF 0
+#endif
+#ifndef NTT_LW_CLS2_8W
+#define NTT_LW_CLS2_8W 0
+#endif
+template <int MBW, int NW>
+static hipError_t pass_LW(const PassArgs& a, int grid, hipStream_t s) {
+  if (a.Xb != nullptr) k_mu_pass_LW<MBW, NW, NTT_LW_PF != 0, true><<<grid, 64 * NW, 0, s>>>(a);
+  else k_mu_pass_LW<MBW, NW, NTT_LW_PF != 0, false><<<grid, 64 * NW, 0, s>>>(a);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
-                         hipStream_t s) {
+                         bool wide, hipStream_t s) {
+  if (wide && pass_L_batch(cls, rp) == 0) return hipErrorInvalidValue;
+  if (update && wide) {
+    // the residual of the incoming (W, H) first, by the per-group pass, then the update
+    if (resid) {
+      const hipError_t e = pass_L_rp<16>(a, cls, grid, false, true, s);
+      if (e != hipSuccess) return e;
+    }
+    switch (cls) {
+      case 0: return pass_LW<1, 4>(a, grid, s);
+      case 1: return pass_LW<2, 4>(a, grid, s);
+      case 2: return NTT_LW_CLS2_8W ? pass_LW<2, 8>(a, grid, s) : pass_LW<4, 4>(a, grid, s);
+      case 3: return pass_LW<4, 8>(a, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return rp == 16 ? pass_L_rp<16>(a, cls, grid, update, resid, s)
                   : pass_L_rp<32>(a, cls, grid, update, resid, s);
 }

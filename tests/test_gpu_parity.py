@@ -89,6 +89,10 @@ SHAPES = [
     (100, 9000, 12), (1100, 8200, 5),
     # one wavefront per group with 4 and 8 row blocks (33..128 rows, >= 1024 groups)
     (60, 17000, 7), (120, 16500, 14),
+    # the batched row-split update pass, 129..256 rows (4 waves): an odd k (scalar loads,
+    # last step partly past the last group) and a k of whole steps at rank 16; 8 waves
+    # of 8 row blocks (two groups per step) with a ragged last step
+    (200, 3001, 11), (250, 4096, 16), (900, 2504, 9),
 ]
 
 
