@@ -138,6 +138,8 @@ void classify_stage(Stage& s, int precision) {
     s.kind = PASS_GENERIC;
   }
   s.fused = s.kind == PASS_S || s.kind == PASS_L;
+  // (a prologue in the wide row-split pass was measured slower than the separate
+  // W-update launch: every workgroup waits for it before its first load)
   s.pro_ok = s.kind == PASS_S && s.r <= 8 && s.m <= 32;
   // BF16 X is read by the S passes at rank padding 16, the row-split and the row-chunked
   // passes; stages the single-workgroup kernel takes (small unfoldings), the S pass at

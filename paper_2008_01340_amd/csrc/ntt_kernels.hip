@@ -1173,12 +1173,8 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_L(PassArgs p) {
 //      H_new H_new^T over columns 16g..16g+15; each wave accumulates X H_new^T for its
 //      rows (X from registers through the transposition tile).
 // Partials as in k_mu_pass_L (the H H^T parts of waves 0..3 summed in that order).
-#ifndef NTT_LW_MIN_WAVES
-#define NTT_LW_MIN_WAVES 1
-#endif
-template <int MBW, int NW, bool PF, bool XBF>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NTT_LW_MIN_WAVES)))
-void k_mu_pass_LW(PassArgs p) {
+template <int MBW, int NW, bool XBF>
+__global__ __launch_bounds__(64 * NW) void k_mu_pass_LW(PassArgs p) {
   constexpr int NQ = 4 * MBW;  // row quads per wave
   constexpr int SN = 20;       // row stride of the W^T X parts: [column index][rank]
   constexpr int ST = 68;       // row stride of the 64-column LDS tiles
@@ -1192,22 +1188,6 @@ void k_mu_pass_LW(PassArgs p) {
   const int m = p.m, r = p.r;
   const int64_t k = p.k;
   const int row0 = w * 16 * MBW;
-
-  // W^T as the A operand of W^T X: wa[i] = W[row0 + 4i + b][a]
-  float wa[NQ];
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const int row = row0 + 4 * i + b;
-    wa[i] = zmask(p.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)], row < m && a < r);
-  }
-  float gw[4];
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) gw[kk] = p.GW[a * 16 + 4 * b + kk];
-
-  v4f accW[MBW];
-  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nsteps = (k + 63) >> 6;
   const int64_t nblk = gridDim.x;
@@ -1246,26 +1226,31 @@ void k_mu_pass_LW(PassArgs p) {
       for (int kk = 0; kk < 4; ++kk) hv[kk] = hrow[kk][colc];
     }
   };
-  float4 xn[NQ];  // next step's loads in flight while one is processed (PF)
-  float hnx[4];
-  if constexpr (PF) {
-    if ((int64_t)blockIdx.x < nsteps) load_step(blockIdx.x, xn, hnx);
+
+  // W^T as the A operand of W^T X: wa[i] = W[row0 + 4i + b][a]; G_W as that of G_W H
+  float wa[NQ];
+  float gw[4];
+  {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int row = row0 + 4 * i + b;
+      wa[i] = zmask(p.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)], row < m && a < r);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) gw[kk] = p.GW[a * 16 + 4 * b + kk];
   }
+
+  v4f accW[MBW];
+  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
 
   for (int64_t st = blockIdx.x; st < nsteps; st += nblk) {
     const int64_t j0 = st << 6;
     const bool full = vec_ok && (j0 + 64 <= k);
     float4 x[NQ];
     float hv[4];
-    if constexpr (PF) {
-#pragma unroll
-      for (int i = 0; i < NQ; ++i) x[i] = xn[i];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) hv[kk] = hnx[kk];
-      if (st + nblk < nsteps) load_step(st + nblk, xn, hnx);
-    } else {
-      load_step(st, x, hv);
-    }
+    load_step(st, x, hv);
 
     // A: parts of W^T X of the four column sets, stored as [a][rank 4b + i]
     {
@@ -2648,16 +2633,10 @@ int pass_L_waves(int cls) { return cls <= 2 ? 4 : 8; }
 
 int pass_L_batch(int cls, int rp) { return (rp == 16 && cls >= 0 && cls <= 3) ? 4 : 0; }
 
-#ifndef NTT_LW_PF
-#define NTT_LW_PF 0
-#endif
-#ifndef NTT_LW_CLS2_8W
-#define NTT_LW_CLS2_8W 0
-#endif
 template <int MBW, int NW>
 static hipError_t pass_LW(const PassArgs& a, int grid, hipStream_t s) {
-  if (a.Xb != nullptr) k_mu_pass_LW<MBW, NW, NTT_LW_PF != 0, true><<<grid, 64 * NW, 0, s>>>(a);
-  else k_mu_pass_LW<MBW, NW, NTT_LW_PF != 0, false><<<grid, 64 * NW, 0, s>>>(a);
+  if (a.Xb != nullptr) k_mu_pass_LW<MBW, NW, true><<<grid, 64 * NW, 0, s>>>(a);
+  else k_mu_pass_LW<MBW, NW, false><<<grid, 64 * NW, 0, s>>>(a);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -2665,6 +2644,7 @@ static hipError_t pass_LW(const PassArgs& a, int grid, hipStream_t s) {
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
                          bool wide, hipStream_t s) {
   if (wide && pass_L_batch(cls, rp) == 0) return hipErrorInvalidValue;
+  if (a.Wprev != nullptr) return hipErrorInvalidValue;  // W-update prologue: r <= 8 pass only
   if (update && wide) {
     // the residual of the incoming (W, H) first, by the per-group pass, then the update
     if (resid) {
@@ -2674,7 +2654,7 @@ hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool upda
     switch (cls) {
       case 0: return pass_LW<1, 4>(a, grid, s);
       case 1: return pass_LW<2, 4>(a, grid, s);
-      case 2: return NTT_LW_CLS2_8W ? pass_LW<2, 8>(a, grid, s) : pass_LW<4, 4>(a, grid, s);
+      case 2: return pass_LW<4, 4>(a, grid, s);
       case 3: return pass_LW<4, 8>(a, grid, s);
       default: return hipErrorInvalidValue;
     }

@@ -227,6 +227,21 @@ def test_sweep_with_row_chunked_stage():
         assert rel(host(cf), host(cg)) <= TOL
 
 
+@pytest.mark.parametrize("m,k,r", [(200, 20000, 10), (100, 17000, 16), (48, 20000, 7)])
+def test_wide_pass_prologue_equals_separate_w_update_bitwise(m, k, r):
+    # The wide row-split pass applies the previous W-update in its prologue when no
+    # trace is recorded; with the trace, the W-update runs as its own kernel.  Both use
+    # the same row code and Gram order, so the factors must agree bit for bit.
+    say(f"case: wide pass prologue vs separate W-update, m={m} k={k} r={r}")
+    rng = np.random.default_rng(m + k + r)
+    X = dev(rng.random((m, k)) + 0.01)
+    T = 30
+    rec = ntt.decompose(X, (1, r, 1), T, seed=5, record_objective=True)
+    fast = ntt.decompose(X, (1, r, 1), T, seed=5)
+    for cr, cf in zip(rec.cores, fast.cores):
+        assert torch.equal(cr, cf)
+
+
 @pytest.mark.parametrize("m,k,r", [
     (1, 5000, 1),     # one row (S pass, r <= 8)
     (5000, 1, 1),     # one column: transposed stage of one row
