@@ -25,11 +25,12 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
+EXTRAS = ("precision_mode", "paper_workload", "batched", "serving")
 # HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8<2> on 768
-# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (84,245.1 KiB) and WRITE_SIZE
-# (35,238.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
+# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (83,932.4 KiB) and WRITE_SIZE
+# (35,211.0 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
 # copy (x2.00, x1.00).  Taken on the current pass kernel; re-measure when it changes.
-MEASURED_TRAFFIC = {"tt32x5_r8": 172.534e6 + 36.084e6}
+MEASURED_TRAFFIC = {"tt32x5_r8": 171.894e6 + 36.056e6}
 
 
 def parse():
@@ -41,7 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision-mode, batched and serving measurements")
+                    help="skip the precision-mode, paper-workload, batched and serving measurements")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated subset of the extra measurements: " + ", ".join(EXTRAS))
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-max-mb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -307,15 +310,23 @@ def main():
                      "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
                      "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
     }
-    if not args.no_extras:
+    extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]
+    unknown = [e for e in extras if e not in EXTRAS]
+    if unknown:
+        raise SystemExit(f"unknown extras {unknown}; choose from {', '.join(EXTRAS)}")
+    if extras:
         del A
         torch.cuda.empty_cache()
+    if "precision_mode" in extras:
         out["precision_mode"] = precision_mode(ntt, S, torch)
         torch.cuda.empty_cache()
+    if "paper_workload" in extras:
         out["paper_workload"] = paper_workload(ntt, S, torch)
         torch.cuda.empty_cache()
+    if "batched" in extras:
         out["batched"] = batched(ntt, S, torch)
         torch.cuda.empty_cache()
+    if "serving" in extras:
         out["serving"] = {
             "fp32": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_FP32),
             "bf16": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_BF16_MIXED),
