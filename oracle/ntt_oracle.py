@@ -20,10 +20,13 @@ What it follows
 * Objective 1/2 ||X - W H||_F^2 (Alg.3, the correction test), computed here as the
   explicit residual, never by the Gram identity.
 * Eq.(3) relative error, Eq.(4) compression ratio.
+* The rank rule of Alg.2 (``eps_rank``): r_l is the smallest k whose singular-value
+  tail ratio of the current unfolding is at most the threshold; used when a threshold
+  is given, else the ranks are given.
 
-Readings where the paper is silent or garbled (ranks are given, not chosen by the
-SVD rule; ranks above min(m, k) are clamped; a fresh random stream per stage; the
-stopping rule) are stated at each function.
+Readings where the paper is silent or garbled (given ranks are caps of the rule;
+ranks above min(m, k) are clamped; a fresh random stream per stage; the stopping
+rule) are stated at each function.
 
 Random initial factors use the SplitMix64 counter rule (Steele, Lea and Flood,
 OOPSLA 2014), implemented here on its own: value i of stream tag under seed is the
@@ -176,14 +179,35 @@ def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
             "snaps": snaps, "norm_x": nx}
 
 
+# ---------------------------------------------------------------- rank selection
+def eps_rank(X, eps) -> int:
+    """The rank rule of Alg.2: the smallest k >= 1 such that
+    sqrt(s_{k+1}^2 + ... + s_N^2) / sqrt(s_1^2 + ... + s_N^2) <= eps, where s_1 >= s_2 >= ...
+    are the singular values of X and N = min(m, n).  A zero matrix gets rank 1.  The tail
+    sums are added from the smallest value up (no cancellation)."""
+    s = np.linalg.svd(np.asarray(X, dtype=np.float64), compute_uv=False)
+    s2 = s * s
+    total = float(np.sum(s2[::-1]))
+    if total == 0.0:
+        return 1
+    tails = np.concatenate([np.cumsum(s2[::-1])[::-1][1:], [0.0]])  # tails[k-1] = sum_{i>k} s_i^2
+    for k in range(1, len(s2) + 1):
+        if math.sqrt(tails[k - 1] / total) <= eps:
+            return k
+    return len(s2)
+
+
 # ---------------------------------------------------------------- the nTT sweep
 def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
-                  inits=None, record_objective=False, snapshots=()):
-    """Alg.2 with given ranks and MU as the NMF: returns cores and per-stage details.
+                  inits=None, record_objective=False, snapshots=(), rank_eps=0.0):
+    """Alg.2 with MU as the NMF: returns cores and per-stage details.
 
     ``A`` is the d-way tensor (converted to float64, C order).  ``ranks`` has d+1
-    entries with r_0 = r_d = 1.  ``inits`` optionally maps stage l (1-based) to
-    (W0, H0); otherwise the seeded uniform init of ``init_factors`` is used.
+    entries with r_0 = r_d = 1.  With ``rank_eps`` = 0 they are the TT ranks (clamped as
+    in ``effective_ranks``); with ``rank_eps`` > 0 each inner rank is chosen at its stage
+    by ``eps_rank`` of the current unfolding (Alg.2) and ``ranks`` only caps it.
+    ``inits`` optionally maps stage l (1-based) to (W0, H0); otherwise the seeded
+    uniform init of ``init_factors`` is used.
     """
     A = np.asarray(A, dtype=np.float64)
     dims = list(A.shape)
@@ -194,6 +218,8 @@ def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
     for l in range(1, d):
         m, k = X.shape
         assert m == r[l - 1] * dims[l - 1]
+        if rank_eps > 0.0:
+            r[l] = min(r[l], eps_rank(X, rank_eps), m, k)
         rl = r[l]
         if inits is not None and l in inits:
             W0, H0 = inits[l]

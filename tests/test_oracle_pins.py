@@ -233,6 +233,55 @@ def test_mu_halves_are_column_separable_and_product_only():
     np.testing.assert_allclose(O.update_W(XHt, HHt, W0, 1e-12), W1, rtol=1e-13)
 
 
+def test_eps_rank_hand_computed_spectrum():
+    # singular values 5, 4, 3, 2, 1 (sum of squares 55); tail ratios after k values:
+    # k=1 sqrt(30/55)=0.7385, k=2 sqrt(14/55)=0.5045, k=3 sqrt(5/55)=0.3015,
+    # k=4 sqrt(1/55)=0.1348, k=5 0.  The rule takes the first k at or below eps.
+    s = np.array([5.0, 4.0, 3.0, 2.0, 1.0])
+    rng = _rng(3)
+    U, _ = np.linalg.qr(rng.standard_normal((9, 5)))
+    V, _ = np.linalg.qr(rng.standard_normal((7, 5)))
+    X = U @ np.diag(s) @ V.T
+    for eps, k in ((0.9, 1), (0.74, 1), (0.73, 2), (0.51, 2), (0.50, 3), (0.31, 3), (0.30, 4),
+                   (0.14, 4), (0.13, 5), (1e-10, 5)):
+        assert O.eps_rank(X, eps) == k, (eps, k)
+        assert O.eps_rank(X.T, eps) == k
+        assert O.eps_rank(3.5 * X, eps) == k
+
+
+def test_eps_rank_matches_truncation_error():
+    # Eckart-Young: the rule's tail ratio is the relative Frobenius error of the best
+    # rank-k truncation; check the chosen k against explicit truncations.
+    X = _nonneg(12, 20, 5)
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    nx = np.linalg.norm(X)
+    for eps in (0.3, 0.1, 0.05, 0.01):
+        k = O.eps_rank(X, eps)
+        err = lambda j: np.linalg.norm(X - (U[:, :j] * s[:j]) @ Vt[:j]) / nx
+        assert err(k) <= eps + 1e-12
+        if k > 1:
+            assert err(k - 1) > eps
+
+
+def test_eps_rank_of_exact_low_rank_and_zero():
+    rng = _rng(8)
+    X = rng.random((15, 3)) @ rng.random((3, 40))
+    assert O.eps_rank(X, 1e-8) == 3
+    assert O.eps_rank(np.zeros((4, 6)), 0.1) == 1
+
+
+def test_sweep_rank_rule_recovers_generating_rank_of_first_unfolding():
+    # a noise-free TT tensor with ranks (1, 3, 4, 1): the first unfolding has rank 3
+    A = S.contract_cores(S.random_cores((6, 7, 8), (1, 3, 4, 1), seed=12)).astype(np.float64)
+    res = O.ntt_decompose(A, (1, 32, 32, 1), 30, seed=1, rank_eps=1e-5)
+    assert res["ranks"][1] == 3
+    assert res["ranks"][2] <= min(3 * 7, 8)
+    assert [c.shape for c in res["cores"]] == [(1, 6, 3), (3, 7, res["ranks"][2]), (res["ranks"][2], 8, 1)]
+    # a rank cap below the rule's choice wins
+    res2 = O.ntt_decompose(A, (1, 2, 32, 1), 5, seed=1, rank_eps=1e-5)
+    assert res2["ranks"][1] == 2
+
+
 def test_gram_identity_equals_explicit_residual():
     X = _nonneg(15, 22, 8)
     W, H = _rng(9).random((15, 4)), _rng(10).random((4, 22))
