@@ -79,6 +79,15 @@ typedef struct {
   int32_t precision;    /* ntt_precision */
   int32_t fp32_tail_iters; /* BF16 mode: last N iterations of each stage in FP32 */
   uint32_t flags;       /* NTT_* flags above */
+  double rank_eps;      /* 0: the inner ranks are the given ranks (clamped).  > 0: the rank
+                           rule of Alg.2: at each stage l, r_l is the smallest k such that
+                           sqrt(s_{k+1}^2 + ... + s_N^2) / sqrt(s_1^2 + ... + s_N^2) <= rank_eps,
+                           s the singular values of the current unfolding X_l (from the
+                           eigenvalues of its FP64 Gram on the shorter side, which must be
+                           at most 2048), capped by the given r_l as clamped; the chosen
+                           ranks come back in ntt_report.eff_ranks and each core is written
+                           compactly at the chosen ranks into its buffer (sized by the
+                           caps).  ntt_decompose only (batched and server plans: 0). */
 } ntt_config;
 
 typedef struct {
@@ -108,7 +117,8 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out);
 
 /* Query a plan: device workspace bytes ntt_decompose needs (bytes may be NULL),
  * effective ranks (host array of d+1 entries, may be NULL) and the Eq.(4)
- * compression ratio prod n_i / sum n_i r_{i-1} r_i at those ranks (may be NULL). */
+ * compression ratio prod n_i / sum n_i r_{i-1} r_i at those ranks (may be NULL).
+ * With rank_eps > 0 the effective ranks are the caps (the core buffer sizes). */
 ntt_status ntt_plan_workspace(ntt_plan_t plan, size_t* bytes, int64_t* eff_ranks,
                               double* compression);
 

@@ -18,6 +18,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
     "-Wno-unused-command-line-argument",
+    # rocSOLVER (symmetric eigenvalues for the rank rule) and the rocBLAS handle it runs on
+    "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",
 ]
 
 

@@ -21,6 +21,9 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "ntt_internal.h"
 
 using namespace ntt;
@@ -150,6 +153,34 @@ void classify_stage(Stage& s, int precision) {
   s.part_stride = align_up(E, 64);
 }
 
+void generic_chunks(const Stage& s, int* G, int64_t* chunk);
+
+// Classes of an m x k, rank-r stage (s) and of its transposed problem (t, when the stage
+// iterates transposed: s.trans_ok).
+void stage_shape(const ntt_config& cfg, int64_t m, int64_t k, int r, Stage& s, Stage& t) {
+  s = Stage{};
+  t = Stage{};
+  s.m = m;
+  s.k = k;
+  s.r = r;
+  classify_stage(s, cfg.precision);
+  if (s.kind == PASS_GENERIC) generic_chunks(s, &s.G, &s.chunk);
+  if (!s.fused) {
+    // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
+    // this one shifted by half a step, and its rows (k) may fit the fused passes
+    Stage u{};
+    u.m = s.k;
+    u.k = s.m;
+    u.r = s.r;
+    classify_stage(u, cfg.precision);
+    if (u.fused && cfg.tol == 0.0 && cfg.max_iters >= 1 && !stage_1wg_ok(u.m, u.k, u.r)) {
+      generic_chunks(u, &u.G_pre, &u.chunk_pre);
+      s.trans_ok = true;
+      t = u;
+    }
+  }
+}
+
 // Column chunks of the generic X H^T partials: enough for parallelism, while their
 // G (m r + r r) floats stay within ~1/4 of the X bytes.
 void generic_chunks(const Stage& s, int* G, int64_t* chunk) {
@@ -167,6 +198,7 @@ struct ntt_plan_s {
   int d = 0;
   int64_t dims[NTT_MAX_DIMS] = {};
   int64_t eff[NTT_MAX_DIMS + 1] = {};
+  int64_t cap[NTT_MAX_DIMS + 1] = {};  // eff as planned (rank_eps > 0: the caps of the rule)
   Stage st[NTT_MAX_DIMS];
   Stage tst[NTT_MAX_DIMS];  // transposed problems of the stages with trans_ok
   double compression = 0.0;
@@ -179,6 +211,9 @@ struct ntt_plan_s {
   size_t off_s = 0;  // row-chunked stages: W^T X per row chunk, then a copy of H
   size_t off_wb = 0;  // prologue-mode stages: the second W buffer
   size_t off_gpart = 0;  // W-update over row blocks: per-block Gram parts
+  // rank rule (rank_eps > 0): Gram partials, the Gram, eigenvalues, eigensolver workspace
+  size_t off_grp = 0, off_gram = 0, off_eig = 0, off_eigws = 0, eigws_size = 0;
+  rocblas_handle rb = nullptr;  // created on first use by the rank rule
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
@@ -192,6 +227,7 @@ struct ntt_plan_s {
   };
   std::vector<GraphEntry> graphs;
   ~ntt_plan_s() {
+    if (rb) (void)rocblas_destroy_handle(rb);
     for (auto e : prof_events) (void)hipEventDestroy(e);
     if (events_ready)
       for (auto e : stage_ev) (void)hipEventDestroy(e);
@@ -245,6 +281,9 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   if (cfg->precision != NTT_PREC_FP32 && cfg->precision != NTT_PREC_BF16_MIXED)
     return fail(NTT_ERR_INVALID_ARG, "unknown precision");
   if (cfg->fp32_tail_iters < 0) return fail(NTT_ERR_INVALID_ARG, "fp32_tail_iters < 0");
+  if (!(cfg->rank_eps >= 0.0) || !std::isfinite(cfg->rank_eps))
+    return fail(NTT_ERR_INVALID_ARG, "rank_eps must be finite and >= 0");
+  const bool eps_mode = cfg->rank_eps > 0.0;
   int64_t total = 1;
   for (int i = 0; i < d; ++i) {
     if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
@@ -279,6 +318,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     p->eff[l] = r;
   }
   p->eff[d] = 1;
+  for (int i = 0; i <= d; ++i) p->cap[i] = p->eff[i];
   p->compression = compression_of(d, p->dims, p->eff);
 
   // stages and workspace
@@ -289,33 +329,19 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   size_t red_max = 0;
   size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0, wb_size = 0;
   int64_t m_max = 1;
-  for (int l = 1; l < d; ++l) {
-    Stage& s = p->st[l - 1];
-    s.m = p->eff[l - 1] * p->dims[l - 1];
-    s.k = 1;
-    for (int j = l; j < d; ++j) s.k *= p->dims[j];
-    s.r = (int)p->eff[l];
-    classify_stage(s, cfg->precision);
-    if (s.kind == PASS_GENERIC) {
-      generic_chunks(s, &s.G, &s.chunk);
-      gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
-    }
+  size_t grp_max = 0, gram_max = 0;
+  int64_t n_max = 0;
+  // one stage shape: its classes (kept in s, t) and its share of the workspace maxima
+  auto plan_stage = [&](int l, int64_t m, int64_t k, int r, Stage& s, Stage& t_out) {
+    stage_shape(*cfg, m, k, r, s, t_out);
+    if (s.kind == PASS_GENERIC) gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
     if (s.kind == PASS_C) {
       gres = std::max(gres, s.G * s.nch);
       s_size = std::max(s_size, (size_t)(s.nch + 1) * (size_t)s.r * (size_t)s.k * sizeof(float));
     }
-    if (!s.fused) {
-      // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
-      // this one shifted by half a step, and its rows (k) may fit the fused passes
-      Stage t{};
-      t.m = s.k;
-      t.k = s.m;
-      t.r = s.r;
-      classify_stage(t, cfg->precision);
-      if (t.fused && cfg->tol == 0.0 && cfg->max_iters >= 1 && !stage_1wg_ok(t.m, t.k, t.r)) {
-        generic_chunks(t, &t.G_pre, &t.chunk_pre);
-        s.trans_ok = true;
-        p->tst[l - 1] = t;
+    if (s.trans_ok) {
+      const Stage& t = t_out;
+      {
         part_floats = std::max(part_floats, (size_t)std::max(t.G, t.G_pre) * t.part_stride);
         red_max = std::max(red_max, (size_t)t.m * t.r + (size_t)t.r * t.r);
         gres = std::max(gres, t.G);
@@ -329,7 +355,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
     red_max = std::max(red_max, E);
     m_max = std::max(m_max, s.m);
-    if (s.trans_ok) m_max = std::max(m_max, p->tst[l - 1].m);
+    if (s.trans_ok) m_max = std::max(m_max, t_out.m);
     gmax = std::max(gmax, s.G);
     gfin = std::max(gfin, s.G);
     part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
@@ -339,7 +365,35 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     }
     if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
     if (s.pro_ok) wb_size = std::max(wb_size, (size_t)s.m * (size_t)s.r * sizeof(float));
+    if (eps_mode) {
+      int ns = 1;
+      size_t pd = 0;
+      gram_plan(s.m, s.k, &ns, &pd);
+      const int64_t n = std::min(s.m, s.k);
+      grp_max = std::max(grp_max, pd);
+      gram_max = std::max(gram_max, (size_t)n * (size_t)n);
+      n_max = std::max(n_max, n);
+    }
+  };
+  for (int l = 1; l < d; ++l) {
+    int64_t k = 1;
+    for (int j = l; j < d; ++j) k *= p->dims[j];
+    plan_stage(l, p->eff[l - 1] * p->dims[l - 1], k, (int)p->eff[l], p->st[l - 1], p->tst[l - 1]);
+    if (eps_mode) {
+      // the rule may choose any r_{l-1} <= cap and r_l <= cap: plan the workspace for all
+      for (int64_t rp_ = 1; rp_ <= p->eff[l - 1]; ++rp_)
+        for (int64_t r_ = 1; r_ <= p->eff[l]; ++r_) {
+          const int64_t m_ = rp_ * p->dims[l - 1];
+          if (r_ > std::min(m_, k)) continue;
+          Stage s2{}, t2{};
+          plan_stage(l, m_, k, (int)r_, s2, t2);
+        }
+    }
     p->total_iters += cfg->max_iters;
+  }
+  if (eps_mode && n_max > 2048) {
+    delete p;
+    return fail(NTT_ERR_INVALID_ARG, "rank_eps: an unfolding's shorter side exceeds 2048");
   }
   gres = std::max(std::max(gres, gmax), kSumsqBlocks);
   size_t off = 0;
@@ -348,7 +402,10 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_part = off; off = align_up(off + part_floats * sizeof(float), 256);
   p->off_rpart = off; off = align_up(off + (size_t)gres * sizeof(double), 256);
   p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
-  if (gfin > 1024) return fail(NTT_ERR_INVALID_ARG, "too many partials for the W-update reduction");
+  if (gfin > 1024) {
+    delete p;
+    return fail(NTT_ERR_INVALID_ARG, "too many partials for the W-update reduction");
+  }
   p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
   p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
   p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
@@ -359,6 +416,15 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_s = off; off = align_up(off + s_size, 256);
   p->off_wb = off; off = align_up(off + wb_size, 256);
   p->off_gpart = off; off = align_up(off + (size_t)((m_max + 255) / 256) * (32 * 32 + 1) * sizeof(double), 256);
+  if (eps_mode) {
+    p->off_grp = off; off = align_up(off + grp_max * sizeof(double), 256);
+    p->off_gram = off; off = align_up(off + gram_max * sizeof(double), 256);
+    p->off_eig = off; off = align_up(off + (2 * (size_t)n_max + 8) * sizeof(double), 256);
+    // eigensolver scratch (eigenvalues only): checked against the solver's own query
+    p->eigws_size = (size_t)32 << 20;
+    p->eigws_size += 2 * gram_max * sizeof(double);
+    p->off_eigws = off; off = align_up(off + p->eigws_size, 256);
+  }
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -368,8 +434,8 @@ ntt_status ntt_plan_workspace(ntt_plan_t p, size_t* bytes, int64_t* eff_ranks, d
   if (!p) return fail(NTT_ERR_INVALID_ARG, "null plan");
   if (bytes) *bytes = p->total;
   if (eff_ranks)
-    for (int i = 0; i <= p->d; ++i) eff_ranks[i] = p->eff[i];
-  if (compression) *compression = p->compression;
+    for (int i = 0; i <= p->d; ++i) eff_ranks[i] = p->cap[i];
+  if (compression) *compression = compression_of(p->d, p->dims, p->cap);
   return NTT_OK;
 }
 
@@ -400,6 +466,10 @@ struct Ctx {
   float* sbuf() const { return reinterpret_cast<float*>(ws + p->off_s); }
   float* wb() const { return reinterpret_cast<float*>(ws + p->off_wb); }
   double* gpart() const { return reinterpret_cast<double*>(ws + p->off_gpart); }
+  double* grp() const { return reinterpret_cast<double*>(ws + p->off_grp); }
+  double* gram() const { return reinterpret_cast<double*>(ws + p->off_gram); }
+  double* eig() const { return reinterpret_cast<double*>(ws + p->off_eig); }
+  void* eigws() const { return ws + p->off_eigws; }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -493,13 +563,91 @@ struct NttJob {
     t = 0;
     prepared = done = false;
     trace_off = 0;
+    if (plan->cfg.rank_eps > 0.0)
+      for (int i = 0; i <= plan->d; ++i) plan->eff[i] = plan->cap[i];
     HIP_TRY(launch_zero_ints(c.ints(), 64, s));
+    return NTT_OK;
+  }
+
+  // The rank rule of Alg.2 for stage l: the squared singular values of X_l are the
+  // eigenvalues of its FP64 Gram on the shorter side (rocSOLVER syevd, eigenvalues
+  // only, in the plan's workspace); r_l is the smallest k whose tail ratio
+  // sqrt(sum_{i>k} s_i^2 / sum_i s_i^2) is at most rank_eps (tails added from the
+  // smallest value up), capped by the planned rank.  The stage is then re-planned at
+  // that rank.
+  ntt_status select_rank() {
+    const ntt_config& cfg = p->cfg;
+    hipStream_t q = c.s;
+    const int64_t m = p->eff[l - 1] * p->dims[l - 1];
+    int64_t k = 1;
+    for (int j = l; j < d(); ++j) k *= p->dims[j];
+    const float* Xl = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
+    HIP_TRY(launch_gram(Xl, m, k, c.grp(), c.gram(), q));
+    const int n = (int)std::min(m, k);
+    if (!p->rb && rocblas_create_handle(&p->rb) != rocblas_status_success) {
+      p->rb = nullptr;
+      return fail(NTT_ERR_DEVICE, "rocblas_create_handle failed");
+    }
+    if (rocblas_set_stream(p->rb, q) != rocblas_status_success)
+      return fail(NTT_ERR_DEVICE, "rocblas_set_stream failed");
+    double* D = c.eig();
+    double* E = D + n;
+    rocblas_int* info = reinterpret_cast<rocblas_int*>(E + n);
+    size_t need = 0;
+    if (rocblas_start_device_memory_size_query(p->rb) != rocblas_status_success)
+      return fail(NTT_ERR_DEVICE, "rocblas memory size query failed");
+    (void)rocsolver_dsyevd(p->rb, rocblas_evect_none, rocblas_fill_upper, n, c.gram(), n, D, E, info);
+    if (rocblas_stop_device_memory_size_query(p->rb, &need) != rocblas_status_success)
+      return fail(NTT_ERR_DEVICE, "rocblas memory size query failed");
+    if (need > p->eigws_size)
+      return fail(NTT_ERR_WORKSPACE_TOO_SMALL, "eigensolver needs " + std::to_string(need) + " bytes");
+    if (rocblas_set_workspace(p->rb, c.eigws(), p->eigws_size) != rocblas_status_success)
+      return fail(NTT_ERR_DEVICE, "rocblas_set_workspace failed");
+    if (rocsolver_dsyevd(p->rb, rocblas_evect_none, rocblas_fill_upper, n, c.gram(), n, D, E, info) !=
+        rocblas_status_success)
+      return fail(NTT_ERR_DEVICE, "rocsolver_dsyevd failed");
+    std::vector<double> ev((size_t)n);
+    rocblas_int hinfo = 0;
+    HIP_TRY(hipMemcpyAsync(ev.data(), D, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, q));
+    HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, q));
+    HIP_TRY(hipStreamSynchronize(q));
+    if (hinfo != 0) return fail(NTT_ERR_DEVICE, "eigensolver did not converge");
+    // eigenvalues ascending; pre[j] = sum of the j smallest (negative rounding -> 0)
+    std::vector<double> pre((size_t)n + 1, 0.0);
+    for (int j = 0; j < n; ++j) pre[j + 1] = pre[j] + std::max(ev[j], 0.0);
+    const double total = pre[n];
+    int64_t rk = 1;
+    if (total > 0.0) {
+      rk = n;
+      for (int kk = 1; kk <= n; ++kk)
+        if (std::sqrt(pre[n - kk] / total) <= cfg.rank_eps) {
+          rk = kk;
+          break;
+        }
+    }
+    const int64_t r = std::min(std::min(p->cap[l], rk), std::min(m, k));
+    p->eff[l] = r;
+    stage_shape(cfg, m, k, (int)r, p->st[l - 1], p->tst[l - 1]);
+    p->compression = compression_of(d(), p->dims, p->eff);
+    // graphs captured for an earlier shape of this stage
+    for (size_t i = 0; i < p->graphs.size();) {
+      if (p->graphs[i].stage == l) {
+        (void)hipGraphExecDestroy(p->graphs[i].exec);
+        p->graphs.erase(p->graphs.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
     return NTT_OK;
   }
 
   // a1 (norm, input check), a2 (initial factors), W^T W, and the BF16 copy (a8)
   ntt_status prepare_stage(bool validate_now) {
     const ntt_config& cfg = p->cfg;
+    if (cfg.rank_eps > 0.0) {
+      const ntt_status rs = select_rank();
+      if (rs != NTT_OK) return rs;
+    }
     const Stage& s = st();
     hipStream_t q = c.s;
     const int dd = d();
@@ -1041,6 +1189,10 @@ extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_
     if (cfgs[i].flags & (NTT_RECORD_OBJECTIVE | NTT_PROFILE | NTT_VALIDATE_INPUT)) {
       delete b;
       return fail(NTT_ERR_INVALID_ARG, "batched mode takes no RECORD/PROFILE/VALIDATE flags");
+    }
+    if (cfgs[i].rank_eps != 0.0) {
+      delete b;
+      return fail(NTT_ERR_INVALID_ARG, "batched mode takes given ranks (rank_eps = 0)");
     }
     ntt_status st = ntt_plan(&cfgs[i], &p);
     if (st != NTT_OK) {

@@ -127,4 +127,12 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s);
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
 
+// Rank rule of Alg.2: FP64 Gram of the shorter side of X (m x k, row-major): G = X X^T
+// (n = m) when m <= k, else X^T X (n = k); G is n x n, row-major, both triangles.  The
+// long dimension is split into nsplit chunks whose partials (npairs x nsplit blocks of
+// 64 x 64 doubles in `part`) are added in chunk order.  gram_plan gives the split and the
+// partial size in doubles for an m x k matrix.
+void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles);
+hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s);
+
 }  // namespace ntt

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ntt_internal.h"
 
 // Tuning knobs (compile-time): minimum waves per SIMD requested from the
@@ -2381,6 +2383,115 @@ __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, i
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------------ Gram for the rank rule
+// FP64 Gram of the shorter side of X (Alg.2 rank rule: the squared singular values of X
+// are the eigenvalues of X X^T or X^T X).  Workgroup (pair, split) forms the 64 x 64
+// block (bi, bj), bi <= bj, of the Gram over one chunk of the long dimension: tiles of
+// 64 short-side indices x 16 long-side indices of both blocks are staged in LDS as FP32
+// (exact in FP64) and multiplied with v_mfma_f64_16x16x4f64, each wave owning a 32 x 32
+// quarter.  The partial goes to part[pair][split]; k_gram_reduce adds the splits in
+// order and writes both triangles.
+struct GramArgs {
+  const float* X;
+  int64_t m, k;     // X is m x k, row-major
+  int n;            // Gram side: min(m, k)
+  int trans;        // 0: G = X X^T (n = m); 1: G = X^T X (n = k)
+  int nb;           // 64-blocks per side
+  int nsplit;
+  int64_t chunk;    // long-side indices per split (multiple of 16)
+  double* part;
+  double* G;
+};
+
+__device__ __forceinline__ void gram_pair(int p, int nb, int* bi, int* bj) {
+  int i = 0;
+  while (p >= nb - i) {  // row i of the upper triangle holds nb - i blocks
+    p -= nb - i;
+    ++i;
+  }
+  *bi = i;
+  *bj = i + p;
+}
+
+__global__ __launch_bounds__(256) void k_gram(GramArgs g) {
+  __shared__ float sA[64][17];
+  __shared__ float sB[64][17];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  int bi, bj;
+  gram_pair(blockIdx.x, g.nb, &bi, &bj);
+  const int split = blockIdx.y;
+  const int64_t L = g.trans ? g.m : g.k;  // long side
+  const int64_t c_begin = (int64_t)split * g.chunk;
+  const int64_t c_end = min(L, c_begin + g.chunk);
+  const int n = g.n;
+  v4d acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += 16) {
+    // element (p, c) of the short x long view: X[p][c] (trans 0) or X[c][p] (trans 1);
+    // entries past n or past the chunk are zero
+    for (int e = tid; e < 2 * 64 * 16; e += 256) {
+      const int which = e >> 10, q = e & 1023;
+      int pl, cl;
+      if (g.trans) {  // consecutive threads along p: rows of X are contiguous in p
+        cl = q >> 6;
+        pl = q & 63;
+      } else {        // consecutive threads along c
+        pl = q >> 4;
+        cl = q & 15;
+      }
+      const int pg = (which ? bj : bi) * 64 + pl;
+      const int64_t cg = c0 + cl;
+      const int pc = min(pg, n - 1);
+      const int64_t cc = min(cg, c_end - 1);
+      const float v = g.trans ? g.X[cc * g.k + pc] : g.X[(int64_t)pc * g.k + cc];
+      const float z = zmask(v, pg < n && cg < c_end);
+      if (which) sB[pl][cl] = z;
+      else sA[pl][cl] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const double av = (double)sA[wi + 16 * ti + a][4 * kk + b];
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          const double bv = (double)sB[wj + 16 * tj + a][4 * kk + b];
+          acc[ti][tj] = mfma16_f64(av, bv, acc[ti][tj]);
+        }
+      }
+    __syncthreads();
+  }
+  // FP64 16 x 16 x 4 result layout: value i of lane (a, b) is row 4 i + b, column a
+  double* dst = g.part + ((size_t)blockIdx.x * g.nsplit + split) * 4096;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[(wi + 16 * ti + 4 * i + b) * 64 + wj + 16 * tj + a] = acc[ti][tj][i];
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
+  int bi, bj;
+  gram_pair(blockIdx.x, g.nb, &bi, &bj);
+  const double* src = g.part + (size_t)blockIdx.x * g.nsplit * 4096;
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    double s = 0.0;
+    for (int sp = 0; sp < g.nsplit; ++sp) s += src[(size_t)sp * 4096 + e];
+    const int gi = bi * 64 + (e >> 6), gj = bj * 64 + (e & 63);
+    if (gi < g.n && gj < g.n) {
+      g.G[(size_t)gi * g.n + gj] = s;
+      g.G[(size_t)gj * g.n + gi] = s;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ TT expand (Eq.(2))
 // Rows of the (n_1...n_{d-1}) x n_d matrix of the full tensor, 64 per block.  Each row's
 // left factor P[row,:] = G_1[i_1,:] G_2[:,i_2,:] ... G_{d-1}[:,i_{d-1},:] is formed in
@@ -2834,6 +2945,39 @@ hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s) {
     k_sum_pairs<<<1, 64, 0, s>>>(t.part, nb, t.part + 2 * nb);
     NTT_CHECK_LAUNCH();
   }
+  return hipSuccess;
+}
+
+void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
+  const int64_t n = std::min(m, k), L = std::max(m, k);
+  const int64_t nb = (n + 63) / 64;
+  const int64_t npairs = nb * (nb + 1) / 2;
+  // about 1024 workgroups, each chunk at least 1024 long-side indices
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024 / npairs, (L + 1023) / 1024));
+  *nsplit = (int)ns;
+  *part_doubles = (size_t)npairs * (size_t)ns * 4096;
+}
+
+hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s) {
+  if (m < 1 || k < 1) return hipErrorInvalidValue;
+  GramArgs g{};
+  g.X = X;
+  g.m = m;
+  g.k = k;
+  g.trans = m > k ? 1 : 0;
+  g.n = (int)std::min(m, k);
+  g.nb = (g.n + 63) / 64;
+  size_t pd = 0;
+  gram_plan(m, k, &g.nsplit, &pd);
+  const int64_t L = std::max(m, k);
+  g.chunk = ((L + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
+  g.part = part;
+  g.G = G;
+  const int npairs = g.nb * (g.nb + 1) / 2;
+  k_gram<<<dim3((unsigned)npairs, (unsigned)g.nsplit), 256, 0, s>>>(g);
+  NTT_CHECK_LAUNCH();
+  k_gram_reduce<<<(unsigned)npairs, 256, 0, s>>>(g);
+  NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
 

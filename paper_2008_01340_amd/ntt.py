@@ -58,6 +58,7 @@ class NttConfig(C.Structure):
         ("precision", C.c_int32),
         ("fp32_tail_iters", C.c_int32),
         ("flags", C.c_uint32),
+        ("rank_eps", C.c_double),
     ]
 
 
@@ -205,7 +206,7 @@ class Plan:
     """Owns an ntt_plan_t; keeps the host arrays the config points to alive."""
 
     def __init__(self, dims, ranks, max_iters, tol=0.0, check_every=10, eps=1e-12, seed=0,
-                 precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0):
+                 precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, rank_eps=0.0):
         lib = load()
         self.dims = [int(n) for n in dims]
         self.ranks = [int(r) for r in ranks]
@@ -215,8 +216,9 @@ class Plan:
         self.cfg = NttConfig(self.d, C.cast(self._dims, C.POINTER(C.c_int64)),
                              C.cast(self._ranks, C.POINTER(C.c_int64)), int(max_iters), float(tol),
                              int(check_every), float(eps), int(seed) & ((1 << 64) - 1),
-                             int(precision), int(fp32_tail_iters), int(flags))
+                             int(precision), int(fp32_tail_iters), int(flags), float(rank_eps))
         self.max_iters = int(max_iters)
+        self.rank_eps = float(rank_eps)
         self.handle = C.c_void_p()
         _check(lib.ntt_plan(C.byref(self.cfg), C.byref(self.handle)), "ntt_plan")
 
@@ -310,8 +312,11 @@ def _stream_handle(torch, stream):
 def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10,
               precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, init_W=None, init_H=None,
               record_objective=False, plan=None, workspace=None, cores=None, stream=None,
-              want_report=True):
-    """Decompose a float32 CUDA tensor; allocates cores/workspace with torch if not given."""
+              want_report=True, rank_eps=0.0):
+    """Decompose a float32 CUDA tensor; allocates cores/workspace with torch if not given.
+
+    With rank_eps > 0 the ranks are chosen by the rule of Alg.2 (``ranks`` are caps);
+    the returned cores are views of the (cap-sized) buffers at the chosen ranks."""
     import torch
     assert A.is_cuda and A.dtype == torch.float32 and A.is_contiguous()
     dims = list(A.shape)
@@ -319,7 +324,10 @@ def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10
         flags |= NTT_RECORD_OBJECTIVE
     if plan is None:
         plan = Plan(dims, ranks, max_iters, tol=tol, check_every=check_every, eps=eps, seed=seed,
-                    precision=precision, fp32_tail_iters=fp32_tail_iters, flags=flags)
+                    precision=precision, fp32_tail_iters=fp32_tail_iters, flags=flags,
+                    rank_eps=rank_eps)
+    if plan.rank_eps > 0.0:
+        want_report = True  # the chosen ranks come back in the report
     nbytes, eff, _ = plan.workspace()
     if workspace is None:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=A.device)
@@ -334,6 +342,10 @@ def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10
     rep = ntt_decompose(plan, _stream_handle(torch, stream), workspace.data_ptr(), A.data_ptr(),
                         [c.data_ptr() for c in cores], iw, ih,
                         trace.data_ptr() if trace is not None else None, want_report)
+    if plan.rank_eps > 0.0:
+        eff = rep["eff_ranks"]
+        cores = [c.reshape(-1)[: eff[k] * dims[k] * eff[k + 1]].view(eff[k], dims[k], eff[k + 1])
+                 for k, c in enumerate(cores)]
     return Decomposition(cores, eff, rep, trace)
 
 

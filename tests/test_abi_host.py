@@ -81,6 +81,9 @@ def test_plan_strict_ranks_errors():
     ({"precision": 7}, (4, 5), (1, 2, 1)),
     ({}, (64, 64, 64), (1, 40, 40, 1)),          # effective rank above 32
     ({}, (1 << 32, 1 << 32, 4), (1, 1, 1, 1)),   # product overflows
+    ({"rank_eps": -0.1}, (4, 5), (1, 2, 1)),
+    ({"rank_eps": float("inf")}, (4, 5), (1, 2, 1)),
+    ({"rank_eps": 0.1}, (3000, 3000), (1, 8, 1)),  # rank rule: shorter side above 2048
 ])
 def test_plan_rejects_invalid_configs(kw, dims, ranks):
     args = {"max_iters": 10}
@@ -129,6 +132,24 @@ def test_workspace_scales_with_the_problem():
     # the 32^5 sweep holds H_1 (8 x 32^4 floats) in the workspace
     assert big >= 8 * 32 ** 4 * 4
     assert small < big
+
+
+def test_rank_rule_plan_reports_caps_and_covers_every_rank():
+    # with rank_eps > 0 the planned ranks are caps: the query reports them, and the
+    # workspace covers the caps' plan plus the Gram, eigenvalues and solver scratch
+    dims, ranks = (20, 24, 30, 18), (1, 12, 16, 9, 1)
+    given = ntt.Plan(dims, ranks, 10)
+    rule = ntt.Plan(dims, ranks, 10, rank_eps=0.05)
+    wg, eg, cg = given.workspace()
+    wr, er, cr = rule.workspace()
+    assert er == eg == [1, 12, 16, 9, 1] and cr == cg
+    assert wr >= wg + 8 * (24 * 12) ** 2  # at least the largest Gram (288 x 288 FP64)
+    lib = ntt.load()
+    cfgs = (ntt.NttConfig * 1)()
+    b = ntt.Plan((4, 5), (1, 2, 1), 10, rank_eps=0.1)
+    cfgs[0] = b.cfg
+    out = ctypes.c_void_p()
+    assert lib.ntt_batch_plan(1, cfgs, ctypes.byref(out)) == ntt.NTT_ERR_INVALID_ARG
 
 
 def test_batch_plan_validation_and_workspace():

@@ -504,6 +504,67 @@ def test_full_size_256pow4_paper_workload_sampled_parity():
     assert e_gpu < 1.0
 
 
+# ------------------------------------------------------------------ f1: the rank rule of Alg.2
+def _tail_ratios(X):
+    s = np.linalg.svd(np.asarray(X, dtype=np.float64), compute_uv=False)
+    s2 = s * s
+    tails = np.concatenate([np.cumsum(s2[::-1])[::-1][1:], [0.0]])
+    return np.sqrt(tails / max(np.sum(s2[::-1]), 1e-300))
+
+
+@pytest.mark.parametrize("m,k,R,noise", [
+    (150, 3000, 5, 1e-3),     # G = X X^T, 3 x 3 blocks of 64, ragged
+    (3000, 130, 7, 1e-3),     # G = X^T X (the shorter side is k)
+    (70, 200000, 4, 1e-2),    # many chunks of the long side
+    (40, 40, 3, 0.0),         # square, exact rank
+])
+def test_rank_rule_matches_oracle_on_matrices(m, k, R, noise):
+    # X = W H + noise, non-negative; the rule's rank for thresholds on both sides of the
+    # spectral gap equals the oracle's (both decide in FP64)
+    say(f"case: rank rule, m={m} k={k} R={R}")
+    rng = np.random.default_rng(m + k)
+    X = (rng.random((m, R)) @ rng.random((R, k)) + noise * rng.random((m, k))).astype(np.float32)
+    ratios = _tail_ratios(X)
+    Xd = dev(X)
+    for eps in (0.5, 0.2, 0.05, 0.01, 1e-3, 1e-5):
+        if np.min(np.abs(ratios - eps)) < 1e-6 * max(eps, 1e-3):
+            continue  # a threshold on a tail ratio is not a fair test of FP64 agreement
+        want = min(O.eps_rank(X, eps), 32, m, k)
+        res = ntt.decompose(Xd, (1, 32, 1), 2, rank_eps=eps, seed=4)
+        assert res.ranks[1] == want, (eps, res.ranks, want)
+        assert tuple(res.cores[0].shape) == (1, m, want) and tuple(res.cores[1].shape) == (want, k, 1)
+
+
+def test_rank_rule_sweep_matches_oracle():
+    say("case: rank-rule sweep 12x14x16x10, caps (1,32,32,32,1), T=60")
+    dims, gen = (12, 14, 16, 10), (1, 3, 5, 4, 1)
+    A = S.noisy_tensor(dims, gen, seed=21, noise="mult", level=0.001)
+    T = 60
+    for eps in (0.05, 0.01):
+        ref = O.ntt_decompose(A, (1, 32, 32, 32, 1), T, seed=9, rank_eps=eps)
+        # the decisions are taken away from the thresholds (else FP32 vs FP64 iterates
+        # could legitimately disagree)
+        for st_ in ref["stages"]:
+            rt = _tail_ratios(st_["X"])
+            assert np.min(np.abs(rt - eps)) > 1e-4 * eps
+        res = ntt.decompose(dev(A), (1, 32, 32, 32, 1), T, seed=9, rank_eps=eps)
+        assert list(res.ranks) == list(ref["ranks"]), (eps, res.ranks, ref["ranks"])
+        for cg, co in zip(res.cores, ref["cores"]):
+            assert tuple(cg.shape) == co.shape
+            assert rel(host(cg), co) <= 1e-4
+        e_gpu = ntt.rel_error(dev(A), res.cores)
+        e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+        say(f"  eps={eps}: ranks {res.ranks}, rel err gpu {e_gpu:.6e} oracle {e_orc:.6e}")
+        assert e_gpu == pytest.approx(e_orc, rel=1e-4)
+    # the same plan run twice gives the same ranks and bits (the stage is re-planned)
+    plan = ntt.Plan(dims, (1, 32, 32, 32, 1), T, seed=9, rank_eps=0.01)
+    a = ntt.decompose(dev(A), (1, 32, 32, 32, 1), T, plan=plan)
+    b = ntt.decompose(dev(A), (1, 32, 32, 32, 1), T, plan=plan)
+    assert a.ranks == b.ranks
+    for ca, cb in zip(a.cores, b.cores):
+        assert torch.equal(ca, cb)
+
+
 # ------------------------------------------------------------------ a8: BF16 precision mode
 BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
 
