@@ -25,7 +25,7 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
-EXTRAS = ("precision_mode", "paper_workload", "batched", "serving")
+EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "batched", "serving")
 # HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8<2> on 768
 # workgroups, W-update prologue): rocprofv3 FETCH_SIZE (83,932.4 KiB) and WRITE_SIZE
 # (35,211.0 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
@@ -125,6 +125,30 @@ def paper_workload(ntt, S, torch):
                         "gflop": res.report["total_gflop"], "rel_error": ntt.rel_error(A, res.cores),
                         "stage_ms": res.report["ms"], "compression": res.report["compression_ratio"]}
         progress(f"paper workload: ranks {r}: {ms:.1f} ms")
+    del A
+    return out
+
+
+def rank_rule(ntt, S, torch):
+    """Compression against relative error with the rank rule of Alg.2 (the style of the
+    paper's Fig.8), on the 128^4 workload, rank caps 16, for the paper's thresholds."""
+    w = S.workload("tt128x4_r16")
+    A = torch.from_numpy(w.tensor()).cuda()
+    caps = (1, 16, 16, 16, 1)
+    out = {"workload": f"{w.name}: {w.note}; rank caps 16", "points": []}
+    for eps in (0.5, 0.25, 0.125, 0.075, 0.01, 0.005, 0.001):
+        plan = ntt.Plan(w.dims, caps, w.iters, eps=w.eps, seed=w.seed, rank_eps=eps)
+        res = ntt.decompose(A, caps, w.iters, plan=plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ntt.decompose(A, caps, w.iters, plan=plan)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out["points"].append({"rank_eps": eps, "ranks": res.ranks, "ms": ms,
+                              "compression": res.report["compression_ratio"],
+                              "rel_error": ntt.rel_error(A, res.cores),
+                              "stage_ms": res.report["ms"]})
+        progress(f"rank rule: eps {eps}: ranks {res.ranks}, {ms:.1f} ms")
     del A
     return out
 
@@ -322,6 +346,9 @@ def main():
         torch.cuda.empty_cache()
     if "paper_workload" in extras:
         out["paper_workload"] = paper_workload(ntt, S, torch)
+        torch.cuda.empty_cache()
+    if "rank_rule" in extras:
+        out["rank_rule"] = rank_rule(ntt, S, torch)
         torch.cuda.empty_cache()
     if "batched" in extras:
         out["batched"] = batched(ntt, S, torch)
