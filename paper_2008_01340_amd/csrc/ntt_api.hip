@@ -48,6 +48,12 @@ ntt_status fail(ntt_status s, const std::string& msg) {
 #define NTT_MAX_PASS_BLOCKS 1024
 #endif
 constexpr int kMaxPassBlocks = NTT_MAX_PASS_BLOCKS;  // persistent grid of the fused pass
+#ifndef NTT_R8_WIDE
+#define NTT_R8_WIDE 1
+#endif
+#ifndef NTT_R8W_CAP
+#define NTT_R8W_CAP 512
+#endif
 #ifndef NTT_L_MAX_BLOCKS
 #define NTT_L_MAX_BLOCKS 768
 #endif
@@ -77,7 +83,7 @@ struct Stage {
   int nch = 0;      // PASS_C: row chunks
   bool pro_ok = false;  // the update pass can apply the W-update in its prologue (r <= 8 pass)
   bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
-  bool wide = false;   // PASS_L: update passes by the wide pass (64-column steps)
+  bool wide = false;   // PASS_L, PASS_S (r <= 8): update passes in 64-column steps
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
@@ -113,7 +119,11 @@ void classify_stage(Stage& s, int precision) {
     if (s.mb <= 2 && s.r <= 8) cap = std::min<int64_t>(gcap, 768);
     if (s.mb == 4) cap = std::min<int64_t>(gcap, 768);
     if (s.mb == 8) cap = std::min<int64_t>(gcap, 512);
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>((ngroups + 3) / 4, cap));
+    // the r <= 8 pass in 64-column steps (one per wave) once there are enough of them
+    s.wide = NTT_R8_WIDE && s.mb <= 2 && s.r <= 8 && ngroups >= 4 * 4 * 256;
+    const int64_t units = s.wide ? ((ngroups + 3) / 4 + 3) / 4 : (ngroups + 3) / 4;
+    if (s.wide && s.mb == 2) cap = std::min<int64_t>(cap, NTT_R8W_CAP);  // two per CU at its registers
+    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, cap));
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
     // the batched update pass takes B whole groups per step; otherwise column groups
@@ -495,7 +505,7 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
 }
 
 hipError_t run_pass(hipStream_t q, const Stage& s, const PassArgs& a, bool update, bool resid) {
-  if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, q);
+  if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, s.wide, q);
   if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, s.wide, q);
   if (s.kind == PASS_C) return launch_pass_C(a, s.rp, s.G, update, resid, q);
   return launch_pass_generic(a, s.rp, s.G, s.chunk, update, resid, q);

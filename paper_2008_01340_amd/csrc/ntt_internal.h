@@ -93,7 +93,7 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, in
                         int validate, double* out, hipStream_t s);
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
-                             hipStream_t s);
+                             bool wide, hipStream_t s);
 int pass_L_class(int64_t m, int rp);  // -1 when m is beyond the row-split variant
 int pass_L_waves(int cls);
 // 16-column groups per step of the wide row-split update pass for a row class (0: the

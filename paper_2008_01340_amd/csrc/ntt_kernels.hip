@@ -567,6 +567,90 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
   if (RESID && tid == 0) p.rpart[blockIdx.x] = ((sRes[0] + sRes[1]) + sRes[2]) + sRes[3];
 }
 
+// W^T (zero padded, 16 x MPAD) and G_W (8 x 8) of the r <= 8 passes in LDS: from W and
+// W^T W, or, in prologue mode (p.Wprev set), by applying the previous iteration's
+// W-update first (the rows of k_wupdate, one thread per row; the Gram by wavefront 0,
+// which holds every row since m <= 64); workgroup 0 then stores W to p.Wout.
+template <int MPAD>
+__device__ __forceinline__ void r8_w_setup(const PassArgs& p, float (*sWt)[MPAD + 4], float (*sG)[8],
+                                           int tid, int w, int a, int b) {
+  const int m = p.m, r = p.r;
+  if (p.Wprev) {
+    __shared__ float sWc[MPAD][9];
+    __shared__ double sGH[8][9];
+    __shared__ double sGW[8][9];
+    float wrow[8];
+    double nrow[8];
+    {
+      const int64_t base = (int64_t)min(tid, m - 1) * r;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int qc = min(q, r - 1);
+        wrow[q] = zmask(p.Wprev[base + qc], q < r);
+        nrow[q] = zmask(p.red[base + qc], q < r);
+      }
+    }
+    const int64_t mr = (int64_t)m * r;
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sGH[c][q] = zmask(p.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
+    }
+    __syncthreads();
+    if (tid < MPAD) {
+      if (tid < m) {
+        double dot = 0.0;
+        wupdate_row<8>(wrow, nrow, sGH, r, p.eps, sWc[tid], &dot);
+        if (blockIdx.x == 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (c < r) p.Wout[(int64_t)tid * r + c] = sWc[tid][c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sWc[tid][c] = 0.f;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      v4d acc[1][1] = {{v4d{0.0, 0.0, 0.0, 0.0}}};
+      gram_rows_f64<8, 1, MPAD>(sWc, acc, 0, a, b);
+      // the other wavefronts of k_wupdate add exact zeros; value i of lane (a, b) is
+      // row 4 i + b, column a
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * i + b < 8 && a < 8) sGW[4 * i + b][a] = acc[0][0][i];
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * MPAD; e += 256) {
+      const int i = e / 16, c = e % 16;
+      sWt[c][i] = c < 8 ? sWc[i][c < 8 ? c : 0] : 0.f;
+    }
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sG[c][q] = (c < r && q < r) ? (float)sGW[c][q] : 0.f;
+    }
+  } else {
+    constexpr int NWL = (16 * MPAD + 255) / 256;
+    float wtmp[NWL];
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      const int i = e / 16, c = e % 16;
+      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
+      wtmp[t] = zmask(v, e < 16 * MPAD && i < m && c < r);
+    }
+#pragma unroll
+    for (int t = 0; t < NWL; ++t) {
+      const int e = tid + 256 * t;
+      if (e < 16 * MPAD) sWt[e % 16][e / 16] = wtmp[t];
+    }
+    if (tid < 64) {
+      const int c = tid >> 3, q = tid & 7;
+      sG[c][q] = p.GW[c * 16 + q];  // zero beyond r
+    }
+  }
+}
+
 // ------------------------------------------------------------------ fused MU pass, r <= 8
 // Specialisation of k_mu_pass (UPDATE only) for r <= 8.  The two 16-wide MFMA products
 // (W^T X and X H_new^T) keep the MFMA path; the r x r products (W^T W) H and
@@ -644,82 +728,7 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   float xn[MB][4], hn_[4];
   if (g < ngroups) load_group(g, xn, hn_);
 #endif
-  if (p.Wprev) {
-    // W-update of the previous iteration (the rows of k_wupdate, one thread per row; the
-    // Gram by wavefront 0, which holds every row since m <= 64), then W^T and G_W to LDS
-    __shared__ float sWc[MPAD][9];
-    __shared__ double sGH[8][9];
-    __shared__ double sGW[8][9];
-    float wrow[8];
-    double nrow[8];
-    {
-      const int64_t base = (int64_t)min(tid, m - 1) * r;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int qc = min(q, r - 1);
-        wrow[q] = zmask(p.Wprev[base + qc], q < r);
-        nrow[q] = zmask(p.red[base + qc], q < r);
-      }
-    }
-    const int64_t mr = (int64_t)m * r;
-    if (tid < 64) {
-      const int c = tid >> 3, q = tid & 7;
-      sGH[c][q] = zmask(p.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
-    }
-    __syncthreads();
-    if (tid < MPAD) {
-      if (tid < m) {
-        double dot = 0.0;
-        wupdate_row<8>(wrow, nrow, sGH, r, p.eps, sWc[tid], &dot);
-        if (blockIdx.x == 0) {
-#pragma unroll
-          for (int c = 0; c < 8; ++c)
-            if (c < r) p.Wout[(int64_t)tid * r + c] = sWc[tid][c];
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) sWc[tid][c] = 0.f;
-      }
-    }
-    __syncthreads();
-    if (w == 0) {
-      v4d acc[1][1] = {{v4d{0.0, 0.0, 0.0, 0.0}}};
-      gram_rows_f64<8, 1, MPAD>(sWc, acc, 0, a, b);
-      // the other wavefronts of k_wupdate add exact zeros; value i of lane (a, b) is
-      // row 4 i + b, column a
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (4 * i + b < 8 && a < 8) sGW[4 * i + b][a] = acc[0][0][i];
-    }
-    __syncthreads();
-    for (int e = tid; e < 16 * MPAD; e += 256) {
-      const int i = e / 16, c = e % 16;
-      sWt[c][i] = c < 8 ? sWc[i][c < 8 ? c : 0] : 0.f;
-    }
-    if (tid < 64) {
-      const int c = tid >> 3, q = tid & 7;
-      sG[c][q] = (c < r && q < r) ? (float)sGW[c][q] : 0.f;
-    }
-  } else {
-    constexpr int NWL = (16 * MPAD + 255) / 256;
-    float wtmp[NWL];
-#pragma unroll
-    for (int t = 0; t < NWL; ++t) {
-      const int e = tid + 256 * t;
-      const int i = e / 16, c = e % 16;
-      const float v = p.W[(int64_t)min(i, m - 1) * r + min(c, r - 1)];
-      wtmp[t] = zmask(v, e < 16 * MPAD && i < m && c < r);
-    }
-#pragma unroll
-    for (int t = 0; t < NWL; ++t) {
-      const int e = tid + 256 * t;
-      if (e < 16 * MPAD) sWt[e % 16][e / 16] = wtmp[t];
-    }
-    if (tid < 64) {
-      const int c = tid >> 3, q = tid & 7;
-      sG[c][q] = p.GW[c * 16 + q];  // zero beyond r
-    }
-  }
+  r8_w_setup<MPAD>(p, sWt, sG, tid, w, a, b);
   __syncthreads();
 
   v4f accW[MB];     // X H_new^T: lane (a,b) reg i -> row 16*blk+4b+i, rank a
@@ -867,6 +876,218 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
             gbuf[idx] = (turn == 3) ? pg[i][q] : gbuf[idx] + pg[i][q];
           }
       }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * r; e += 256) dst[e] = buf[(e / r) * 16 + (e % r)];
+  for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * 8 + (e % r)];
+}
+
+// ------------------------------------------------------------------ wide r <= 8 pass
+// The r <= 8 pass over 64-column steps, one step per wave, X read as in the wide
+// row-split pass: lane (a, b) loads X[4i + b][j0 + 4a .. 4a + 3] for row quads i (4 rows
+// x 256 bytes per load instruction), which is directly the B operand of W^T X for the
+// column sets q = 0..3 (columns j0 + 4a + q).  Per step:
+//   - the W^T X values of ranks < 8 and the H tile go to LDS as [column][rank], and each
+//     lane takes one column (lane l: column j0 + l) for D_H = G_W H (VALU, 8 x 8) and the
+//     epilogue of its 8 ranks;
+//   - H_new goes to LDS as [rank][column] and to HBM (rows of 256 bytes);
+//   - X H_new^T per 16-row block (X through a per-wave transposition tile) and
+//     H_new H_new^T, both with MFMA (K = columns).
+// Partials as in k_mu_pass_r8 (waves added in the order 3, 2, 1, 0).
+template <int NQ, bool XBF>
+__global__ __launch_bounds__(256) void k_mu_pass_r8w(PassArgs p) {
+  constexpr int MPAD = 4 * NQ;  // 16 or 32 rows
+  constexpr int NB = NQ / 4;    // 16-row blocks
+  constexpr int ST = 68;        // row stride of the 64-column tiles
+  constexpr int SC = 9;         // row stride of the [column][rank] tiles
+  __shared__ __attribute__((aligned(16))) float sWt[16][MPAD + 4];
+  __shared__ __attribute__((aligned(16))) float sG[8][8];
+  __shared__ __attribute__((aligned(16))) float sT[4][16 * ST];  // per-wave X block
+  __shared__ __attribute__((aligned(16))) float sHn[4][8 * ST];  // per-wave H_new [rank][col]
+  __shared__ float sNc[4][64 * SC];                              // per-wave W^T X [col][rank]
+  __shared__ float sHc[4][64 * SC];                              // per-wave H [col][rank]
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int64_t nsteps = (k + 63) >> 6;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  const bool vec_ok = ((k & 3) == 0) && x_aligned<XBF>(p) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+  const float* hrow0 = p.H + (int64_t)min(b, r - 1) * k;      // H rows b and b + 4 (clamped)
+  const float* hrow1 = p.H + (int64_t)min(b + 4, r - 1) * k;
+
+  auto load_step = [&](int64_t st, float4 (&x)[NQ], float4 (&h)[2]) {
+    const int64_t j0 = st << 6;
+    if (vec_ok && (j0 + 64 <= k)) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = ldx4<XBF>(p, (int64_t)min(4 * i + b, m - 1) * k + j0 + 4 * a);
+      h[0] = *reinterpret_cast<const float4*>(hrow0 + j0 + 4 * a);
+      h[1] = *reinterpret_cast<const float4*>(hrow1 + j0 + 4 * a);
+    } else {  // ragged or unaligned step (rare): masked here
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t col = j0 + 4 * a + q;
+          v[q] = zmask(ldx<XBF>(p, (int64_t)min(4 * i + b, m - 1) * k + min(col, k - 1)), col < k);
+        }
+        x[i] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+      float v0[4], v1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = j0 + 4 * a + q;
+        v0[q] = zmask(hrow0[min(col, k - 1)], col < k);
+        v1[q] = zmask(hrow1[min(col, k - 1)], col < k);
+      }
+      h[0] = make_float4(v0[0], v0[1], v0[2], v0[3]);
+      h[1] = make_float4(v1[0], v1[1], v1[2], v1[3]);
+    }
+  };
+
+  int64_t st = (int64_t)blockIdx.x * 4 + w;
+  float4 xn[NQ], hn2[2];  // next step's loads, in flight while one is processed
+  if (st < nsteps) load_step(st, xn, hn2);
+  r8_w_setup<MPAD>(p, sWt, sG, tid, w, a, b);
+  __syncthreads();
+  float wa[NQ];  // W^T as the A operand of W^T X: W[4i + b][a] (zero past m and r)
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) wa[i] = sWt[a][4 * i + b];
+
+  v4f accW[NB];
+  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int blk = 0; blk < NB; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
+  float* sN = sNc[w];
+  float* sH = sHc[w];
+  float* sHw = sHn[w];
+  float* sTw = sT[w];
+
+  for (; st < nsteps; st += wstride) {
+    const int64_t j0 = st << 6;
+    float4 x[NQ], h[2];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) x[i] = xn[i];
+    h[0] = hn2[0];
+    h[1] = hn2[1];
+    if (st + wstride < nsteps) load_step(st + wstride, xn, hn2);
+
+    // W^T X of the four column sets: lane (a, b) value i of set q is rank 4b + i, column
+    // j0 + 4a + q
+    v4f nh[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nh[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      nh[0] = mfma16(wa[i], x[i].x, nh[0]);
+      nh[1] = mfma16(wa[i], x[i].y, nh[1]);
+      nh[2] = mfma16(wa[i], x[i].z, nh[2]);
+      nh[3] = mfma16(wa[i], x[i].w, nh[3]);
+    }
+    wave_sync();
+    if (b < 2) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sN[(4 * a + q) * SC + 4 * b + i] = nh[q][i];
+    }
+    {
+      const float h0v[4] = {h[0].x, h[0].y, h[0].z, h[0].w};
+      const float h1v[4] = {h[1].x, h[1].y, h[1].z, h[1].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sH[(4 * a + q) * SC + b] = (b < r) ? h0v[q] : 0.f;
+        sH[(4 * a + q) * SC + b + 4] = (b + 4 < r) ? h1v[q] : 0.f;
+      }
+    }
+    wave_sync();
+    // one column per lane: D_H = G_W H and the epilogue of ranks 0..7
+    const int64_t colg = j0 + lane;
+    float hc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) hc[c] = sH[lane * SC + c];
+    float hnew[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float4 g0 = *reinterpret_cast<const float4*>(&sG[c][0]);
+      const float4 g1 = *reinterpret_cast<const float4*>(&sG[c][4]);
+      float dh = g0.x * hc[0];
+      dh = fmaf(g0.y, hc[1], dh);
+      dh = fmaf(g0.z, hc[2], dh);
+      dh = fmaf(g0.w, hc[3], dh);
+      dh = fmaf(g1.x, hc[4], dh);
+      dh = fmaf(g1.y, hc[5], dh);
+      dh = fmaf(g1.z, hc[6], dh);
+      dh = fmaf(g1.w, hc[7], dh);
+      const float q = fmaxf(0.f, fast_div(hc[c] * sN[lane * SC + c], dh + p.eps));
+      hnew[c] = (c < r && colg < k) ? q : 0.f;
+    }
+    // H_new to LDS as [rank][column] and to HBM
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sHw[c * ST + lane] = hnew[c];
+    if (colg < k) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < r) p.H[(int64_t)c * k + colg] = hnew[c];
+    }
+    wave_sync();
+    // B operands H_new[a][j0 + 16g + 4b .. 4b + 3] (ranks 8.. are zero)
+    float4 hb[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 v = *reinterpret_cast<const float4*>(&sHw[min(a, 7) * ST + 16 * g + 4 * b]);
+      hb[g] = (a < 8) ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // H_new H_new^T (K = columns)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      accG = mfma16(hb[g].x, hb[g].x, accG);
+      accG = mfma16(hb[g].y, hb[g].y, accG);
+      accG = mfma16(hb[g].z, hb[g].z, accG);
+      accG = mfma16(hb[g].w, hb[g].w, accG);
+    }
+    // X H_new^T per 16-row block (M = row, N = rank, K = column)
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) *reinterpret_cast<float4*>(&sTw[(4 * j + b) * ST + 4 * a]) = x[4 * blk + j];
+      wave_sync();
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 xa = *reinterpret_cast<const float4*>(&sTw[a * ST + 16 * g + 4 * b]);
+        accW[blk] = mfma16(xa.x, hb[g].x, accW[blk]);
+        accW[blk] = mfma16(xa.y, hb[g].y, accW[blk]);
+        accW[blk] = mfma16(xa.z, hb[g].z, accW[blk]);
+        accW[blk] = mfma16(xa.w, hb[g].w, accW[blk]);
+      }
+    }
+  }
+
+  // ---- per-workgroup partials, waves added in the order 3, 2, 1, 0
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+  float* buf = &sT[0][0];   // MPAD x 16 floats
+  float* gbuf = &sHn[0][0];  // 8 x 8 floats
+  __syncthreads();
+  for (int turn = 3; turn >= 0; --turn) {
+    if (w == turn) {
+#pragma unroll
+      for (int blk = 0; blk < NB; ++blk)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int idx = (16 * blk + 4 * b + i) * 16 + a;
+          buf[idx] = (turn == 3) ? accW[blk][i] : buf[idx] + accW[blk][i];
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * b + i < 8 && a < 8) {
+          const int idx = (4 * b + i) * 8 + a;
+          gbuf[idx] = (turn == 3) ? accG[i] : gbuf[idx] + accG[i];
+        }
     }
     __syncthreads();
   }
@@ -2541,18 +2762,29 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
     cur ^= 1;
     __syncthreads();
   }
-  // last contraction, fused with the output or the error sums
+  // last contraction, fused with the output or the error sums; G_d is read from LDS
+  // when it fits (it is read r_{d-1} times per entry), and the row/column split of the
+  // flat index uses 32-bit division when the block's entries allow it
+  constexpr int kGd = 4096;
+  __shared__ float sGd[kGd];
   const int rl = t.ranks[d - 1];
   const int64_t nd = t.dims[d - 1];
   const float* Gd = t.cores[d - 1];
+  const bool gd_lds = (int64_t)rl * nd <= kGd;
+  if (gd_lds) {
+    for (int e = tid; e < rl * (int)nd; e += 256) sGd[e] = Gd[e];
+    __syncthreads();
+  }
   const int64_t base = r0 * nd;
   const int64_t cnt = (int64_t)nrow * nd;
   double s_err = 0.0, s_ref = 0.0;
-  for (int64_t e = tid; e < cnt; e += 256) {
-    const int rr = (int)(e / nd);
-    const int64_t col = e - (int64_t)rr * nd;
+  auto entry = [&](int64_t e, int rr, int64_t col) {
     float s = 0.f;
-    for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], Gd[(int64_t)q * nd + col], s);
+    if (gd_lds) {
+      for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], sGd[q * (int)nd + (int)col], s);
+    } else {
+      for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], Gd[(int64_t)q * nd + col], s);
+    }
     if (MODE == 0) {
       t.out[base + e] = s;
     } else {
@@ -2560,6 +2792,18 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
       const double dv = av - (double)s;
       s_err += dv * dv;
       s_ref += av * av;
+    }
+  };
+  if (cnt < ((int64_t)1 << 31)) {
+    const int nd32 = (int)nd, cnt32 = (int)cnt;
+    for (int e = tid; e < cnt32; e += 256) {
+      const int rr = e / nd32;
+      entry(e, rr, e - rr * nd32);
+    }
+  } else {
+    for (int64_t e = tid; e < cnt; e += 256) {
+      const int rr = (int)(e / nd);
+      entry(e, rr, e - (int64_t)rr * nd);
     }
   }
   if (MODE == 1) {
@@ -2678,9 +2922,20 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
 }
 
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
-                             hipStream_t s) {
+                             bool wide, hipStream_t s) {
   if (rp == 16 && a.r <= 8 && mb <= 2 && update && !resid) {
     const bool xb = a.Xb != nullptr;
+    if (wide) {
+      if (mb == 1) {
+        if (xb) k_mu_pass_r8w<4, true><<<grid, 256, 0, s>>>(a);
+        else k_mu_pass_r8w<4, false><<<grid, 256, 0, s>>>(a);
+      } else {
+        if (xb) k_mu_pass_r8w<8, true><<<grid, 256, 0, s>>>(a);
+        else k_mu_pass_r8w<8, false><<<grid, 256, 0, s>>>(a);
+      }
+      NTT_CHECK_LAUNCH();
+      return hipSuccess;
+    }
     switch (mb) {
       case 1:
         if (xb) k_mu_pass_r8<1, true><<<grid, 256, 0, s>>>(a);
