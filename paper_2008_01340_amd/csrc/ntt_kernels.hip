@@ -895,8 +895,15 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 //   - X H_new^T per 16-row block (X through a per-wave transposition tile) and
 //     H_new H_new^T, both with MFMA (K = columns).
 // Partials as in k_mu_pass_r8 (waves added in the order 3, 2, 1, 0).
+#ifndef NTT_R8W_WAVES
+#define NTT_R8W_WAVES 1
+#endif
+#ifndef NTT_R8W_PF
+#define NTT_R8W_PF 0
+#endif
 template <int NQ, bool XBF>
-__global__ __launch_bounds__(256) void k_mu_pass_r8w(PassArgs p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTT_R8W_WAVES)))
+void k_mu_pass_r8w(PassArgs p) {
   constexpr int MPAD = 4 * NQ;  // 16 or 32 rows
   constexpr int NB = NQ / 4;    // 16-row blocks
   constexpr int ST = 68;        // row stride of the 64-column tiles
@@ -951,7 +958,7 @@ __global__ __launch_bounds__(256) void k_mu_pass_r8w(PassArgs p) {
 
   int64_t st = (int64_t)blockIdx.x * 4 + w;
   float4 xn[NQ], hn2[2];  // next step's loads, in flight while one is processed
-  if (st < nsteps) load_step(st, xn, hn2);
+  if (NTT_R8W_PF && st < nsteps) load_step(st, xn, hn2);
   r8_w_setup<MPAD>(p, sWt, sG, tid, w, a, b);
   __syncthreads();
   float wa[NQ];  // W^T as the A operand of W^T X: W[4i + b][a] (zero past m and r)
@@ -970,11 +977,15 @@ __global__ __launch_bounds__(256) void k_mu_pass_r8w(PassArgs p) {
   for (; st < nsteps; st += wstride) {
     const int64_t j0 = st << 6;
     float4 x[NQ], h[2];
+#if NTT_R8W_PF
 #pragma unroll
     for (int i = 0; i < NQ; ++i) x[i] = xn[i];
     h[0] = hn2[0];
     h[1] = hn2[1];
     if (st + wstride < nsteps) load_step(st + wstride, xn, hn2);
+#else
+    load_step(st, x, h);
+#endif
 
     // W^T X of the four column sets: lane (a, b) value i of set q is rank 4b + i, column
     // j0 + 4a + q
