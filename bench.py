@@ -26,11 +26,11 @@ def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
 EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "batched", "serving")
-# HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8<2> on 768
-# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (83,932.4 KiB) and WRITE_SIZE
-# (35,211.0 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
+# HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8w<8> on 512
+# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (82,023.8 KiB) and WRITE_SIZE
+# (33,408.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
 # copy (x2.00, x1.00).  Taken on the current pass kernel; re-measure when it changes.
-MEASURED_TRAFFIC = {"tt32x5_r8": 171.894e6 + 36.056e6}
+MEASURED_TRAFFIC = {"tt32x5_r8": 167.985e6 + 34.210e6}
 
 
 def parse():

@@ -2773,29 +2773,18 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
     cur ^= 1;
     __syncthreads();
   }
-  // last contraction, fused with the output or the error sums; G_d is read from LDS
-  // when it fits (it is read r_{d-1} times per entry), and the row/column split of the
-  // flat index uses 32-bit division when the block's entries allow it
-  constexpr int kGd = 4096;
-  __shared__ float sGd[kGd];
+  // last contraction, fused with the output or the error sums
   const int rl = t.ranks[d - 1];
   const int64_t nd = t.dims[d - 1];
   const float* Gd = t.cores[d - 1];
-  const bool gd_lds = (int64_t)rl * nd <= kGd;
-  if (gd_lds) {
-    for (int e = tid; e < rl * (int)nd; e += 256) sGd[e] = Gd[e];
-    __syncthreads();
-  }
   const int64_t base = r0 * nd;
   const int64_t cnt = (int64_t)nrow * nd;
   double s_err = 0.0, s_ref = 0.0;
-  auto entry = [&](int64_t e, int rr, int64_t col) {
+  for (int64_t e = tid; e < cnt; e += 256) {
+    const int rr = (int)(e / nd);
+    const int64_t col = e - (int64_t)rr * nd;
     float s = 0.f;
-    if (gd_lds) {
-      for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], sGd[q * (int)nd + (int)col], s);
-    } else {
-      for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], Gd[(int64_t)q * nd + col], s);
-    }
+    for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], Gd[(int64_t)q * nd + col], s);
     if (MODE == 0) {
       t.out[base + e] = s;
     } else {
@@ -2803,18 +2792,6 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
       const double dv = av - (double)s;
       s_err += dv * dv;
       s_ref += av * av;
-    }
-  };
-  if (cnt < ((int64_t)1 << 31)) {
-    const int nd32 = (int)nd, cnt32 = (int)cnt;
-    for (int e = tid; e < cnt32; e += 256) {
-      const int rr = e / nd32;
-      entry(e, rr, e - rr * nd32);
-    }
-  } else {
-    for (int64_t e = tid; e < cnt; e += 256) {
-      const int rr = (int)(e / nd);
-      entry(e, rr, e - (int64_t)rr * nd);
     }
   }
   if (MODE == 1) {
