@@ -89,10 +89,13 @@ SHAPES = [
     (100, 9000, 12), (1100, 8200, 5),
     # one wavefront per group with 4 and 8 row blocks (33..128 rows, >= 1024 groups)
     (60, 17000, 7), (120, 16500, 14),
-    # the batched row-split update pass, 129..256 rows (4 waves): an odd k (scalar loads,
-    # last step partly past the last group) and a k of whole steps at rank 16; 8 waves
-    # of 8 row blocks (two groups per step) with a ragged last step
-    (200, 3001, 11), (250, 4096, 16), (900, 2504, 9),
+    # the wide row-split update pass: 129..256 rows (4 waves) with an odd k (scalar loads,
+    # last step partly past the end) and a k of whole steps at rank 16; 8 waves with a
+    # ragged last step; 33..64 rows with >= 256 steps
+    (200, 3001, 11), (250, 4096, 16), (900, 2504, 9), (300, 17000, 13), (50, 16390, 6),
+    # the wide r <= 8 pass (>= 4096 groups): 32 rows with an odd k (every step on the
+    # masked path), 16 rows of whole steps, 25 rows with a ragged last step
+    (30, 70001, 7), (16, 65600, 8), (25, 66000, 5),
 ]
 
 
@@ -575,6 +578,7 @@ BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
     ((24, 30, 20, 36), (1, 6, 8, 5, 1), "mult", 0.01, 150),
     ((1200, 8, 8), (1, 6, 4, 1), "mult", 0.01, 150),  # stage 1 transposed (1200 x 64)
     ((40, 40, 40, 30), (1, 32, 16, 8, 1), "mult", 0.01, 100),  # stage 2 row-chunked (1280 x 1200)
+    ((20, 40, 40, 50), (1, 6, 5, 4, 1), "mult", 0.01, 100),  # stage 1 on the wide r <= 8 pass
     ((64, 32, 40, 40), (1, 16, 8, 6, 1), "mult", 0.01, 120),   # stage 1 on the S pass, 4 row blocks
 ])
 def test_bf16_mode_final_error_matches_oracle(dims, gen, noise, level, T):
