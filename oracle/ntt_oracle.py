@@ -17,6 +17,9 @@ What it follows
   is the Lee-Seung rule for min 1/2 ||X - W H||_F^2 with W, H >= 0, H updated first:
       H <- max(0, H * (W^T X) / ((W^T W) H + eps))
       W <- max(0, W * (X H^T) / (W (H H^T) + eps))
+* NMF by Alg.3 (``bcd_nmf``): projected-gradient block steps, W then H, from
+  extrapolated points, with the objective test keeping or dropping each new pair;
+  the readings of the garbled listing are B1-B8 at that section.
 * Objective 1/2 ||X - W H||_F^2 (Alg.3, the correction test), computed here as the
   explicit residual, never by the Gram identity.
 * Eq.(3) relative error, Eq.(4) compression ratio.
@@ -179,6 +182,125 @@ def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
             "snaps": snaps, "norm_x": nx}
 
 
+# ---------------------------------------------------------------- NMF by BCD (Alg.3)
+# Alg.3 minimises the same objective by alternating projected-gradient steps on the
+# two blocks (W first, then H), each from an extrapolated point, with the objective
+# test deciding whether the new pair is kept ("extrapolation") or dropped
+# ("correction").  Readings of the listing, where it is garbled or silent:
+#   B1  the W step subtracts the scaled gradient, W = max(0, W_m - G_W / L_W), as the
+#       H step of the listing does (the W line prints no G_W term);
+#   B2  the step sizes are 1/L with L_W = ||H H^T||_F and L_H = ||W^T W||_F (the H line's
+#       square root is read as this norm; the Frobenius norm bounds the spectral norm,
+#       the Lipschitz constant of the block gradient, from above, so every plain step
+#       descends); a zero L takes no gradient step (the block is only projected);
+#   B3  no per-iteration L1 normalisation of W: it would rescale W H without a matching
+#       rescale of H, and the block-coordinate method the paper cites has none;
+#   B4  the starting objective is 1/2 ||X||_F^2 (the objective at W = H = 0; the
+#       listing prints ||X|| without the square);
+#   B5  the random factors are scaled to ||W||_F = ||H||_F = sqrt(||X||_F) and form the
+#       first iterate and also its "previous" iterate;
+#   B6  a correction returns to the last kept pair (with its X H^T and H H^T) and the
+#       next iteration starts from it without extrapolation; t and the objective are
+#       unchanged (a random restart would throw away all progress);
+#   B7  w = (t - 1) / t+ with t+ = (1 + sqrt(1 + 4 t^2)) / 2; the caps compare the
+#       Gram norms of the partner block at the two last kept iterates,
+#       w_W = min(w, delta sqrt(||H_{l-1} H_{l-1}^T||_F / ||H_l H_l^T||_F)),
+#       w_H = min(w, delta sqrt(||W_{l-1}^T W_{l-1}||_F / ||W_l^T W_l||_F)),
+#       a zero denominator leaving w; delta (a user parameter) defaults to 0.9999;
+#   B8  the result is the last kept pair; the objective of the test is the explicit
+#       residual 1/2 ||X - W H||_F^2.
+def bcd_lipschitz(G) -> float:
+    """B2: the step constant of a block, the Frobenius norm of its r x r Gram."""
+    return math.sqrt(float(np.sum(np.asarray(G, dtype=np.float64) ** 2)))
+
+
+def bcd_step_W(XHt, HHt, Wm):
+    """The W block step of Alg.3 (B1, B2) from the extrapolated W_m, given X H^T and
+    H H^T of the kept H.  Returns (W, L_W)."""
+    L = bcd_lipschitz(HHt)
+    if L == 0.0:
+        return np.maximum(0.0, Wm), L
+    return np.maximum(0.0, Wm - (Wm @ HHt - XHt) / L), L
+
+
+def bcd_step_H(WtX, WtW, Hm):
+    """The H block step of Alg.3 (B2) from the extrapolated H_m, given W^T X and W^T W of
+    the new W.  Column j of the result depends only on column j of W^T X and H_m.
+    Returns (H, L_H)."""
+    L = bcd_lipschitz(WtW)
+    if L == 0.0:
+        return np.maximum(0.0, Hm), L
+    return np.maximum(0.0, Hm - (WtW @ Hm - WtX) / L), L
+
+
+def bcd_normalise(X, W0, H0):
+    """B5: scale the random factors to Frobenius norm sqrt(||X||_F) (a zero factor is
+    left as it is)."""
+    nx = math.sqrt(float(np.sum(np.asarray(X, dtype=np.float64) ** 2)))
+    W = np.array(W0, dtype=np.float64)
+    H = np.array(H0, dtype=np.float64)
+    nw = math.sqrt(float(np.sum(W * W)))
+    nh = math.sqrt(float(np.sum(H * H)))
+    if nw > 0.0:
+        W = W / nw * math.sqrt(nx)
+    if nh > 0.0:
+        H = H / nh * math.sqrt(nx)
+    return W, H
+
+
+def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
+    """NMF of X by Alg.3 (BCD with extrapolation and correction) from (W0, H0).
+
+    Returns a dict with the kept pair W, H, ``corrections`` (how many iterations were
+    dropped), ``kept`` (per iteration: True when kept), ``objective`` (the objective of
+    each iteration's candidate pair, kept or not), ``t`` and ``w`` (the extrapolation
+    sequence after each iteration), and ``snaps[t] = (W, H)`` after t iterations.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    W, H = bcd_normalise(X, W0, H0)
+    Wp, Hp = W, H
+    Wm, Hm = W, H
+    HHt, XHt = H @ H.T, X @ H.T
+    gH, gW = bcd_lipschitz(HHt), bcd_lipschitz(W.T @ W)
+    t = 1.0
+    obj = 0.5 * float(np.sum(X * X))  # B4
+    snaps = {}
+    if 0 in snapshots:
+        snaps[0] = (W.copy(), H.copy())
+    kept, f_hist, t_hist, w_hist = [], [], [], []
+    for it in range(1, iters + 1):
+        Wn, _ = bcd_step_W(XHt, HHt, Wm)
+        WtW = Wn.T @ Wn
+        Hn, LH = bcd_step_H(Wn.T @ X, WtW, Hm)
+        f = objective(X, Wn, Hn)
+        f_hist.append(f)
+        if f >= obj:  # correction (B6)
+            kept.append(False)
+            Wm, Hm = W, H
+            w = 0.0
+        else:  # extrapolation (B7)
+            kept.append(True)
+            tp = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * t * t))
+            w = (t - 1.0) / tp
+            HHn = Hn @ Hn.T
+            gHn, gWn = bcd_lipschitz(HHn), LH
+            wW = min(w, delta * math.sqrt(gH / gHn)) if gHn > 0.0 else w
+            wH = min(w, delta * math.sqrt(gW / gWn)) if gWn > 0.0 else w
+            Wp, Hp, W, H = W, H, Wn, Hn
+            HHt, XHt = HHn, X @ Hn.T
+            gH, gW = gHn, gWn
+            Wm = W + wW * (W - Wp)
+            Hm = H + wH * (H - Hp)
+            t, obj = tp, f
+        t_hist.append(t)
+        w_hist.append(w)
+        if it in snapshots:
+            snaps[it] = (W.copy(), H.copy())
+    return {"W": W, "H": H, "iters": iters, "corrections": kept.count(False), "kept": kept,
+            "objective": np.array(f_hist), "t": np.array(t_hist), "w": np.array(w_hist),
+            "snaps": snaps, "norm_x": math.sqrt(float(np.sum(X * X)))}
+
+
 # ---------------------------------------------------------------- rank selection
 def eps_rank(X, eps) -> int:
     """The rank rule of Alg.2: the smallest k >= 1 such that
@@ -199,8 +321,10 @@ def eps_rank(X, eps) -> int:
 
 # ---------------------------------------------------------------- the nTT sweep
 def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
-                  inits=None, record_objective=False, snapshots=(), rank_eps=0.0):
-    """Alg.2 with MU as the NMF: returns cores and per-stage details.
+                  inits=None, record_objective=False, snapshots=(), rank_eps=0.0,
+                  nmf="mu", delta=0.9999):
+    """Alg.2 with MU (``nmf="mu"``) or Alg.3 (``nmf="bcd"``, fixed ``iters`` per stage,
+    extrapolation cap ``delta``) as the NMF: returns cores and per-stage details.
 
     ``A`` is the d-way tensor (converted to float64, C order).  ``ranks`` has d+1
     entries with r_0 = r_d = 1.  With ``rank_eps`` = 0 they are the TT ranks (clamped as
@@ -225,7 +349,10 @@ def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
             W0, H0 = inits[l]
         else:
             W0, H0 = init_factors(seed, l, m, rl, k)
-        res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots)
+        if nmf == "bcd":
+            res = bcd_nmf(X, W0, H0, iters, delta, snapshots)
+        else:
+            res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots)
         res.update({"X": X, "W0": W0, "H0": H0, "m": m, "k": k, "r": rl})
         stages.append(res)
         cores.append(res["W"].reshape(r[l - 1], dims[l - 1], rl))

@@ -360,3 +360,134 @@ def test_stop_rule_on_tolerance():
     assert holds(t)
     assert not any(holds(s) for s in range(10, t, 10))
     np.testing.assert_array_equal(res["W"], O.mu_nmf(X, W0, H0, t)["W"])
+
+
+# ------------------------------------------------------------------ BCD NMF (Alg.3)
+def _f(X, W, H):
+    R = X - W @ H
+    return 0.5 * float(np.sum(R * R))
+
+
+def test_bcd_rank1_W_step_is_the_nnls_closed_form():
+    # r = 1: the Frobenius norm of h h^T is |h|^2, the exact Lipschitz constant, and the
+    # block problem separates by rows, so one step solves it: w_i = max(0, <x_i, h>/|h|^2)
+    # whatever the starting point
+    rng = _rng(40)
+    X = rng.random((7, 9)) - 0.3
+    h = rng.random((1, 9))
+    Wm = rng.random((7, 1)) * 5.0 - 2.0
+    W, L = O.bcd_step_W(X @ h.T, h @ h.T, Wm)
+    hh = sum(h[0, j] * h[0, j] for j in range(9))
+    for i in range(7):
+        xh = sum(X[i, j] * h[0, j] for j in range(9))
+        assert W[i, 0] == pytest.approx(max(0.0, xh / hh), rel=1e-12, abs=1e-14)
+    assert L == pytest.approx(hh, rel=1e-14)
+
+
+def _fd_grad(fun, M, h=1e-3):
+    G = np.zeros_like(M)
+    for idx in np.ndindex(*M.shape):
+        P = M.copy(); P[idx] += h
+        Q = M.copy(); Q[idx] -= h
+        G[idx] = (fun(P) - fun(Q)) / (2.0 * h)  # exact for a quadratic up to rounding
+    return G
+
+
+def test_bcd_block_steps_are_projected_gradient_steps():
+    rng = _rng(41)
+    m, r, k = 6, 3, 8
+    X = rng.random((m, k))
+    W = rng.random((m, r))
+    H = rng.random((r, k))
+    Wm = W + 0.4 * (rng.random((m, r)) - 0.5)  # an extrapolated point, some entries < 0
+    Hm = H + 0.4 * (rng.random((r, k)) - 0.5)
+    Wn, LW = O.bcd_step_W(X @ H.T, H @ H.T, Wm)
+    GW = _fd_grad(lambda A: _f(X, A, H), Wm)
+    lam = np.linalg.eigvalsh(H @ H.T).max()
+    assert lam * (1 - 1e-12) <= LW <= math.sqrt(r) * lam * (1 + 1e-12)
+    assert np.allclose(Wn, np.maximum(0.0, Wm - GW / LW), rtol=1e-8, atol=1e-10)
+    Hn, LH = O.bcd_step_H(W.T @ X, W.T @ W, Hm)
+    GH = _fd_grad(lambda B: _f(X, W, B), Hm)
+    lam = np.linalg.eigvalsh(W.T @ W).max()
+    assert lam * (1 - 1e-12) <= LH <= math.sqrt(r) * lam * (1 + 1e-12)
+    assert np.allclose(Hn, np.maximum(0.0, Hm - GH / LH), rtol=1e-8, atol=1e-10)
+    # each block step from the current point does not increase the objective
+    assert _f(X, O.bcd_step_W(X @ H.T, H @ H.T, W)[0], H) <= _f(X, W, H)
+    assert _f(X, W, O.bcd_step_H(W.T @ X, W.T @ W, H)[0]) <= _f(X, W, H)
+
+
+def test_bcd_init_is_scaled_to_root_norm_of_X():
+    rng = _rng(42)
+    X = rng.random((20, 30)) * 3.0
+    W0, H0 = rng.random((20, 4)), rng.random((4, 30))
+    res = O.bcd_nmf(X, W0, H0, 0)
+    nx = math.sqrt(float(np.sum(X * X)))
+    assert math.sqrt(float(np.sum(res["W"] ** 2))) == pytest.approx(math.sqrt(nx), rel=1e-12)
+    assert math.sqrt(float(np.sum(res["H"] ** 2))) == pytest.approx(math.sqrt(nx), rel=1e-12)
+    # directions are those of the random factors
+    assert np.allclose(res["W"] / W0, (res["W"] / W0)[0, 0], rtol=1e-12)
+
+
+def test_bcd_without_extrapolation_is_monotone_and_never_corrects():
+    rng = _rng(43)
+    X = rng.random((20, 30))
+    res = O.bcd_nmf(X, rng.random((20, 3)), rng.random((3, 30)), 100, delta=0.0)
+    assert res["corrections"] == 0
+    f = res["objective"]
+    assert f[0] < 0.5 * float(np.sum(X * X))
+    assert np.all(np.diff(f) < 0.0)
+
+
+def test_bcd_extrapolation_sequence():
+    # while every pair is kept, t follows the accelerated-gradient sequence: t_1 is the
+    # golden ratio, t_k >= (k + 2) / 2, and the weights w = (t_{k-1} - 1) / t_k grow from 0
+    # towards 1
+    rng = _rng(44)
+    W, H = rng.random((30, 3)), rng.random((3, 40))
+    X = W @ H
+    res = O.bcd_nmf(X, rng.random((30, 3)), rng.random((3, 40)), 30)
+    n = res["kept"].index(False) if False in res["kept"] else len(res["kept"])
+    assert n >= 10
+    t, w = res["t"][:n], res["w"][:n]
+    assert t[0] == pytest.approx((1 + math.sqrt(5)) / 2, rel=1e-15)
+    assert all(t[k] >= (k + 3) / 2 for k in range(len(t)))
+    assert w[0] == 0.0 and np.all(np.diff(w) > 0) and w[-1] < 1.0
+
+
+def test_bcd_correction_returns_to_the_last_kept_pair():
+    A = S.workload("tt16x3_r4").tensor().astype(np.float64)
+    X = A.reshape(16, 256)
+    W0, H0 = O.init_factors(0, 1, 16, 4, 256)
+    full = O.bcd_nmf(X, W0, H0, 200)
+    c = full["kept"].index(False) + 1  # first dropped iteration (1-based)
+    res = O.bcd_nmf(X, W0, H0, c + 1, snapshots=(c - 1, c, c + 1))
+    Wb, Hb = res["snaps"][c - 1]
+    Wc, Hc = res["snaps"][c]
+    assert np.array_equal(Wb, Wc) and np.array_equal(Hb, Hc)
+    assert res["objective"][c - 1] >= _f(X, Wb, Hb)  # the dropped candidate was no better
+    # the next iteration is a plain (unextrapolated) step from the kept pair
+    Wn, _ = O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wb)
+    Hn, _ = O.bcd_step_H(Wn.T @ X, Wn.T @ Wn, Hb)
+    assert res["objective"][c] == pytest.approx(_f(X, Wn, Hn), rel=1e-12)
+    if res["kept"][c]:
+        assert np.allclose(res["snaps"][c + 1][0], Wn, rtol=1e-12, atol=0)
+
+
+def test_bcd_recovers_an_exact_nonnegative_factorisation():
+    rng = _rng(45)
+    W, H = rng.random((30, 3)), rng.random((3, 40))
+    X = W @ H
+    res = O.bcd_nmf(X, rng.random((30, 3)), rng.random((3, 40)), 800)
+    err = math.sqrt(2.0 * _f(X, res["W"], res["H"])) / math.sqrt(float(np.sum(X * X)))
+    assert err < 1e-4
+
+
+def test_bcd_sweep_reaches_lower_error_than_mu():
+    # the comparison of the paper's 500 GB experiment (Sec. V, Fig. 8c): at the same ranks
+    # BCD reaches a lower reconstruction error than MU
+    A = S.workload("tt16x3_r4").tensor()
+    e = {}
+    for nmf in ("mu", "bcd"):
+        res = O.ntt_decompose(A, (1, 4, 4, 1), 200, nmf=nmf)
+        e[nmf] = O.rel_error(A, O.tt_reconstruct(res["cores"]))
+    assert e["bcd"] < 0.5 * e["mu"]
