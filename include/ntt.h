@@ -58,6 +58,15 @@ typedef enum {
                              iterations of each stage FP32; norms FP64 */
 } ntt_precision;
 
+typedef enum {
+  NTT_NMF_MU = 0, /* multiplicative updates (H first, then W) */
+  NTT_NMF_BCD = 1 /* Alg.3: projected-gradient block steps, W then H, from extrapolated
+                     points; an iteration whose pair does not lower the objective
+                     1/2 ||X_l - W H||^2 is dropped and the next one starts from the kept
+                     pair without extrapolation.  Step sizes 1/||H H^T||_F, 1/||W^T W||_F;
+                     factors first scaled to ||W||_F = ||H||_F = sqrt(||X_l||_F) */
+} ntt_nmf;
+
 /* ntt_config.flags */
 #define NTT_STRICT_RANKS 1u     /* infeasible rank -> NTT_ERR_RANK_INFEASIBLE (else clamp) */
 #define NTT_VALIDATE_INPUT 2u   /* check A >= 0 and finite before the sweep */
@@ -88,6 +97,14 @@ typedef struct {
                            ranks come back in ntt_report.eff_ranks and each core is written
                            compactly at the chosen ranks into its buffer (sized by the
                            caps).  ntt_decompose only (batched and server plans: 0). */
+  int32_t nmf;          /* ntt_nmf (0: MU).  NTT_NMF_BCD runs exactly max_iters iterations
+                           per stage (tol must be 0), in FP32 (precision NTT_PREC_FP32),
+                           ntt_decompose only; it ignores eps and NTT_PROFILE, and with
+                           NTT_RECORD_OBJECTIVE stores the objective of every iteration's
+                           candidate pair (kept or dropped, FP64 residual).  Its workspace
+                           adds two r_l x (n_{l+1}..n_d) buffers per stage. */
+  double bcd_delta;     /* BCD: cap of the extrapolation weights, in [0, 1) (0.9999 is
+                           usual; 0 turns extrapolation off) */
 } ntt_config;
 
 typedef struct {
@@ -103,6 +120,7 @@ typedef struct {
   double total_ms;
   double total_gflop;
   double compression_ratio;            /* Eq.(4) at eff_ranks */
+  int32_t corrections[NTT_MAX_DIMS];   /* BCD: dropped iterations per stage (MU: 0) */
 } ntt_report;
 
 typedef struct ntt_plan_s* ntt_plan_t;

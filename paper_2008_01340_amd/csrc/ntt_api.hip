@@ -193,6 +193,9 @@ void stage_shape(const ntt_config& cfg, int64_t m, int64_t k, int r, Stage& s, S
 
 // Column chunks of the generic X H^T partials: enough for parallelism, while their
 // G (m r + r r) floats stay within ~1/4 of the X bytes.
+// floats between the column chunks' partials of the BCD products
+size_t bcd_part_stride(int64_t m, int r) { return align_up((size_t)m * r + (size_t)r * r, 64); }
+
 void generic_chunks(const Stage& s, int* G, int64_t* chunk) {
   const double Ed = (double)s.m * s.r + (double)s.r * s.r;
   const int64_t gcap_gen = std::max<int64_t>(1, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed));
@@ -223,6 +226,9 @@ struct ntt_plan_s {
   size_t off_gpart = 0;  // W-update over row blocks: per-block Gram parts
   // rank rule (rank_eps > 0): Gram partials, the Gram, eigenvalues, eigensolver workspace
   size_t off_grp = 0, off_gram = 0, off_eig = 0, off_eigws = 0, eigws_size = 0;
+  // BCD (Alg.3): the two other H buffers, W before and candidate, X H^T and H H^T of the
+  // kept H, W_n^T W_n, the state block
+  size_t off_bh[2] = {0, 0}, off_bwp = 0, off_bwn = 0, off_bxh = 0, off_bhh = 0, off_bgw = 0, off_bst = 0;
   rocblas_handle rb = nullptr;  // created on first use by the rank rule
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
@@ -294,6 +300,14 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   if (!(cfg->rank_eps >= 0.0) || !std::isfinite(cfg->rank_eps))
     return fail(NTT_ERR_INVALID_ARG, "rank_eps must be finite and >= 0");
   const bool eps_mode = cfg->rank_eps > 0.0;
+  if (cfg->nmf != NTT_NMF_MU && cfg->nmf != NTT_NMF_BCD) return fail(NTT_ERR_INVALID_ARG, "unknown nmf");
+  const bool bcd = cfg->nmf == NTT_NMF_BCD;
+  if (bcd) {
+    if (cfg->precision != NTT_PREC_FP32) return fail(NTT_ERR_INVALID_ARG, "BCD runs in FP32 only");
+    if (cfg->tol != 0.0) return fail(NTT_ERR_INVALID_ARG, "BCD runs a fixed iteration count (tol = 0)");
+    if (!(cfg->bcd_delta >= 0.0 && cfg->bcd_delta < 1.0))
+      return fail(NTT_ERR_INVALID_ARG, "bcd_delta must be in [0, 1)");
+  }
   int64_t total = 1;
   for (int i = 0; i < d; ++i) {
     if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
@@ -341,6 +355,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   int64_t m_max = 1;
   size_t grp_max = 0, gram_max = 0;
   int64_t n_max = 0;
+  size_t bh_size = 0, bm_size = 0;  // BCD: one H buffer, one m x r factor (elements)
   // one stage shape: its classes (kept in s, t) and its share of the workspace maxima
   auto plan_stage = [&](int l, int64_t m, int64_t k, int r, Stage& s, Stage& t_out) {
     stage_shape(*cfg, m, k, r, s, t_out);
@@ -375,6 +390,16 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     }
     if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
     if (s.pro_ok) wb_size = std::max(wb_size, (size_t)s.m * (size_t)s.r * sizeof(float));
+    if (bcd) {
+      int G = 1;
+      int64_t chunk = 64;
+      bcd_chunks(s.m, s.k, s.r, &G, &chunk);
+      part_floats = std::max(part_floats, (size_t)G * bcd_part_stride(s.m, s.r));
+      gres = std::max<int>(gres, G * (int)((s.m + 63) / 64));
+      gfin = std::max(gfin, G);
+      bh_size = std::max(bh_size, (size_t)s.r * (size_t)s.k);
+      bm_size = std::max(bm_size, (size_t)s.m * (size_t)s.r);
+    }
     if (eps_mode) {
       int ns = 1;
       size_t pd = 0;
@@ -436,6 +461,16 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     p->eigws_size += 4 * gram_max * sizeof(double);
     p->off_eigws = off; off = align_up(off + p->eigws_size, 256);
   }
+  if (bcd) {
+    p->off_bh[0] = off; off = align_up(off + bh_size * sizeof(float), 256);
+    p->off_bh[1] = off; off = align_up(off + bh_size * sizeof(float), 256);
+    p->off_bwp = off; off = align_up(off + bm_size * sizeof(float), 256);
+    p->off_bwn = off; off = align_up(off + bm_size * sizeof(float), 256);
+    p->off_bxh = off; off = align_up(off + bm_size * sizeof(double), 256);
+    p->off_bhh = off; off = align_up(off + 32 * 32 * sizeof(double), 256);
+    p->off_bgw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
+    p->off_bst = off; off = align_up(off + sizeof(BcdState), 256);
+  }
   p->total = off;
   *out = p;
   return NTT_OK;
@@ -481,6 +516,7 @@ struct Ctx {
   double* gram() const { return reinterpret_cast<double*>(ws + p->off_gram); }
   double* eig() const { return reinterpret_cast<double*>(ws + p->off_eig); }
   void* eigws() const { return ws + p->off_eigws; }
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
 PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const float* W, float eps) {
@@ -548,6 +584,8 @@ struct NttJob {
   bool pro = false, pro_done = false;
   double nx = 0.0;
   std::vector<double> fhist;
+  bool bcd = false;  // the stage runs Alg.3 (BCD) instead of MU
+  BcdArgs ba{};
 
   const Stage& st() const { return p->st[l - 1]; }
   const Stage& es() const { return trans ? p->tst[l - 1] : p->st[l - 1]; }  // as iterated
@@ -568,7 +606,7 @@ struct NttJob {
       for (int i = 0; i < plan->d - 1; ++i) initH[i] = iH[i];
     trace = trace_;
     record = (plan->cfg.flags & NTT_RECORD_OBJECTIVE) && trace_;
-    profile = (plan->cfg.flags & NTT_PROFILE) && want_report;
+    profile = (plan->cfg.flags & NTT_PROFILE) && want_report && plan->cfg.nmf == NTT_NMF_MU;
     want_final = record || want_report || plan->cfg.tol > 0.0;
     l = 1;
     t = 0;
@@ -679,10 +717,11 @@ struct NttJob {
     else HIP_TRY(launch_init_uniform(W, mr, cfg.seed, 2ull * l, q));
     if (initH[l - 1]) HIP_TRY(launch_copy(H, initH[l - 1], rk, q));
     else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, q));
-    trans = s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    bcd = cfg.nmf == NTT_NMF_BCD;
+    trans = !bcd && s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     const Stage& e = es();
-    one_wg = !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
-    pro = s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    one_wg = !bcd && !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
+    pro = !bcd && s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     pro_done = false;
     const float eps = (float)cfg.eps;
     if (trans) {
@@ -697,7 +736,7 @@ struct NttJob {
       pa = pass_args(c, s, X, H, W, eps);
     }
     pa_bf = pa;
-    bf_iters = e.bf16 ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    bf_iters = (e.bf16 && !bcd) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
     if (bf_iters > 0) {
       HIP_TRY(launch_cast_bf16(c.xb(), pa.X, s.m * s.k, q));
       pa_bf.Xb = c.xb();
@@ -719,6 +758,32 @@ struct NttJob {
     t = 0;
     final_known = false;
     fhist.clear();
+    if (bcd) {
+      ba = BcdArgs{};
+      ba.X = X;
+      ba.Hb[0] = H;
+      ba.Hb[1] = c.at<float>(p->off_bh[0]);
+      ba.Hb[2] = c.at<float>(p->off_bh[1]);
+      ba.W = W;
+      ba.Wp = c.at<float>(p->off_bwp);
+      ba.Wn = c.at<float>(p->off_bwn);
+      ba.XHc = c.at<double>(p->off_bxh);
+      ba.HHc = c.at<double>(p->off_bhh);
+      ba.GWn = c.at<float>(p->off_bgw);
+      ba.st = c.at<BcdState>(p->off_bst);
+      ba.part = c.part();
+      ba.part_stride = (int64_t)bcd_part_stride(s.m, s.r);
+      bcd_chunks(s.m, s.k, s.r, &ba.G, &ba.chunk);
+      ba.red = c.red();
+      ba.rpart = c.rpart();
+      ba.scal = c.scal(l);
+      ba.trace = nullptr;
+      ba.m = (int)s.m;
+      ba.r = s.r;
+      ba.k = s.k;
+      ba.delta = cfg.bcd_delta;
+      HIP_TRY(launch_bcd_prepare(ba, q));
+    }
     if (cfg.tol > 0.0) {
       HIP_TRY(residual_now(nullptr));
       double h2[2];
@@ -754,7 +819,7 @@ struct NttJob {
 
   hipError_t graph_for(int n, bool bf, int it0, hipGraphExec_t* out) {
     const PassArgs& pg = bf ? pa_bf : pa;
-    const int variant = pro ? (it0 == 0 ? 1 : 2) : 0;
+    const int variant = bcd ? 3 : (pro ? (it0 == 0 ? 1 : 2) : 0);
     const void* wkey = variant == 2 ? (const void*)wbuf(it0 - 1) : (const void*)pg.W;
     for (auto& g : p->graphs)
       if (g.stage == l && g.iters == n && g.bf == bf && g.variant == variant && g.X == pg.X &&
@@ -775,6 +840,10 @@ struct NttJob {
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int i = 0; i < n && le == hipSuccess; ++i) {
+      if (bcd) {
+        le = launch_bcd_iter(ba, cap_stream);
+        continue;
+      }
       if (pro) {
         le = pro_iter(cap_stream, it0 + i, bf);
         continue;
@@ -810,6 +879,7 @@ struct NttJob {
   // a3 + a4: up to `budget` MU iterations of the current stage (a stopping check of a5
   // may end the stage early); *stage_done is set when no iterations remain.
   ntt_status iterate(int budget, bool* stage_done) {
+    if (bcd) return iterate_bcd(budget, stage_done);
     if (trans) return iterate_transposed(budget, stage_done);
     if (pro) return iterate_prologue(budget, stage_done);
     const ntt_config& cfg = p->cfg;
@@ -883,6 +953,38 @@ struct NttJob {
     }
     *stage_done = stop || t >= cfg.max_iters;
     if (stop) iters[l - 1] = t;
+    return NTT_OK;
+  }
+
+  // Alg.3: up to `budget` of the stage's T iterations (fixed count).  With a trace, the
+  // objective of candidate j (1-based) is stored when iteration j + 1 (or the end of the
+  // stage) decides on it, at trace slot j - 1.
+  ntt_status iterate_bcd(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    hipStream_t q = c.s;
+    const int T = cfg.max_iters;
+    while (budget > 0 && t < T) {
+      const int block = std::min(budget, T - t);
+      int n_done = 0;
+      if (!record) {
+        while (block - n_done >= kGraphIters) {
+          hipGraphExec_t ex = nullptr;
+          HIP_TRY(graph_for(kGraphIters, false, t + n_done, &ex));
+          HIP_TRY(hipGraphLaunch(ex, q));
+          n_done += kGraphIters;
+        }
+      }
+      for (; n_done < block; ++n_done) {
+        BcdArgs b = ba;
+        const int it = t + n_done + 1;
+        b.trace = (record && it >= 2) ? trace + trace_off + (it - 2) : nullptr;
+        HIP_TRY(launch_bcd_iter(b, q));
+      }
+      t += block;
+      budget -= block;
+      final_known = false;
+    }
+    *stage_done = t >= T;
     return NTT_OK;
   }
 
@@ -969,6 +1071,12 @@ struct NttJob {
   ntt_status finish_stage() {
     const ntt_config& cfg = p->cfg;
     if (iters[l - 1] == 0) iters[l - 1] = t;
+    if (bcd) {  // decision on the last candidate; the kept H into the stage's buffer
+      BcdArgs b = ba;
+      b.trace = (record && t >= 1) ? trace + trace_off + (t - 1) : nullptr;
+      HIP_TRY(launch_bcd_finish(b, c.s));
+      bcd = false;
+    }
     if (want_final && !final_known)
       HIP_TRY(residual_now((record && t >= 1) ? trace + trace_off + (t - 1) : nullptr));
     if (trans) {  // W = H'^T, H = W'^T
@@ -1008,6 +1116,7 @@ struct NttJob {
       const Stage& s = p->st[ll - 1];
       const double* v = sc + (size_t)SCAL_COUNT * (ll - 1);
       rep->iters[ll - 1] = iters[ll - 1];
+      if (p->cfg.nmf == NTT_NMF_BCD) rep->corrections[ll - 1] = (int32_t)v[SCAL_BCD_CORR];
       rep->norm_x[ll - 1] = std::sqrt(v[SCAL_NX2]);
       rep->objective[ll - 1] = v[SCAL_OBJ];
       rep->stage_rel_err[ll - 1] =
@@ -1043,7 +1152,7 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
     for (auto& e : p->stage_ev) HIP_TRY(hipEventCreate(&e));
     p->events_ready = true;
   }
-  const bool profile = (cfg.flags & NTT_PROFILE) && report;
+  const bool profile = (cfg.flags & NTT_PROFILE) && report && cfg.nmf == NTT_NMF_MU;
   if (profile && (int64_t)p->prof_events.size() < 2 * (int64_t)cfg.max_iters) {
     while (p->prof_events.size() < 2 * (size_t)cfg.max_iters) {
       hipEvent_t e;
@@ -1200,6 +1309,10 @@ extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_
     if (cfgs[i].flags & (NTT_RECORD_OBJECTIVE | NTT_PROFILE | NTT_VALIDATE_INPUT)) {
       delete b;
       return fail(NTT_ERR_INVALID_ARG, "batched mode takes no RECORD/PROFILE/VALIDATE flags");
+    }
+    if (cfgs[i].nmf != NTT_NMF_MU) {
+      delete b;
+      return fail(NTT_ERR_INVALID_ARG, "batched mode runs MU (nmf = 0)");
     }
     if (cfgs[i].rank_eps != 0.0) {
       delete b;

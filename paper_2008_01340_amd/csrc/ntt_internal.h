@@ -11,7 +11,8 @@
 namespace ntt {
 
 // FP64 scalars kept on the device per stage
-enum { SCAL_NX2 = 0, SCAL_OBJ = 1, SCAL_MONITOR = 2, SCAL_OBJ0 = 3, SCAL_COUNT = 8 };
+enum { SCAL_NX2 = 0, SCAL_OBJ = 1, SCAL_MONITOR = 2, SCAL_OBJ0 = 3, SCAL_BCD_W2 = 4,
+       SCAL_BCD_H2 = 5, SCAL_BCD_CORR = 6, SCAL_BCD_OBJ = 7, SCAL_COUNT = 8 };
 
 // One MU pass over the columns of an m x k unfolding.
 struct PassArgs {
@@ -84,6 +85,53 @@ struct TTArgs {
   float* out;      // MODE 0 output
   double* part;    // MODE 1 per-block (err, ref) pairs, then the two totals
 };
+
+// BCD NMF (Alg.3): state of one stage, in device memory, read and written by the kernels
+// only (so that iterations replay from a captured graph).  Hb[cur] holds the kept H,
+// Hb[prev] the kept H before it, Hb[nxt] receives the candidate; the three indices are
+// always a permutation of 0, 1, 2.
+struct BcdState {
+  double t, obj;   // extrapolation sequence and the objective of the kept pair
+  double wW, wH;   // extrapolation weights of the next iteration
+  double gH, gW;   // ||H H^T||_F and ||W^T W||_F of the kept pair
+  double gWn;      // ||W_n^T W_n||_F of the candidate W (the H step size 1/gWn)
+  double pad0;
+  int cur, prev, nxt, first, corrections, pad1[3];
+};
+
+struct BcdArgs {
+  const float* X;    // m x k, row stride k
+  float* Hb[3];      // three r x k buffers; Hb[0] is the stage's H (the result goes there)
+  float* W;          // m x r, the kept W (the stage's core buffer)
+  float* Wp;         // m x r, the kept W before it
+  float* Wn;         // m x r, the candidate W
+  double* XHc;       // m x r, X H^T of the kept H
+  double* HHc;       // r x r, H H^T of the kept H
+  float* GWn;        // 32 x 32 zero padded, W_n^T W_n (FP32, for the H step)
+  BcdState* st;
+  float* part;       // X H^T, H H^T partials per column chunk ([m][r] then [r][r])
+  int64_t part_stride;
+  int G;             // column chunks
+  int64_t chunk;     // columns per chunk (multiple of 64)
+  double* red;       // the reduced partials (m r + r r), FP64
+  double* rpart;     // residual partials, G x ceil(m / 64)
+  double* scal;      // the stage's SCAL_* scalars
+  double* trace;     // where the step stores the candidate's objective (NULL: nowhere)
+  int m, r;
+  int64_t k;
+  double delta;      // extrapolation cap
+};
+// Column chunks of the BCD products for an m x k unfolding at rank r (G <= 1024).
+void bcd_chunks(int64_t m, int64_t k, int r, int* G, int64_t* chunk);
+// Stage set-up: scale W and Hb[0] to Frobenius norm sqrt(||X||_F) (scal[SCAL_NX2] must
+// hold ||X||^2), reset the state and form X H^T, H H^T of the initial H.
+hipError_t launch_bcd_prepare(const BcdArgs& b, hipStream_t s);
+// One iteration: decision on the previous candidate and the W step, the H step, the
+// products of the new candidate and their reduction.
+hipError_t launch_bcd_iter(const BcdArgs& b, hipStream_t s);
+// End of the stage: decision on the last candidate; the kept H goes to Hb[0] and the
+// number of dropped iterations to scal[SCAL_BCD_CORR].
+hipError_t launch_bcd_finish(const BcdArgs& b, hipStream_t s);
 
 hipError_t launch_init_uniform(float* out, int64_t n, uint64_t seed, uint64_t tag, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);

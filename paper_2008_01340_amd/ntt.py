@@ -28,6 +28,10 @@ NTT_ERR_DEVICE = 6
 NTT_PREC_FP32 = 0
 NTT_PREC_BF16_MIXED = 1
 
+NTT_NMF_MU = 0
+NTT_NMF_BCD = 1
+_NMF = {"mu": NTT_NMF_MU, "bcd": NTT_NMF_BCD}
+
 NTT_STRICT_RANKS = 1
 NTT_VALIDATE_INPUT = 2
 NTT_RECORD_OBJECTIVE = 4
@@ -59,6 +63,8 @@ class NttConfig(C.Structure):
         ("fp32_tail_iters", C.c_int32),
         ("flags", C.c_uint32),
         ("rank_eps", C.c_double),
+        ("nmf", C.c_int32),
+        ("bcd_delta", C.c_double),
     ]
 
 
@@ -75,6 +81,7 @@ class NttReport(C.Structure):
         ("total_ms", C.c_double),
         ("total_gflop", C.c_double),
         ("compression_ratio", C.c_double),
+        ("corrections", C.c_int32 * NTT_MAX_DIMS),
     ]
 
     def to_dict(self, d: int) -> dict:
@@ -91,6 +98,7 @@ class NttReport(C.Structure):
             "total_ms": self.total_ms,
             "total_gflop": self.total_gflop,
             "compression_ratio": self.compression_ratio,
+            "corrections": list(self.corrections[:s]),
         }
 
 
@@ -206,7 +214,10 @@ class Plan:
     """Owns an ntt_plan_t; keeps the host arrays the config points to alive."""
 
     def __init__(self, dims, ranks, max_iters, tol=0.0, check_every=10, eps=1e-12, seed=0,
-                 precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, rank_eps=0.0):
+                 precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, rank_eps=0.0,
+                 nmf="mu", delta=0.9999):
+        """``nmf``: "mu" (multiplicative updates) or "bcd" (Alg.3, extrapolation cap
+        ``delta``)."""
         lib = load()
         self.dims = [int(n) for n in dims]
         self.ranks = [int(r) for r in ranks]
@@ -216,7 +227,8 @@ class Plan:
         self.cfg = NttConfig(self.d, C.cast(self._dims, C.POINTER(C.c_int64)),
                              C.cast(self._ranks, C.POINTER(C.c_int64)), int(max_iters), float(tol),
                              int(check_every), float(eps), int(seed) & ((1 << 64) - 1),
-                             int(precision), int(fp32_tail_iters), int(flags), float(rank_eps))
+                             int(precision), int(fp32_tail_iters), int(flags), float(rank_eps),
+                             _NMF[nmf], float(delta))
         self.max_iters = int(max_iters)
         self.rank_eps = float(rank_eps)
         self.handle = C.c_void_p()
@@ -312,8 +324,10 @@ def _stream_handle(torch, stream):
 def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10,
               precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, init_W=None, init_H=None,
               record_objective=False, plan=None, workspace=None, cores=None, stream=None,
-              want_report=True, rank_eps=0.0):
+              want_report=True, rank_eps=0.0, nmf="mu", delta=0.9999):
     """Decompose a float32 CUDA tensor; allocates cores/workspace with torch if not given.
+
+    ``nmf="bcd"`` runs Alg.3 (BCD with extrapolation cap ``delta``) instead of MU.
 
     With rank_eps > 0 the ranks are chosen by the rule of Alg.2 (``ranks`` are caps);
     the returned cores are views of the (cap-sized) buffers at the chosen ranks."""
@@ -325,7 +339,7 @@ def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10
     if plan is None:
         plan = Plan(dims, ranks, max_iters, tol=tol, check_every=check_every, eps=eps, seed=seed,
                     precision=precision, fp32_tail_iters=fp32_tail_iters, flags=flags,
-                    rank_eps=rank_eps)
+                    rank_eps=rank_eps, nmf=nmf, delta=delta)
     if plan.rank_eps > 0.0:
         want_report = True  # the chosen ranks come back in the report
     nbytes, eff, _ = plan.workspace()

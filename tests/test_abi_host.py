@@ -84,6 +84,11 @@ def test_plan_strict_ranks_errors():
     ({"rank_eps": -0.1}, (4, 5), (1, 2, 1)),
     ({"rank_eps": float("inf")}, (4, 5), (1, 2, 1)),
     ({"rank_eps": 0.1}, (3000, 3000), (1, 8, 1)),  # rank rule: shorter side above 2048
+    ({"nmf": "bcd", "precision": 1}, (4, 5), (1, 2, 1)),  # BCD runs in FP32 only
+    ({"nmf": "bcd", "tol": 1e-3}, (4, 5), (1, 2, 1)),     # BCD: fixed iteration count
+    ({"nmf": "bcd", "delta": 1.0}, (4, 5), (1, 2, 1)),
+    ({"nmf": "bcd", "delta": -0.5}, (4, 5), (1, 2, 1)),
+    ({"nmf": "bcd", "delta": float("nan")}, (4, 5), (1, 2, 1)),
 ])
 def test_plan_rejects_invalid_configs(kw, dims, ranks):
     args = {"max_iters": 10}
@@ -161,3 +166,22 @@ def test_batch_plan_validation_and_workspace():
         ntt.Batch([((4, 5, 6), (1, 2, 3, 2), 1)], 10)  # r_d != 1
     lib = ntt.load()
     assert lib.ntt_batch_plan(0, None, None) == ntt.NTT_ERR_INVALID_ARG
+
+
+def test_unknown_nmf_and_batched_bcd_are_rejected(lib):
+    dims, ranks = ntt._i64([4, 5]), ntt._i64([1, 2, 1])
+    cfg = ntt.NttConfig(2, ctypes.cast(dims, ctypes.POINTER(ctypes.c_int64)),
+                        ctypes.cast(ranks, ctypes.POINTER(ctypes.c_int64)), 5, 0.0, 10, 1e-12, 0,
+                        0, 0, 0, 0.0, 2, 0.9999)
+    h = ctypes.c_void_p()
+    assert lib.ntt_plan(ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
+    assert "nmf" in lib.ntt_last_error().decode()
+    cfg.nmf = ntt.NTT_NMF_BCD
+    assert lib.ntt_batch_plan(1, ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
+
+
+def test_bcd_workspace_adds_two_h_buffers():
+    dims, ranks = (32, 32, 32), (1, 8, 8, 1)
+    mu = ntt.Plan(dims, ranks, 10).workspace()[0]
+    bcd = ntt.Plan(dims, ranks, 10, nmf="bcd").workspace()[0]
+    assert bcd >= mu + 2 * 8 * 32 * 32 * 4

@@ -1,0 +1,232 @@
+"""GPU parity of the BCD NMF (Alg.3) against the CPU FP64 oracle, through the C ABI.
+
+The correction test compares two objectives; where the oracle's margin of a decision
+(|f - f_kept| / f_kept) is below what FP32 products can resolve, the two sides may
+decide differently and then follow different (equally valid) trajectories.  So:
+* per-iterate parity (candidate objectives, kept factors) is checked over iterations
+  whose oracle decisions all have margins above MARGIN, and the dropped-iteration counts
+  must agree there;
+* long runs, where decisions near ties occur, are checked on the final relative error
+  (Eq.(3)) with the bar LONG_BAR, like the BF16 mode.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2008_01340_amd import ntt  # noqa: E402
+
+DEV = "cuda:0"
+# Per-iterate bar: FP32 products (relative rounding ~ r 2^-24 per entry) propagated
+# through at most T = 40 extrapolated steps.
+TOL = 1e-4
+MARGIN = 1e-3   # decisions with a smaller relative margin are not compared
+# An objective near an exact fit is resolved only to ~(r 2^-24)^2 ||X||^2 by FP32 products
+# (as for MU): objectives are compared as |f_gpu - f_orc| <= TOL f_orc + FLOOR ||X||^2, and
+# margins are taken relative to f + FLOOR ||X||^2.
+FLOOR = 1e-12
+LONG_BAR = 1e-3  # |e_gpu - e_oracle| on the final relative error after long runs
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def margins(res):
+    """Relative margin of each iteration's decision in an oracle run."""
+    out, kept_obj = [], 0.5 * res["norm_x"] ** 2
+    fl = FLOOR * res["norm_x"] ** 2
+    for f, k in zip(res["objective"], res["kept"]):
+        out.append(abs(f - kept_obj) / (kept_obj + fl))
+        if k:
+            kept_obj = f
+    return np.array(out)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "a GPU is required for the gpu-marked tests"
+    ntt.load()
+    yield
+    torch.cuda.synchronize()
+
+
+SHAPES = [
+    # (m, k, r): ragged m and k, ranks at the three paddings (8, 16, 32)
+    (16, 256, 4), (7, 33, 3), (45, 517, 5), (100, 301, 16), (130, 77, 32), (1, 50, 1),
+    (200, 3, 3), (33, 250, 24), (300, 2000, 10), (64, 4099, 8), (520, 700, 12),
+]
+
+
+@pytest.mark.parametrize("m,k,r", SHAPES)
+def test_bcd_single_stage_per_iterate_parity(m, k, r):
+    say(f"case: BCD d=2 NMF m={m} k={k} r={r}")
+    rng = np.random.default_rng(m * 1000 + k + 7)
+    X = (rng.random((m, k)) + 0.05).astype(np.float32)
+    W0, H0 = O.init_factors(11, 1, m, r, k)
+    T = 40
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, T, snapshots=(1, 2, 5, 20, T))
+    mg = margins(ref)
+    safe = int(np.argmax(mg < MARGIN)) if np.any(mg < MARGIN) else T  # iterations 1..safe
+    res = ntt.decompose(dev(X), (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)],
+                        record_objective=True, nmf="bcd")
+    f_gpu = host(res.trace)
+    f_orc = ref["objective"]
+    fl = FLOOR * ref["norm_x"] ** 2
+    diff = np.abs(f_gpu[:safe] - f_orc[:safe])
+    d = diff / (f_orc[:safe] + fl)
+    say(f"  safe iterations {safe}/{T}, max rel objective diff {d.max() if safe else 0:.2e}, "
+        f"oracle corrections {ref['corrections']}")
+    assert safe >= 1
+    assert np.all(diff <= TOL * f_orc[:safe] + fl), d
+    for t in (1, 2, 5, 20, T):
+        if t > safe:
+            break
+        r_t = ntt.decompose(dev(X), (1, r, 1), t, init_W=[dev(W0)], init_H=[dev(H0)], nmf="bcd")
+        Wg = host(r_t.cores[0]).reshape(m, r)
+        Hg = host(r_t.cores[1]).reshape(r, k)
+        Wo, Ho = ref["snaps"][t]
+        say(f"  t={t}: W {rel(Wg, Wo):.2e} H {rel(Hg, Ho):.2e}")
+        assert rel(Wg, Wo) <= TOL, (t, rel(Wg, Wo))
+        assert rel(Hg, Ho) <= TOL, (t, rel(Hg, Ho))
+        assert Wg.min() >= 0 and Hg.min() >= 0
+        assert r_t.report["corrections"][0] == ref["kept"][:t].count(False)
+
+
+def test_bcd_without_extrapolation_descends_and_never_corrects():
+    say("case: BCD delta=0, 64 x 3000 rank 6, T=60")
+    rng = np.random.default_rng(5)
+    X = rng.random((64, 3000)).astype(np.float32)
+    W0, H0 = O.init_factors(2, 1, 64, 6, 3000)
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, 60, delta=0.0)
+    res = ntt.decompose(dev(X), (1, 6, 1), 60, init_W=[dev(W0)], init_H=[dev(H0)],
+                        record_objective=True, nmf="bcd", delta=0.0)
+    f = host(res.trace)
+    assert res.report["corrections"][0] == 0 == ref["corrections"]
+    assert np.all(np.diff(f) < 0.0)
+    assert np.max(np.abs(f - ref["objective"]) / ref["objective"]) <= TOL
+    assert rel(host(res.cores[0]).reshape(64, 6), ref["W"]) <= TOL
+
+
+def test_bcd_graph_replay_equals_direct_launches_bitwise():
+    say("case: BCD 16^3 sweep T=80 with (graphs) and without (trace) replay")
+    w = S.workload("tt16x3_r4")
+    Ad = dev(w.tensor())
+    a = ntt.decompose(Ad, w.target_ranks, 80, seed=w.seed, nmf="bcd")
+    b = ntt.decompose(Ad, w.target_ranks, 80, seed=w.seed, nmf="bcd", record_objective=True)
+    c = ntt.decompose(Ad, w.target_ranks, 80, seed=w.seed, nmf="bcd")
+    for x, y, z in zip(a.cores, b.cores, c.cores):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    assert a.report["corrections"] == b.report["corrections"]
+
+
+def test_bcd_sweep_16cubed_matches_oracle():
+    say("case: BCD sweep 16^3 ranks (4,4), T=200")
+    w = S.workload("tt16x3_r4")
+    A = w.tensor()
+    T = w.iters
+    ref = O.ntt_decompose(A, w.target_ranks, T, seed=w.seed, nmf="bcd")
+    res = ntt.decompose(dev(A), w.target_ranks, T, seed=w.seed, nmf="bcd", record_objective=True)
+    f_gpu = host(res.trace).reshape(2, T)
+    st1 = ref["stages"][0]
+    mg = margins(st1)
+    safe = int(np.argmax(mg < MARGIN)) if np.any(mg < MARGIN) else T
+    d = np.abs(f_gpu[0][:safe] - st1["objective"][:safe]) / st1["objective"][:safe]
+    say(f"  stage 1: safe {safe}/{T}, max rel objective diff {d.max():.2e}; corrections "
+        f"gpu {res.report['corrections']} oracle {[s['corrections'] for s in ref['stages']]}")
+    assert np.all(d <= TOL)
+    if safe == T:
+        assert res.report["corrections"][0] == st1["corrections"]
+        assert rel(host(res.cores[0]), ref["cores"][0]) <= TOL
+    e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+    e_gpu = ntt.rel_error(dev(A), res.cores)
+    say(f"  rel err: oracle {e_orc:.6e} gpu {e_gpu:.6e}")
+    assert abs(e_gpu - e_orc) <= LONG_BAR
+    mu = ntt.decompose(dev(A), w.target_ranks, T, seed=w.seed)
+    assert e_gpu < ntt.rel_error(dev(A), mu.cores)  # BCD below MU at equal iterations
+
+
+@pytest.mark.parametrize("dims,gen,noise,level,T", [
+    ((24, 20, 30, 16), (1, 6, 5, 4, 1), "mult", 0.05, 150),
+    ((20, 40, 40, 50), (1, 6, 5, 4, 1), "mult", 0.01, 100),
+    ((40, 30, 20, 30), (1, 16, 12, 8, 1), "absnormal", 0.01, 100),
+])
+def test_bcd_sweep_final_error_matches_oracle(dims, gen, noise, level, T):
+    say(f"case: BCD sweep dims={dims} ranks={gen} T={T}")
+    A = S.noisy_tensor(dims, gen, seed=7, noise=noise, level=level)
+    ref = O.ntt_decompose(A, gen, T, seed=3, nmf="bcd")
+    e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+    Ad = dev(A)
+    res = ntt.decompose(Ad, gen, T, seed=3, nmf="bcd")
+    e_gpu = ntt.rel_error(Ad, res.cores)
+    say(f"  rel err: oracle {e_orc:.6e} gpu {e_gpu:.6e}; corrections gpu "
+        f"{res.report['corrections']} oracle {[s['corrections'] for s in ref['stages']]}")
+    assert abs(e_gpu - e_orc) <= LONG_BAR
+    for c in res.cores:
+        assert float(c.min()) >= 0.0
+    assert res.report["iters"] == [T] * (len(dims) - 1)
+
+
+def test_bcd_zero_iterations_returns_scaled_init():
+    say("case: BCD T=0 (scaled random factors)")
+    rng = np.random.default_rng(3)
+    X = rng.random((20, 70)).astype(np.float32)
+    W0, H0 = O.init_factors(4, 1, 20, 5, 70)
+    res = ntt.decompose(dev(X), (1, 5, 1), 0, init_W=[dev(W0)], init_H=[dev(H0)], nmf="bcd")
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, 0)
+    assert rel(host(res.cores[0]).reshape(20, 5), ref["W"]) <= 1e-6
+    assert rel(host(res.cores[1]).reshape(5, 70), ref["H"]) <= 1e-6
+
+
+def test_bcd_with_rank_rule():
+    say("case: BCD with the rank rule, 24 x 20 x 30 x 16 ranks <= 8, rank_eps 0.02")
+    A = S.noisy_tensor((24, 20, 30, 16), (1, 6, 5, 4, 1), seed=7, noise="mult", level=0.01)
+    ref = O.ntt_decompose(A, (1, 8, 8, 8, 1), 60, seed=3, nmf="bcd", rank_eps=0.02)
+    res = ntt.decompose(dev(A), (1, 8, 8, 8, 1), 60, seed=3, nmf="bcd", rank_eps=0.02)
+    assert list(res.report["eff_ranks"]) == list(ref["ranks"])
+    e_orc = O.rel_error(A, O.tt_reconstruct(ref["cores"]))
+    e_gpu = ntt.rel_error(dev(A), res.cores)
+    say(f"  ranks {ref['ranks']} rel err oracle {e_orc:.6e} gpu {e_gpu:.6e}")
+    assert abs(e_gpu - e_orc) <= LONG_BAR
+
+
+def test_bcd_full_size_first_unfolding_per_iterate():
+    """The 32^5 workload's first unfolding (32 x 32^4, rank 8) as the sweep runs it: the
+    first iterations against the oracle, every entry."""
+    say("case: BCD full-size first unfolding 32 x 1048576 rank 8, T=1..4")
+    w = S.workload("tt32x5_r8")
+    A = w.tensor()
+    X = A.reshape(32, -1)
+    Xd = dev(X)
+    W0, H0 = O.init_factors(w.seed, 1, 32, 8, X.shape[1])
+    T = 4
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, T, snapshots=tuple(range(1, T + 1)))
+    assert np.all(margins(ref) > MARGIN)
+    for t in range(1, T + 1):
+        g = ntt.decompose(Xd, (1, 8, 1), t, init_W=[dev(W0)], init_H=[dev(H0)], nmf="bcd")
+        Wo, Ho = ref["snaps"][t]
+        eW = rel(host(g.cores[0]).reshape(32, 8), Wo)
+        eH = rel(host(g.cores[1]).reshape(8, -1), Ho)
+        say(f"  t={t}: W {eW:.2e} H {eH:.2e}")
+        assert eW <= TOL and eH <= TOL
