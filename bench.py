@@ -25,7 +25,7 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
-EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "batched", "serving")
+EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "bcd", "batched", "serving")
 # HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8w<8> on 512
 # workgroups, W-update prologue): rocprofv3 FETCH_SIZE (82,023.8 KiB) and WRITE_SIZE
 # (33,408.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
@@ -149,6 +149,39 @@ def rank_rule(ntt, S, torch):
                               "rel_error": ntt.rel_error(A, res.cores),
                               "stage_ms": res.report["ms"]})
         progress(f"rank rule: eps {eps}: ranks {res.ranks}, {ms:.1f} ms")
+    del A
+    return out
+
+
+def bcd(ntt, S, torch, mu_err, mu_ms):
+    """The sweep with the BCD NMF of Alg.3 (extrapolation cap 0.9999) on the 32^5 workload
+    at the same ranks and iteration count as the MU sweep: time, error, dropped iterations,
+    and the bytes each stage-1 iteration moves (two X passes: the H step and the products)."""
+    w = S.workload("tt32x5_r8")
+    A = torch.from_numpy(w.tensor()).cuda()
+    plan = ntt.Plan(w.dims, w.target_ranks, w.iters, seed=w.seed, nmf="bcd")
+    res = ntt.decompose(A, w.target_ranks, w.iters, plan=plan)
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        res = ntt.decompose(A, w.target_ranks, w.iters, plan=plan)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0) * 1e3)
+    ms = min(runs)
+    err = ntt.rel_error(A, res.cores)
+    m, k, r = 32, 32 ** 4, 8
+    it_ms = res.report["ms"][0] / w.iters
+    # per iteration: X twice, the kept H (and the kept H before it while extrapolating),
+    # the candidate H written and read back
+    bytes_it = 8.0 * m * k + 16.0 * r * k
+    out = {"workload": f"{w.name}: {w.note}; BCD (Alg.3), delta 0.9999", "ms": ms,
+           "rel_error": err, "mu_rel_error": mu_err, "mu_ms": mu_ms,
+           "corrections": res.report["corrections"], "stage_ms": res.report["ms"],
+           "stage1_ms_per_iter": it_ms,
+           "stage1_gbs": bytes_it / (it_ms * 1e-3) / 1e9, "stage1_bytes_per_iter": bytes_it}
+    progress(f"bcd: {ms:.1f} ms, rel err {err:.4e} (MU {mu_err:.4e}), corrections "
+             f"{res.report['corrections']}")
     del A
     return out
 
@@ -349,6 +382,9 @@ def main():
         torch.cuda.empty_cache()
     if "rank_rule" in extras:
         out["rank_rule"] = rank_rule(ntt, S, torch)
+        torch.cuda.empty_cache()
+    if "bcd" in extras:
+        out["bcd"] = bcd(ntt, S, torch, err, ms)
         torch.cuda.empty_cache()
     if "batched" in extras:
         out["batched"] = batched(ntt, S, torch)

@@ -70,11 +70,13 @@ __global__ void k_bcd_state_init(BcdState* st, const double* __restrict__ scal) 
 // X H^T and H H^T partials of H (Hb[0] when `init`, else the candidate Hb[nxt]), as
 // block (g, rb) covers column chunk g and rows 64 rb .. 64 rb + 63; with RESID also the
 // FP64 sum of (x - (W_n H)_ij)^2 over the tile.  Partial layout per chunk: [m][r] then
-// [r][r] (H H^T by the rb = 0 blocks).
-template <int RP, bool RESID>
+// [r][r] (H H^T by the rb = 0 blocks).  XV: X rows are read as float4 (k % 4 == 0 and a
+// 16-byte aligned X).
+template <int RP, bool RESID, bool XV>
 __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
-  __shared__ float sX[64][65];
-  __shared__ float sH[RP][65];
+  // rows of 68 floats: 16-byte aligned, so the tile is written and read as float4
+  __shared__ __attribute__((aligned(16))) float sX[64][68];
+  __shared__ __attribute__((aligned(16))) float sH[RP][68];
   __shared__ double sRes[4];
   const int tid = threadIdx.x;
   const int m = b.m, r = b.r;
@@ -82,7 +84,12 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
   const float* __restrict__ H = init ? b.Hb[0] : b.Hb[b.st->nxt];
   const int g = blockIdx.x, rb = blockIdx.y;
   const int64_t c0 = (int64_t)g * b.chunk, c1 = min(k, c0 + b.chunk);
-  const int row = tid >> 2, qd = tid & 3;
+  const int mrows = min(64, m - 64 * rb);  // rows of this block inside X
+  // threads per row: 4 (16 columns of a 64-column tile each), 8 when the block holds at
+  // most 32 rows, 16 when at most 16
+  const int tpr = mrows <= 16 ? 16 : (mrows <= 32 ? 8 : 4);
+  const int cpt = 64 / tpr;
+  const int row = tid / tpr, part = tid % tpr;
   const int gi = 64 * rb + row;
   float acc[RP];
   float w[RP];
@@ -91,54 +98,141 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
     acc[c] = 0.f;
     w[c] = RESID ? bmask(b.Wn[(int64_t)min(gi, m - 1) * r + min(c, r - 1)], gi < m && c < r) : 0.f;
   }
+  // the Gram: GT threads per pair while there are fewer pairs than threads
+  constexpr int GT = RP * RP >= 256 ? 1 : 256 / (RP * RP);
   constexpr int NG = RP * RP / 256 > 0 ? RP * RP / 256 : 1;
   float accg[NG];
 #pragma unroll
   for (int t = 0; t < NG; ++t) accg[t] = 0.f;
   double res = 0.0;
-  for (int64_t j0 = c0; j0 < c1; j0 += 64) {
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e >> 6, jj = e & 63;
-      const int xi = 64 * rb + i;
-      const int64_t gj = j0 + jj;
-      sX[i][jj] = bmask(b.X[(int64_t)min(xi, m - 1) * k + min(gj, c1 - 1)], xi < m && gj < c1);
+  // Tiles go through registers two deep: the loads of tile t + 2 are issued before
+  // tile t is computed, and each tile is stored to LDS (masked there) when its turn comes.
+  constexpr int HPT = (RP * 64 + 255) / 256;  // H tile entries per thread
+  float4 xr0[4], xr1[4];
+  float hr0[HPT], hr1[HPT];
+  auto issue = [&](float4 (&xr)[4], float (&hr)[HPT], int64_t j0) {
+    if (XV) {
+      // 16 float4 per tile row: each load instruction of a wave covers 4 rows x 256
+      // bytes; groups of 16 rows wholly beyond m are not loaded
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (16 * q < mrows) {
+          const int e = tid + 256 * q;
+          const int i = e >> 4, j4 = (e & 15) * 4;
+          const int xi = 64 * rb + i;
+          const int64_t gj = j0 + j4;
+          const bool ok = xi < m && gj < c1;
+          xr[q] = *reinterpret_cast<const float4*>(b.X + (int64_t)min(xi, m - 1) * k + (ok ? gj : c0));
+        }
+      }
     }
-    for (int e = tid; e < RP * 64; e += 256) {
-      const int c = e >> 6, jj = e & 63;
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) {
+      const int e = tid + 256 * t;
+      const int c = min(e >> 6, RP - 1), jj = e & 63;
       const int64_t gj = j0 + jj;
-      sH[c][jj] = bmask(H[(int64_t)min(c, r - 1) * k + min(gj, c1 - 1)], c < r && gj < c1);
+      hr[t] = H[(int64_t)min(c, r - 1) * k + min(gj, c1 - 1)];
     }
-    __syncthreads();
+  };
+  auto store = [&](const float4 (&xr)[4], const float (&hr)[HPT], int64_t j0) {
+    if (XV) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int i = e >> 4, j4 = (e & 15) * 4;
+        const int xi = 64 * rb + i;
+        const bool ok = 16 * q < mrows && xi < m && j0 + j4 < c1;
+        *reinterpret_cast<float4*>(&sX[i][j4]) = ok ? xr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    } else {
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int i = e >> 6, jj = e & 63;
+        const int xi = 64 * rb + i;
+        const int64_t gj = j0 + jj;
+        sX[i][jj] = bmask(b.X[(int64_t)min(xi, m - 1) * k + min(gj, c1 - 1)], xi < m && gj < c1);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) {
+      const int e = tid + 256 * t;
+      if (e < RP * 64) {
+        const int c = e >> 6, jj = e & 63;
+        sH[c][jj] = (c < r && j0 + jj < c1) ? hr[t] : 0.f;
+      }
+    }
+  };
+  auto compute = [&]() {
+    // four columns per LDS read; the columns are still taken in order
 #pragma unroll 1
-    for (int jj = qd * 16; jj < qd * 16 + 16; ++jj) {
-      const float x = sX[row][jj];
-      float wh = 0.f;
+    for (int j4 = part * cpt; j4 < part * cpt + cpt; j4 += 4) {
+      const float4 xv = *reinterpret_cast<const float4*>(&sX[row][j4]);
+      float wh0 = 0.f, wh1 = 0.f, wh2 = 0.f, wh3 = 0.f;
 #pragma unroll
       for (int c = 0; c < RP; ++c) {
-        acc[c] = fmaf(x, sH[c][jj], acc[c]);
-        if (RESID) wh = fmaf(w[c], sH[c][jj], wh);
+        const float4 hv = *reinterpret_cast<const float4*>(&sH[c][j4]);
+        float a = acc[c];
+        a = fmaf(xv.x, hv.x, a);
+        a = fmaf(xv.y, hv.y, a);
+        a = fmaf(xv.z, hv.z, a);
+        a = fmaf(xv.w, hv.w, a);
+        acc[c] = a;
+        if (RESID) {
+          wh0 = fmaf(w[c], hv.x, wh0);
+          wh1 = fmaf(w[c], hv.y, wh1);
+          wh2 = fmaf(w[c], hv.z, wh2);
+          wh3 = fmaf(w[c], hv.w, wh3);
+        }
       }
-      if (RESID) {
-        const double dl = (double)x - (double)wh;  // 0 outside the matrix
-        res += dl * dl;
+      if (RESID) {  // 0 outside the matrix
+        const double d0 = (double)xv.x - (double)wh0, d1 = (double)xv.y - (double)wh1;
+        const double d2 = (double)xv.z - (double)wh2, d3 = (double)xv.w - (double)wh3;
+        res += d0 * d0;
+        res += d1 * d1;
+        res += d2 * d2;
+        res += d3 * d3;
       }
     }
     if (rb == 0) {
+      // H H^T: pair p of the RP x RP Gram, GT threads per pair over 64 / GT columns each
 #pragma unroll
       for (int t = 0; t < NG; ++t) {
-        const int pidx = tid + 256 * t;
+        const int pidx = tid / GT + (256 / GT) * t;
         if (pidx < RP * RP) {
           const int c = pidx / RP, q = pidx % RP;
+          const int j1 = (tid % GT) * (64 / GT);
           float s = accg[t];
 #pragma unroll 4
-          for (int jj = 0; jj < 64; ++jj) s = fmaf(sH[c][jj], sH[q][jj], s);
+          for (int jj = j1; jj < j1 + 64 / GT; jj += 4) {
+            const float4 u = *reinterpret_cast<const float4*>(&sH[c][jj]);
+            const float4 v = *reinterpret_cast<const float4*>(&sH[q][jj]);
+            s = fmaf(u.x, v.x, s);
+            s = fmaf(u.y, v.y, s);
+            s = fmaf(u.z, v.z, s);
+            s = fmaf(u.w, v.w, s);
+          }
           accg[t] = s;
         }
       }
     }
+  };
+  // two tiles in flight: tile t + 2 is issued while tile t is computed
+  issue(xr0, hr0, c0);
+  if (c0 + 64 < c1) issue(xr1, hr1, c0 + 64);
+  for (int64_t j0 = c0; j0 < c1; j0 += 128) {
+    __syncthreads();
+    store(xr0, hr0, j0);
+    __syncthreads();
+    if (j0 + 128 < c1) issue(xr0, hr0, j0 + 128);
+    compute();
+    if (j0 + 64 < c1) {
+      __syncthreads();
+      store(xr1, hr1, j0 + 64);
+      __syncthreads();
+      if (j0 + 192 < c1) issue(xr1, hr1, j0 + 192);
+      compute();
+    }
   }
-  // the four column quarters of each row, added in order
+  // the column parts of each row, added in order
   __syncthreads();
   float* red = &sX[0][0];
   float* dst = b.part + (int64_t)g * b.part_stride;
@@ -146,17 +240,24 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
     __syncthreads();
     red[tid] = acc[c];
     __syncthreads();
-    if (qd == 0) {
-      const float s = ((red[tid] + red[tid + 1]) + red[tid + 2]) + red[tid + 3];
+    if (part == 0) {
+      float s = red[tid];
+      for (int p2 = 1; p2 < tpr; ++p2) s += red[tid + p2];
       if (gi < m && c < r) dst[(int64_t)gi * r + c] = s;
     }
   }
   if (rb == 0) {
 #pragma unroll
     for (int t = 0; t < NG; ++t) {
-      const int pidx = tid + 256 * t;
-      if (pidx < RP * RP && pidx / RP < r && pidx % RP < r)
-        dst[(int64_t)m * r + (pidx / RP) * r + (pidx % RP)] = accg[t];
+      __syncthreads();
+      red[tid] = accg[t];
+      __syncthreads();
+      const int pidx = tid / GT + (256 / GT) * t;
+      if (tid % GT == 0 && pidx < RP * RP && pidx / RP < r && pidx % RP < r) {
+        float s = red[tid];
+        for (int p2 = 1; p2 < GT; ++p2) s += red[tid + p2];
+        dst[(int64_t)m * r + (pidx / RP) * r + (pidx % RP)] = s;
+      }
     }
   }
   if (RESID) {
@@ -170,131 +271,152 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
 // The decision on the previous candidate (unless this is the stage's first step), then,
 // unless `final_step`, the W step and G = W_n^T W_n.  One workgroup; thread tid owns rows
 // tid, tid + 256, ... in every phase, so it only re-reads global data it wrote itself.
+// The kernel is latency-bound: every load it needs for the decision and for its first
+// 256 rows is issued at once, the sums go through one barrier, and every thread then
+// takes the (identical) decision itself.
 template <int RP>
 __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
   __shared__ float sWn[256][RP + 1];
   __shared__ double sHH[RP][RP + 1];
-  __shared__ double sRed[256];
-  __shared__ double sPar[3];  // w_W, w_H, ||H H^T||_F of the kept H
-  __shared__ int sMode;       // 0: candidate dropped, 1: kept, 2: first step
-  const int tid = threadIdx.x;
+  __shared__ double sPart[3][4];  // per-wave sums: objective, ||H_n H_n^T||^2, ||G||^2
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int m = b.m, r = b.r;
   const int64_t mr = (int64_t)m * r;
   BcdState* st = b.st;
-  const int first = st->first;
-  __syncthreads();  // every wave has read the state before thread 0 rewrites it
-  if (first) {
-    if (tid == 0) {
-      double g2 = 0.0;
-      for (int e = 0; e < r * r; ++e) g2 += b.red[mr + e] * b.red[mr + e];
-      BcdState s = *st;
-      s.first = 0;
-      s.gH = std::sqrt(g2);
-      s.wW = s.wH = 0.0;
-      *st = s;
-      sMode = 2;
-      sPar[0] = 0.0;
-      sPar[1] = 0.0;
-      sPar[2] = s.gH;
+  const BcdState s0 = *st;
+  // rows of one 256-row chunk: kept W, W before it, candidate W, X H^T kept and candidate
+  float wc[RP], wp[RP], wn[RP];
+  double xc[RP], xn[RP];
+  auto load_rows = [&](int i0) {
+    const int i = i0 + tid;
+    const bool ok = i < m;
+    const int ic = ok ? i : m - 1;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+      const int64_t e = (int64_t)ic * r + min(c, r - 1);
+      const bool v = ok && c < r;
+      wc[c] = bmask(b.W[e], v);
+      wp[c] = bmask(b.Wp[e], v);
+      wn[c] = bmask(b.Wn[e], v);
+      xc[c] = bmask(b.XHc[e], v);
+      xn[c] = bmask(b.red[e], v);
     }
-  } else {
-    double a = 0.0;
-    for (int i = tid; i < b.G * ((m + 63) / 64); i += 256) a += b.rpart[i];
-    sRed[tid] = a;
-    __syncthreads();
-    if (tid == 0) {
-      double f = 0.0;
-      for (int i = 0; i < 256; ++i) f += sRed[i];
-      f *= 0.5;
-      if (b.trace) b.trace[0] = f;
-      BcdState s = *st;
-      if (f < s.obj) {
-        const double tp = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * s.t * s.t));
-        const double w = (s.t - 1.0) / tp;
-        double g2 = 0.0;
-        for (int e = 0; e < r * r; ++e) g2 += b.red[mr + e] * b.red[mr + e];
-        const double gHn = std::sqrt(g2), gWn = s.gWn;
-        s.wW = gHn > 0.0 ? std::min(w, b.delta * std::sqrt(s.gH / gHn)) : w;
-        s.wH = gWn > 0.0 ? std::min(w, b.delta * std::sqrt(s.gW / gWn)) : w;
-        s.gH = gHn;
-        s.gW = gWn;
-        s.t = tp;
-        s.obj = f;
-        const int old_prev = s.prev;
-        s.prev = s.cur;
-        s.cur = s.nxt;
-        s.nxt = old_prev;
-        sMode = 1;
-      } else {
-        s.wW = s.wH = 0.0;
-        s.corrections += 1;
-        sMode = 0;
-      }
-      *st = s;
-      sPar[0] = s.wW;
-      sPar[1] = s.wH;
-      sPar[2] = s.gH;
-    }
-  }
-  __syncthreads();
-  const int mode = sMode;
-  const double wW = sPar[0], LW = sPar[2];
-  // H H^T of the kept H into LDS (and into HHc when it changed)
-  for (int e = tid; e < RP * RP; e += 256) {
+  };
+  load_rows(0);
+  const int nres = b.G * ((m + 63) / 64);
+  double fpart = 0.0;
+  if (!s0.first)
+    for (int i = tid; i < nres; i += 256) fpart += b.rpart[i];
+  constexpr int NG = (RP * RP + 255) / 256;
+  constexpr int GT = RP * RP >= 256 ? 1 : 256 / (RP * RP);
+  double hn[NG], hc[NG];
+  double g2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < NG; ++t) {
+    const int e = tid + 256 * t;
     const int c = e / RP, q = e % RP;
-    double v = 0.0;
-    if (c < r && q < r) {
-      v = mode ? b.red[mr + c * r + q] : b.HHc[c * r + q];
-      if (mode) b.HHc[c * r + q] = v;
+    const bool ok = e < RP * RP && c < r && q < r;
+    const int64_t ee = ok ? (int64_t)c * r + q : 0;
+    hn[t] = bmask(b.red[mr + ee], ok);
+    hc[t] = bmask(b.HHc[ee], ok);
+    g2 += hn[t] * hn[t];
+  }
+  fpart = bcd_wave_sum(fpart);
+  g2 = bcd_wave_sum(g2);
+  if (ln == 0) {
+    sPart[0][wv] = fpart;
+    sPart[1][wv] = g2;
+  }
+  __syncthreads();  // also: every wave has read the state before thread 0 rewrites it
+  const double f = 0.5 * (((sPart[0][0] + sPart[0][1]) + sPart[0][2]) + sPart[0][3]);
+  const double gHn = std::sqrt(((sPart[1][0] + sPart[1][1]) + sPart[1][2]) + sPart[1][3]);
+  BcdState s = s0;
+  int mode;  // 0: candidate dropped, 1: kept, 2: first step
+  if (s0.first) {
+    mode = 2;
+    s.first = 0;
+    s.gH = gHn;
+    s.wW = s.wH = 0.0;
+  } else if (f < s0.obj) {
+    mode = 1;
+    const double tp = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * s0.t * s0.t));
+    const double w = (s0.t - 1.0) / tp;
+    s.wW = gHn > 0.0 ? std::min(w, b.delta * std::sqrt(s0.gH / gHn)) : w;
+    s.wH = s0.gWn > 0.0 ? std::min(w, b.delta * std::sqrt(s0.gW / s0.gWn)) : w;
+    s.gH = gHn;
+    s.gW = s0.gWn;
+    s.t = tp;
+    s.obj = f;
+    s.prev = s0.cur;
+    s.cur = s0.nxt;
+    s.nxt = s0.prev;
+  } else {
+    mode = 0;
+    s.wW = s.wH = 0.0;
+    s.corrections += 1;
+  }
+  if (tid == 0) {
+    if (b.trace && !s0.first) b.trace[0] = f;
+    *st = s;
+  }
+  // H H^T of the kept H into LDS (and into HHc when it changed)
+#pragma unroll
+  for (int t = 0; t < NG; ++t) {
+    const int e = tid + 256 * t;
+    if (e < RP * RP) {
+      const int c = e / RP, q = e % RP;
+      const double v = mode ? hn[t] : hc[t];
+      sHH[c][q] = v;
+      if (mode && c < r && q < r) b.HHc[c * r + q] = v;
     }
-    sHH[c][q] = v;
   }
   if (final_step) {
-    for (int64_t e = tid; e < mr; e += 256)
-      if (mode == 1) {
-        b.Wp[e] = b.W[e];
-        b.W[e] = b.Wn[e];
-        b.XHc[e] = b.red[e];
-      }
+    for (int i0 = 0; i0 < m; i0 += 256) {
+      if (i0 > 0) load_rows(i0);
+      const int i = i0 + tid;
+      if (mode == 1 && i < m)
+#pragma unroll
+        for (int c = 0; c < RP; ++c)
+          if (c < r) {
+            const int64_t e = (int64_t)i * r + c;
+            b.Wp[e] = wc[c];
+            b.W[e] = wn[c];
+            b.XHc[e] = xn[c];
+          }
+    }
     if (tid == 0) {
-      b.scal[SCAL_BCD_CORR] = (double)st->corrections;
-      b.scal[SCAL_BCD_OBJ] = st->obj;
+      b.scal[SCAL_BCD_CORR] = (double)s.corrections;
+      b.scal[SCAL_BCD_OBJ] = s.obj;
     }
     return;
   }
   __syncthreads();
-  constexpr int NG = (RP * RP + 255) / 256;
+  const double wW = s.wW, LW = s.gH;
   double gacc[NG];
 #pragma unroll
   for (int t = 0; t < NG; ++t) gacc[t] = 0.0;
   for (int i0 = 0; i0 < m; i0 += 256) {
+    if (i0 > 0) load_rows(i0);
     const int i = i0 + tid;
-    float wn[RP];
+    float wo[RP];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) wn[c] = 0.f;
+    for (int c = 0; c < RP; ++c) wo[c] = 0.f;
     if (i < m) {
       double wm[RP], xh[RP];
 #pragma unroll
       for (int c = 0; c < RP; ++c) {
-        wm[c] = 0.0;
-        xh[c] = 0.0;
+        // the kept W (and the kept W before it) after the decision
+        const double cur = mode == 1 ? (double)wn[c] : (double)wc[c];
+        const double prv = mode == 1 ? (double)wc[c] : (double)wp[c];
+        xh[c] = mode ? xn[c] : xc[c];
+        wm[c] = wW != 0.0 ? cur + wW * (cur - prv) : cur;
         if (c < r) {
           const int64_t e = (int64_t)i * r + c;
-          double wc, wp;
           if (mode == 1) {
-            wp = b.W[e];
-            wc = b.Wn[e];
-            b.Wp[e] = (float)wp;
-            b.W[e] = (float)wc;
-            xh[c] = b.red[e];
-            b.XHc[e] = xh[c];
-          } else {
-            wc = b.W[e];
-            wp = wW != 0.0 ? (double)b.Wp[e] : wc;
-            xh[c] = mode == 2 ? b.red[e] : b.XHc[e];
-            if (mode == 2) b.XHc[e] = xh[c];
+            b.Wp[e] = wc[c];
+            b.W[e] = wn[c];
           }
-          wm[c] = wW != 0.0 ? wc + wW * (wc - wp) : wc;
+          if (mode) b.XHc[e] = xh[c];
         }
       }
 #pragma unroll
@@ -304,51 +426,74 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
 #pragma unroll
           for (int q = 0; q < RP; ++q) gr += wm[q] * sHH[q][c];
           const double v = LW > 0.0 ? wm[c] - gr / LW : wm[c];
-          wn[c] = (float)std::max(0.0, v);
-          b.Wn[(int64_t)i * r + c] = wn[c];
+          wo[c] = (float)std::max(0.0, v);
+          b.Wn[(int64_t)i * r + c] = wo[c];
         }
       }
     }
 #pragma unroll
-    for (int c = 0; c < RP; ++c) sWn[tid][c] = wn[c];
+    for (int c = 0; c < RP; ++c) sWn[tid][c] = wo[c];
     __syncthreads();
+    // GT threads per pair while there are fewer pairs than threads, each over 256 / GT
+    // rows of the chunk
 #pragma unroll
     for (int t = 0; t < NG; ++t) {
-      const int pidx = tid + 256 * t;
+      const int pidx = tid / GT + (256 / GT) * t;
       if (pidx < RP * RP) {
         const int c = pidx / RP, q = pidx % RP;
-        double s = gacc[t];
-        const int rows = min(256, m - i0);
-        for (int j = 0; j < rows; ++j) s += (double)sWn[j][c] * (double)sWn[j][q];
-        gacc[t] = s;
+        const int j1 = (tid % GT) * (256 / GT);
+        const int j2 = min(j1 + 256 / GT, m - i0);
+        double sum = gacc[t];
+        for (int j = j1; j < j2; ++j) sum += (double)sWn[j][c] * (double)sWn[j][q];
+        gacc[t] = sum;
       }
     }
     __syncthreads();
   }
-  double g2 = 0.0;
+  double gg = 0.0;
+  double* sGp = reinterpret_cast<double*>(&sWn[0][0]);  // 256 doubles fit in sWn
 #pragma unroll
   for (int t = 0; t < NG; ++t) {
-    const int pidx = tid + 256 * t;
-    if (pidx < RP * RP) {
+    __syncthreads();
+    sGp[tid] = gacc[t];
+    __syncthreads();
+    const int pidx = tid / GT + (256 / GT) * t;
+    if (tid % GT == 0 && pidx < RP * RP) {
       const int c = pidx / RP, q = pidx % RP;
-      b.GWn[c * 32 + q] = (float)gacc[t];
-      g2 += gacc[t] * gacc[t];
+      double v = sGp[tid];
+      for (int p2 = 1; p2 < GT; ++p2) v += sGp[tid + p2];
+      b.GWn[c * 32 + q] = (float)v;
+      gg += v * v;
     }
   }
-  sRed[tid] = g2;
+  gg = bcd_wave_sum(gg);
+  if (ln == 0) sPart[2][wv] = gg;
   __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int i = 0; i < 256; ++i) s += sRed[i];
-    st->gWn = std::sqrt(s);
-  }
+  if (tid == 0) st->gWn = std::sqrt(((sPart[2][0] + sPart[2][1]) + sPart[2][2]) + sPart[2][3]);
 }
 
-// The H step, one thread per column: H_m from the kept H (and, with extrapolation, the
-// kept H before it), W_n^T X with W_n streamed through LDS in 64-row chunks, then
+// The H step, CPT adjacent columns per thread (vector loads and stores; k % CPT == 0 and
+// 4 CPT-byte aligned rows): H_m from the kept H (and, with extrapolation, the kept H
+// before it), W_n^T X with W_n streamed through LDS in 64-row chunks, then
 // H_n = max(0, H_m - (G H_m - W_n^T X) / ||G||_F) into Hb[nxt].
-template <int RP>
+template <int N> struct BVec { typedef float __attribute__((ext_vector_type(N))) T; };
+template <> struct BVec<1> { typedef float T; };
+
+template <int N>
+__device__ __forceinline__ float bget(const typename BVec<N>::T& v, int u) {
+  if constexpr (N == 1) return v;
+  else return v[u];
+}
+
+template <int N>
+__device__ __forceinline__ void bset(typename BVec<N>::T& v, int u, float x) {
+  if constexpr (N == 1) v = x;
+  else v[u] = x;
+}
+
+template <int RP, int CPT>
 __global__ __launch_bounds__(256) void k_bcd_h(BcdArgs b) {
+  typedef typename BVec<CPT>::T VT;
   __shared__ float sW[64][RP + 1];
   __shared__ float sG[RP][RP + 1];
   const int tid = threadIdx.x;
@@ -361,21 +506,85 @@ __global__ __launch_bounds__(256) void k_bcd_h(BcdArgs b) {
   const float wH = (float)st->wH;
   const double LH = st->gWn;
   const float Lf = (float)LH;
-  const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t j = ((int64_t)blockIdx.x * 256 + tid) * CPT;
   const bool act = j < k;
-  const int64_t jc = act ? j : k - 1;
-  float hm[RP];
+  const int64_t jc = act ? j : k - CPT;
+  float hm[CPT][RP];
 #pragma unroll
   for (int c = 0; c < RP; ++c) {
     const int64_t e = (int64_t)min(c, r - 1) * k + jc;
-    const float hc = bmask(Hc[e], act && c < r);
+    const bool ok = act && c < r;
+    const VT hc = *reinterpret_cast<const VT*>(Hc + e);
     if (wH != 0.f) {
-      const float hp = bmask(Hp[e], act && c < r);
-      hm[c] = fmaf(wH, hc - hp, hc);
+      const VT hp = *reinterpret_cast<const VT*>(Hp + e);
+#pragma unroll
+      for (int u = 0; u < CPT; ++u)
+        hm[u][c] = bmask(fmaf(wH, bget<CPT>(hc, u) - bget<CPT>(hp, u), bget<CPT>(hc, u)), ok);
     } else {
-      hm[c] = hc;
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) hm[u][c] = bmask(bget<CPT>(hc, u), ok);
     }
   }
+  for (int e = tid; e < RP * RP; e += 256) sG[e / RP][e % RP] = b.GWn[(e / RP) * 32 + e % RP];
+  float acc[CPT][RP];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u)
+#pragma unroll
+    for (int c = 0; c < RP; ++c) acc[u][c] = 0.f;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * RP; e += 256) {
+      const int i = e / RP, c = e % RP;
+      sW[i][c] = bmask(b.Wn[(int64_t)min(i0 + i, m - 1) * r + min(c, r - 1)], i0 + i < m && c < r);
+    }
+    __syncthreads();
+    const int iend = min(64, m - i0);
+#pragma unroll 8
+    for (int i = 0; i < iend; ++i) {
+      const VT x = *reinterpret_cast<const VT*>(b.X + (int64_t)(i0 + i) * k + jc);
+#pragma unroll
+      for (int u = 0; u < CPT; ++u)
+#pragma unroll
+        for (int c = 0; c < RP; ++c) acc[u][c] = fmaf(sW[i][c], bget<CPT>(x, u), acc[u][c]);
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+      if (c < r) {
+        VT out;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          float gr = -acc[u][c];
+#pragma unroll
+          for (int q = 0; q < RP; ++q) gr = fmaf(sG[c][q], hm[u][q], gr);
+          const float v = LH > 0.0 ? hm[u][c] - gr / Lf : hm[u][c];
+          bset<CPT>(out, u, fmaxf(0.f, v));
+        }
+        *reinterpret_cast<VT*>(Hn + (int64_t)c * k + j) = out;
+      }
+    }
+  }
+}
+
+// The H step with the rows of W_n^T X split over RG thread groups (short unfoldings, where
+// one thread per column gives too few workgroups): a workgroup takes CT = 256 / RG
+// columns; thread (g, col) sums rows i = g, g + RG, ... of each 64-row chunk; the RG
+// partial sums are added in order in LDS and CT threads apply the step to their column.
+template <int RP, int RG>
+__global__ __launch_bounds__(256) void k_bcd_hs(BcdArgs b) {
+  constexpr int CT = 256 / RG;
+  __shared__ float sW[64][RP + 1];
+  __shared__ float sG[RP][RP + 1];
+  __shared__ float sAcc[RG][CT][RP + 1];
+  const int tid = threadIdx.x;
+  const int m = b.m, r = b.r;
+  const int64_t k = b.k;
+  const BcdState* st = b.st;
+  const int grp = tid / CT, col = tid % CT;
+  const int64_t j = (int64_t)blockIdx.x * CT + col;
+  const bool act = j < k;
+  const int64_t jc = act ? j : k - 1;
   for (int e = tid; e < RP * RP; e += 256) sG[e / RP][e % RP] = b.GWn[(e / RP) * 32 + e % RP];
   float acc[RP];
 #pragma unroll
@@ -387,19 +596,42 @@ __global__ __launch_bounds__(256) void k_bcd_h(BcdArgs b) {
       sW[i][c] = bmask(b.Wn[(int64_t)min(i0 + i, m - 1) * r + min(c, r - 1)], i0 + i < m && c < r);
     }
     __syncthreads();
-    const int iend = min(64, m - i0);
-#pragma unroll 8
-    for (int i = 0; i < iend; ++i) {
-      const float x = bmask(b.X[(int64_t)(i0 + i) * k + jc], act);
+    // all 64 / RG rows of the chunk in flight at once (sW is zero beyond m)
+    float xs[64 / RG];
 #pragma unroll
-      for (int c = 0; c < RP; ++c) acc[c] = fmaf(sW[i][c], x, acc[c]);
+    for (int u = 0; u < 64 / RG; ++u)
+      xs[u] = b.X[(int64_t)min(i0 + grp + u * RG, m - 1) * k + jc];
+#pragma unroll
+    for (int u = 0; u < 64 / RG; ++u) {
+      const float x = act ? xs[u] : 0.f;
+#pragma unroll
+      for (int c = 0; c < RP; ++c) acc[c] = fmaf(sW[grp + u * RG][c], x, acc[c]);
     }
   }
-  if (act) {
+#pragma unroll
+  for (int c = 0; c < RP; ++c) sAcc[grp][col][c] = acc[c];
+  __syncthreads();
+  if (tid < CT && act) {
+    const float* __restrict__ Hc = b.Hb[st->cur];
+    const float* __restrict__ Hp = b.Hb[st->prev];
+    float* __restrict__ Hn = b.Hb[st->nxt];
+    const float wH = (float)st->wH;
+    const double LH = st->gWn;
+    const float Lf = (float)LH;
+    float hm[RP], wx[RP];
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+      float a = 0.f;
+      for (int g2 = 0; g2 < RG; ++g2) a += sAcc[g2][tid][c];
+      wx[c] = a;
+      const int64_t e = (int64_t)min(c, r - 1) * k + j;
+      const float hc = Hc[e];
+      hm[c] = c < r ? (wH != 0.f ? fmaf(wH, hc - Hp[e], hc) : hc) : 0.f;
+    }
 #pragma unroll
     for (int c = 0; c < RP; ++c) {
       if (c < r) {
-        float gr = -acc[c];
+        float gr = -wx[c];
 #pragma unroll
         for (int q = 0; q < RP; ++q) gr = fmaf(sG[c][q], hm[q], gr);
         const float v = LH > 0.0 ? hm[c] - gr / Lf : hm[c];
@@ -428,13 +660,66 @@ __global__ void k_bcd_commit(BcdArgs b) {
 
 int bcd_rp(int r) { return r <= 8 ? 8 : (r <= 16 ? 16 : 32); }
 
+bool aligned(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
+
 template <int RP>
 hipError_t bcd_xht(const BcdArgs& b, bool resid, hipStream_t s) {
   const dim3 grid((unsigned)b.G, (unsigned)((b.m + 63) / 64));
-  if (resid) k_bcd_xht<RP, true><<<grid, 256, 0, s>>>(b, 0);
-  else k_bcd_xht<RP, false><<<grid, 256, 0, s>>>(b, 1);
+  const bool xv = b.k % 4 == 0 && aligned(b.X, 16);
+  if (resid) {
+    if (xv) k_bcd_xht<RP, true, true><<<grid, 256, 0, s>>>(b, 0);
+    else k_bcd_xht<RP, true, false><<<grid, 256, 0, s>>>(b, 0);
+  } else {
+    if (xv) k_bcd_xht<RP, false, true><<<grid, 256, 0, s>>>(b, 1);
+    else k_bcd_xht<RP, false, false><<<grid, 256, 0, s>>>(b, 1);
+  }
   NTT_BCD_CHECK();
   return hipSuccess;
+}
+
+// columns per thread of the H step: 4 at r <= 8, 2 at r <= 16, else 1, when the rows
+// allow vector access
+int bcd_cpt(const BcdArgs& b) {
+  int c = b.r <= 8 ? 4 : (b.r <= 16 ? 2 : 1);
+  while (c > 1 && !(b.k % c == 0 && aligned(b.X, 4 * c) && aligned(b.Hb[0], 4 * c) &&
+                    aligned(b.Hb[1], 4 * c) && aligned(b.Hb[2], 4 * c)))
+    c >>= 1;
+  return c;
+}
+
+template <int RP, int CPT>
+hipError_t bcd_h(const BcdArgs& b, hipStream_t s) {
+  const int64_t nb = (b.k + 256 * CPT - 1) / (256 * CPT);
+  k_bcd_h<RP, CPT><<<(unsigned)nb, 256, 0, s>>>(b);
+  NTT_BCD_CHECK();
+  return hipSuccess;
+}
+
+template <int RP, int RG>
+hipError_t bcd_hs(const BcdArgs& b, hipStream_t s) {
+  const int64_t nb = (b.k + 256 / RG - 1) / (256 / RG);
+  k_bcd_hs<RP, RG><<<(unsigned)nb, 256, 0, s>>>(b);
+  NTT_BCD_CHECK();
+  return hipSuccess;
+}
+
+hipError_t bcd_h_any(const BcdArgs& b, hipStream_t s) {
+  const int cpt = bcd_cpt(b);
+  // short unfoldings: rows split over 4 (64 columns per workgroup) or 16 thread groups
+  if ((b.k + 256 * cpt - 1) / (256 * cpt) < 512) {
+    const bool rg4 = (b.k + 63) / 64 >= 256;
+    switch (bcd_rp(b.r)) {
+      case 8: return rg4 ? bcd_hs<8, 4>(b, s) : bcd_hs<8, 16>(b, s);
+      case 16: return rg4 ? bcd_hs<16, 4>(b, s) : bcd_hs<16, 16>(b, s);
+      default: return rg4 ? bcd_hs<32, 4>(b, s) : bcd_hs<32, 16>(b, s);
+    }
+  }
+  switch (bcd_rp(b.r)) {
+    case 8:
+      return cpt == 4 ? bcd_h<8, 4>(b, s) : (cpt == 2 ? bcd_h<8, 2>(b, s) : bcd_h<8, 1>(b, s));
+    case 16: return cpt == 2 ? bcd_h<16, 2>(b, s) : bcd_h<16, 1>(b, s);
+    default: return bcd_h<32, 1>(b, s);
+  }
 }
 
 hipError_t bcd_xht_any(const BcdArgs& b, bool resid, hipStream_t s) {
@@ -511,13 +796,8 @@ hipError_t launch_bcd_iter(const BcdArgs& b, hipStream_t s) {
   if (!bcd_args_ok(b)) return hipErrorInvalidValue;
   hipError_t e = bcd_step(b, 0, s);
   if (e != hipSuccess) return e;
-  const int64_t nb = (b.k + 255) / 256;
-  switch (bcd_rp(b.r)) {
-    case 8: k_bcd_h<8><<<(unsigned)nb, 256, 0, s>>>(b); break;
-    case 16: k_bcd_h<16><<<(unsigned)nb, 256, 0, s>>>(b); break;
-    default: k_bcd_h<32><<<(unsigned)nb, 256, 0, s>>>(b); break;
-  }
-  NTT_BCD_CHECK();
+  e = bcd_h_any(b, s);
+  if (e != hipSuccess) return e;
   e = bcd_xht_any(b, true, s);
   if (e != hipSuccess) return e;
   return bcd_reduce(b, s);

@@ -76,6 +76,9 @@ SHAPES = [
     # (m, k, r): ragged m and k, ranks at the three paddings (8, 16, 32)
     (16, 256, 4), (7, 33, 3), (45, 517, 5), (100, 301, 16), (130, 77, 32), (1, 50, 1),
     (200, 3, 3), (33, 250, 24), (300, 2000, 10), (64, 4099, 8), (520, 700, 12),
+    # H step with rows split over 4 groups, one column per thread (odd k) and 4 columns
+    # per thread with a ragged last workgroup
+    (200, 40000, 6), (16, 300001, 3), (24, 600004, 5),
 ]
 
 
