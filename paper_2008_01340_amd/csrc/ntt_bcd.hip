@@ -37,6 +37,8 @@ namespace {
 __device__ __forceinline__ float bmask(float v, bool ok) { return v * (ok ? 1.f : 0.f); }
 __device__ __forceinline__ double bmask(double v, bool ok) { return v * (ok ? 1.0 : 0.0); }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double bcd_wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -306,9 +308,14 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
   const int nres = b.G * ((m + 63) / 64);
   double fpart = 0.0;
   if (!s0.first)
-    for (int i = tid; i < nres; i += 256) fpart += b.rpart[i];
+    for (int i0 = tid; i0 < nres; i0 += 256 * 8) {  // eight independent loads at a time
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = bmask(b.rpart[min(i0 + 256 * u, nres - 1)], i0 + 256 * u < nres);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) fpart += v[u];
+    }
   constexpr int NG = (RP * RP + 255) / 256;
-  constexpr int GT = RP * RP >= 256 ? 1 : 256 / (RP * RP);
   double hn[NG], hc[NG];
   double g2 = 0.0;
 #pragma unroll
@@ -392,9 +399,16 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
   }
   __syncthreads();
   const double wW = s.wW, LW = s.gH;
-  double gacc[NG];
+  // G = W_n^T W_n with FP64 MFMA (16 x 16 x 4): wave wv takes rows 64 wv .. 64 wv + 63 of
+  // each 256-row chunk, four rows a step, the lane (a, bq) feeding W_n[row 4 st + bq][a]
+  // as both operands; output register i of lane l is G[4 i + l / 16][l % 16]
+  constexpr int NT = (RP + 15) / 16;
+  v4d gm[NT][NT];
 #pragma unroll
-  for (int t = 0; t < NG; ++t) gacc[t] = 0.0;
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) gm[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int la = ln & 15, lb = ln >> 4;
   for (int i0 = 0; i0 < m; i0 += 256) {
     if (i0 > 0) load_rows(i0);
     const int i = i0 + tid;
@@ -434,37 +448,39 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
 #pragma unroll
     for (int c = 0; c < RP; ++c) sWn[tid][c] = wo[c];
     __syncthreads();
-    // GT threads per pair while there are fewer pairs than threads, each over 256 / GT
-    // rows of the chunk
+    const int nst = min(16, (m - i0 - 64 * wv + 3) / 4);  // steps holding rows < m
+    for (int st4 = 0; st4 < nst; ++st4) {
+      const int row = 64 * wv + 4 * st4 + lb;
+      double op[NT];
 #pragma unroll
-    for (int t = 0; t < NG; ++t) {
-      const int pidx = tid / GT + (256 / GT) * t;
-      if (pidx < RP * RP) {
-        const int c = pidx / RP, q = pidx % RP;
-        const int j1 = (tid % GT) * (256 / GT);
-        const int j2 = min(j1 + 256 / GT, m - i0);
-        double sum = gacc[t];
-        for (int j = j1; j < j2; ++j) sum += (double)sWn[j][c] * (double)sWn[j][q];
-        gacc[t] = sum;
+      for (int h = 0; h < NT; ++h) {
+        const int c = 16 * h + la;
+        op[h] = c < RP ? (double)sWn[row][c < RP ? c : 0] : 0.0;
       }
+#pragma unroll
+      for (int h = 0; h < NT; ++h)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) gm[h][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[h], op[q], gm[h][q], 0, 0, 0);
     }
     __syncthreads();
   }
-  double gg = 0.0;
-  double* sGp = reinterpret_cast<double*>(&sWn[0][0]);  // 256 doubles fit in sWn
+  // the four waves' sums, added in wave order (sWn is free now)
+  double* sGp = reinterpret_cast<double*>(&sWn[0][0]);  // [4][NT * NT][64][4]
 #pragma unroll
-  for (int t = 0; t < NG; ++t) {
-    __syncthreads();
-    sGp[tid] = gacc[t];
-    __syncthreads();
-    const int pidx = tid / GT + (256 / GT) * t;
-    if (tid % GT == 0 && pidx < RP * RP) {
-      const int c = pidx / RP, q = pidx % RP;
-      double v = sGp[tid];
-      for (int p2 = 1; p2 < GT; ++p2) v += sGp[tid + p2];
-      b.GWn[c * 32 + q] = (float)v;
-      gg += v * v;
-    }
+  for (int h = 0; h < NT; ++h)
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sGp[(((size_t)wv * NT * NT + h * NT + q) * 64 + ln) * 4 + i] = gm[h][q][i];
+  __syncthreads();
+  double gg = 0.0;
+  for (int e = tid; e < RP * RP; e += 256) {
+    const int c = e / RP, q = e % RP;
+    const int h = c / 16, i = (c % 16) / 4, lane = (c % 4) * 16 + q % 16, qq = q / 16;
+    double v = 0.0;
+    for (int w4 = 0; w4 < 4; ++w4) v += sGp[(((size_t)w4 * NT * NT + h * NT + qq) * 64 + lane) * 4 + i];
+    b.GWn[c * 32 + q] = (float)v;
+    gg += v * v;
   }
   gg = bcd_wave_sum(gg);
   if (ln == 0) sPart[2][wv] = gg;
