@@ -102,7 +102,8 @@ typedef struct {
                            ntt_decompose only; it ignores eps and NTT_PROFILE, and with
                            NTT_RECORD_OBJECTIVE stores the objective of every iteration's
                            candidate pair (kept or dropped, FP64 residual).  Its workspace
-                           adds two r_l x (n_{l+1}..n_d) buffers per stage. */
+                           adds two r_l x (n_{l+1}..n_d) buffers per stage; unfoldings may
+                           have at most 4194240 rows. */
   double bcd_delta;     /* BCD: cap of the extrapolation weights, in [0, 1) (0.9999 is
                            usual; 0 turns extrapolation off) */
 } ntt_config;

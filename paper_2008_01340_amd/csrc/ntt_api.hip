@@ -426,6 +426,10 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     }
     p->total_iters += cfg->max_iters;
   }
+  if (bcd && m_max > 64 * 65535) {
+    delete p;
+    return fail(NTT_ERR_INVALID_ARG, "BCD: an unfolding has more than 4194240 rows");
+  }
   if (eps_mode && n_max > 2048) {
     delete p;
     return fail(NTT_ERR_INVALID_ARG, "rank_eps: an unfolding's shorter side exceeds 2048");

@@ -89,6 +89,7 @@ def test_plan_strict_ranks_errors():
     ({"nmf": "bcd", "delta": 1.0}, (4, 5), (1, 2, 1)),
     ({"nmf": "bcd", "delta": -0.5}, (4, 5), (1, 2, 1)),
     ({"nmf": "bcd", "delta": float("nan")}, (4, 5), (1, 2, 1)),
+    ({"nmf": "bcd"}, (5000000, 2), (1, 1, 1)),  # BCD: more rows than its grid takes
 ])
 def test_plan_rejects_invalid_configs(kw, dims, ranks):
     args = {"max_iters": 10}
