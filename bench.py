@@ -125,30 +125,43 @@ def paper_workload(ntt, S, torch):
                         "gflop": res.report["total_gflop"], "rel_error": ntt.rel_error(A, res.cores),
                         "stage_ms": res.report["ms"], "compression": res.report["compression_ratio"]}
         progress(f"paper workload: ranks {r}: {ms:.1f} ms")
+    # the paper times both NMF methods on this workload (Fig.5): BCD at ranks 10
+    ranks = (1, 10, 10, 10, 1)
+    plan = ntt.Plan(w.dims, ranks, w.iters, seed=w.seed, nmf="bcd")
+    res = ntt.decompose(A, ranks, w.iters, plan=plan, want_report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ntt.decompose(A, ranks, w.iters, plan=plan, cores=res.cores)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out["bcd_r10"] = {"ms": ms, "rel_error": ntt.rel_error(A, res.cores), "stage_ms": res.report["ms"],
+                      "corrections": res.report["corrections"]}
+    progress(f"paper workload: BCD ranks 10: {ms:.1f} ms")
     del A
     return out
 
 
 def rank_rule(ntt, S, torch):
     """Compression against relative error with the rank rule of Alg.2 (the style of the
-    paper's Fig.8), on the 128^4 workload, rank caps 16, for the paper's thresholds."""
+    paper's Fig.8, which draws it for both NMF methods), on the 128^4 workload, rank caps
+    16, for the paper's thresholds, with MU and with BCD."""
     w = S.workload("tt128x4_r16")
     A = torch.from_numpy(w.tensor()).cuda()
     caps = (1, 16, 16, 16, 1)
     out = {"workload": f"{w.name}: {w.note}; rank caps 16", "points": []}
-    for eps in (0.5, 0.25, 0.125, 0.075, 0.01, 0.005, 0.001):
-        plan = ntt.Plan(w.dims, caps, w.iters, eps=w.eps, seed=w.seed, rank_eps=eps)
+    for nmf, eps in [(n, e) for n in ("mu", "bcd") for e in (0.5, 0.25, 0.125, 0.075, 0.01, 0.005, 0.001)]:
+        plan = ntt.Plan(w.dims, caps, w.iters, eps=w.eps, seed=w.seed, rank_eps=eps, nmf=nmf)
         res = ntt.decompose(A, caps, w.iters, plan=plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = ntt.decompose(A, caps, w.iters, plan=plan)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        out["points"].append({"rank_eps": eps, "ranks": res.ranks, "ms": ms,
+        out["points"].append({"nmf": nmf, "rank_eps": eps, "ranks": res.ranks, "ms": ms,
                               "compression": res.report["compression_ratio"],
                               "rel_error": ntt.rel_error(A, res.cores),
                               "stage_ms": res.report["ms"]})
-        progress(f"rank rule: eps {eps}: ranks {res.ranks}, {ms:.1f} ms")
+        progress(f"rank rule: {nmf} eps {eps}: ranks {res.ranks}, {ms:.1f} ms")
     del A
     return out
 
