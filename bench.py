@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(A, w, seconds):
+def cpu_baseline(A, w, seconds, bcd_seconds=0.0):
     """The FP64 oracle on this host, on a bounded sample: MU iterations of stage 1."""
     import numpy as np
     import oracle as O
@@ -75,9 +75,21 @@ def cpu_baseline(A, w, seconds):
         if el >= seconds or n >= 500:
             break
     flops = n * (4.0 * m * k * r + 4.0 * (m + k) * r * r)
-    return {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}) of the same workload, "
-                      f"NumPy FP64, {el:.1f} s"}
+    out = {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}) of the same workload, "
+                     f"NumPy FP64, {el:.1f} s"}
+    if bcd_seconds > 0:
+        # the BCD oracle (Alg.3) on the same first unfolding: ms per iteration
+        W0, H0 = O.init_factors(w.seed, 1, m, r, k)
+        t0 = time.perf_counter()
+        O.bcd_nmf(X, W0, H0, 1)
+        nb = max(2, min(64, int(bcd_seconds / (time.perf_counter() - t0))))
+        t0 = time.perf_counter()
+        O.bcd_nmf(X, W0, H0, nb)
+        el = time.perf_counter() - t0
+        out["bcd"] = {"ms_per_iter": el * 1e3 / nb, "kind": "oracle",
+                      "sample": f"{nb} BCD iterations of stage 1 ({m}x{k}, r={r}), NumPy FP64, {el:.1f} s"}
+    return out
 
 
 def precision_mode(ntt, S, torch):
@@ -192,7 +204,12 @@ def bcd(ntt, S, torch, mu_err, mu_ms):
            "rel_error": err, "mu_rel_error": mu_err, "mu_ms": mu_ms,
            "corrections": res.report["corrections"], "stage_ms": res.report["ms"],
            "stage1_ms_per_iter": it_ms,
-           "stage1_gbs": bytes_it / (it_ms * 1e-3) / 1e9, "stage1_bytes_per_iter": bytes_it}
+           "stage1_gbs": bytes_it / (it_ms * 1e-3) / 1e9, "stage1_bytes_per_iter": bytes_it,
+           # a whole stage-1 iteration (step, H step, products, reduction) against HBM
+           "roofline": {"bound": "hbm", "achieved": bytes_it / (it_ms * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": bytes_it / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "BCD stage-1 iteration (32x1048576, r=8), four launches"}}
     progress(f"bcd: {ms:.1f} ms, rel err {err:.4e} (MU {mu_err:.4e}), corrections "
              f"{res.report['corrections']}")
     del A
@@ -409,7 +426,8 @@ def main():
             "note": f"{args.serve_requests} requests of the serving stream recipe, sizes capped at "
                     f"{args.serve_max_mb} MB, Poisson arrivals at 0.5 and 0.8 of the saturated rate"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_seconds,
+                                           4.0 if "bcd" in extras else 0.0)
     print(json.dumps(out), flush=True)
 
 
