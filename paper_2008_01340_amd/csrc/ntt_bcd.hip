@@ -38,6 +38,7 @@ __device__ __forceinline__ float bmask(float v, bool ok) { return v * (ok ? 1.f 
 __device__ __forceinline__ double bmask(double v, bool ok) { return v * (ok ? 1.0 : 0.0); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double bcd_wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -265,6 +266,169 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
   if (RESID) {
     res = bcd_wave_sum(res);
     if ((tid & 63) == 0) sRes[tid >> 6] = res;
+    __syncthreads();
+    if (tid == 0) b.rpart[(int64_t)g * gridDim.y + rb] = ((sRes[0] + sRes[1]) + sRes[2]) + sRes[3];
+  }
+}
+
+// The same products with FP32 MFMA (16 x 16 x 4), for unfoldings of more than 32 rows
+// (X 16-byte readable, k % 4 == 0).  Block (g, rb) as above; wave w owns tile rows
+// 16 w .. 16 w + 15.  Lane l = (a, q4) with a = l % 16, q4 = l / 16; output register i of
+// an MFMA is D[4 q4 + i][a].  Per 64-column tile:
+//   X H^T: A = X[16 w + a][4 s + q4], B = H[16 n + a][4 s + q4] over s = 0..15;
+//   W_n H (residual): A = W_n[16 w + a][4 s + q4] (registers), B = H[4 s + q4][16 cb + a],
+//     the result lined up with X[16 w + 4 q4 + i][16 cb + a] read from LDS;
+//   H H^T (rb = 0): the 16 column steps split over the four waves, summed in wave order.
+template <int RP, bool RESID>
+__global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
+  constexpr int NB = (RP + 15) / 16;  // 16-wide rank blocks
+  constexpr int RQ = NB * 16;         // ranks padded to a multiple of 16
+  constexpr int HPT = RQ / 4;         // H tile entries per thread
+  __shared__ __attribute__((aligned(16))) float sX[64][68];
+  __shared__ __attribute__((aligned(16))) float sH[RQ][68];
+  __shared__ double sRes[4];
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63, la = ln & 15, lq = ln >> 4;
+  const int m = b.m, r = b.r;
+  const int64_t k = b.k;
+  const float* __restrict__ H = init ? b.Hb[0] : b.Hb[b.st->nxt];
+  const int g = blockIdx.x, rb = blockIdx.y;
+  const int64_t c0 = (int64_t)g * b.chunk, c1 = min(k, c0 + b.chunk);
+  const int mrows = min(64, m - 64 * rb);
+  float wop[RQ / 4];
+#pragma unroll
+  for (int s4 = 0; s4 < RQ / 4; ++s4) {
+    const int row = 64 * rb + 16 * wv + la, c = 4 * s4 + lq;
+    wop[s4] = RESID ? bmask(b.Wn[(int64_t)min(row, m - 1) * r + min(c, r - 1)], row < m && c < r) : 0.f;
+  }
+  v4f accx[NB];
+  v4f accg[NB][NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    accx[n] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NB; ++q) accg[n][q] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
+  double res = 0.0;
+  float4 xr0[4], xr1[4];
+  float hr0[HPT], hr1[HPT];
+  auto issue = [&](float4 (&xr)[4], float (&hr)[HPT], int64_t j0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (16 * q < mrows) {
+        const int e = tid + 256 * q;
+        const int i = e >> 4, j4 = (e & 15) * 4;
+        const int xi = 64 * rb + i;
+        const int64_t gj = j0 + j4;
+        const bool ok = xi < m && gj < c1;
+        xr[q] = *reinterpret_cast<const float4*>(b.X + (int64_t)min(xi, m - 1) * k + (ok ? gj : c0));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) {
+      const int e = tid + 256 * t;
+      const int c = e >> 6, jj = e & 63;
+      hr[t] = H[(int64_t)min(c, r - 1) * k + min(j0 + jj, c1 - 1)];
+    }
+  };
+  auto store = [&](const float4 (&xr)[4], const float (&hr)[HPT], int64_t j0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e >> 4, j4 = (e & 15) * 4;
+      const bool ok = 16 * q < mrows && 64 * rb + i < m && j0 + j4 < c1;
+      *reinterpret_cast<float4*>(&sX[i][j4]) = ok ? xr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int t = 0; t < HPT; ++t) {
+      const int e = tid + 256 * t;
+      const int c = e >> 6, jj = e & 63;
+      sH[c][jj] = (c < r && j0 + jj < c1) ? hr[t] : 0.f;
+    }
+  };
+  auto compute = [&]() {
+#pragma unroll 4
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const float av = sX[16 * wv + la][4 * s4 + lq];
+#pragma unroll
+      for (int n = 0; n < NB; ++n)
+        accx[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sH[16 * n + la][4 * s4 + lq], accx[n], 0, 0, 0);
+    }
+    if (rb == 0) {
+#pragma unroll
+      for (int s4 = 4 * wv; s4 < 4 * wv + 4; ++s4) {
+        float op[NB];
+#pragma unroll
+        for (int n = 0; n < NB; ++n) op[n] = sH[16 * n + la][4 * s4 + lq];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            accg[n][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[n], op[q], accg[n][q], 0, 0, 0);
+      }
+    }
+    if (RESID) {
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        v4f d = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = 0; s4 < RQ / 4; ++s4)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[s4], sH[4 * s4 + lq][16 * cb + la], d, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double dl = (double)sX[16 * wv + 4 * lq + i][16 * cb + la] - (double)d[i];
+          res += dl * dl;  // 0 outside the matrix
+        }
+      }
+    }
+  };
+  issue(xr0, hr0, c0);
+  if (c0 + 64 < c1) issue(xr1, hr1, c0 + 64);
+  for (int64_t j0 = c0; j0 < c1; j0 += 128) {
+    __syncthreads();
+    store(xr0, hr0, j0);
+    __syncthreads();
+    if (j0 + 128 < c1) issue(xr0, hr0, j0 + 128);
+    compute();
+    if (j0 + 64 < c1) {
+      __syncthreads();
+      store(xr1, hr1, j0 + 64);
+      __syncthreads();
+      if (j0 + 192 < c1) issue(xr1, hr1, j0 + 192);
+      compute();
+    }
+  }
+  float* dst = b.part + (int64_t)g * b.part_stride;
+#pragma unroll
+  for (int n = 0; n < NB; ++n)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 64 * rb + 16 * wv + 4 * lq + i, c = 16 * n + la;
+      if (row < m && c < r) dst[(int64_t)row * r + c] = accx[n][i];
+    }
+  if (rb == 0) {
+    __syncthreads();
+    float* sG = &sX[0][0];  // [4 waves][NB * NB][64 lanes][4]: at most 16 KB, within sX
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sG[(((wv * NB * NB) + n * NB + q) * 64 + ln) * 4 + i] = accg[n][q][i];
+    __syncthreads();
+    for (int e = tid; e < RQ * RQ; e += 256) {
+      const int c = e / RQ, q = e % RQ;
+      if (c < r && q < r) {
+        // FP32 16 x 16 x 4 output: register i of lane l is row 4 (l / 16) + i, column l % 16
+        const int n = c / 16, i = c % 4, lane = ((c % 16) / 4) * 16 + q % 16, qq = q / 16;
+        float v = 0.f;
+        for (int w4 = 0; w4 < 4; ++w4) v += sG[(((w4 * NB * NB) + n * NB + qq) * 64 + lane) * 4 + i];
+        dst[(int64_t)m * r + c * r + q] = v;
+      }
+    }
+  }
+  if (RESID) {
+    res = bcd_wave_sum(res);
+    if (ln == 0) sRes[wv] = res;
     __syncthreads();
     if (tid == 0) b.rpart[(int64_t)g * gridDim.y + rb] = ((sRes[0] + sRes[1]) + sRes[2]) + sRes[3];
   }
@@ -682,6 +846,12 @@ template <int RP>
 hipError_t bcd_xht(const BcdArgs& b, bool resid, hipStream_t s) {
   const dim3 grid((unsigned)b.G, (unsigned)((b.m + 63) / 64));
   const bool xv = b.k % 4 == 0 && aligned(b.X, 16);
+  if (xv && b.m > 32) {  // MFMA products
+    if (resid) k_bcd_xhtm<RP, true><<<grid, 256, 0, s>>>(b, 0);
+    else k_bcd_xhtm<RP, false><<<grid, 256, 0, s>>>(b, 1);
+    NTT_BCD_CHECK();
+    return hipSuccess;
+  }
   if (resid) {
     if (xv) k_bcd_xht<RP, true, true><<<grid, 256, 0, s>>>(b, 0);
     else k_bcd_xht<RP, true, false><<<grid, 256, 0, s>>>(b, 0);

@@ -79,6 +79,9 @@ SHAPES = [
     # H step with rows split over 4 groups, one column per thread (odd k) and 4 columns
     # per thread with a ragged last workgroup
     (200, 40000, 6), (16, 300001, 3), (24, 600004, 5),
+    # MFMA products (more than 32 rows, k % 4 == 0) at paddings 16 and 32, ragged last row
+    # block
+    (96, 1000, 24), (70, 3000, 32), (260, 4096, 16),
 ]
 
 
