@@ -271,33 +271,43 @@ __global__ __launch_bounds__(256) void k_bcd_xht(BcdArgs b, int init) {
   }
 }
 
-// The same products with FP32 MFMA (16 x 16 x 4), for unfoldings of more than 32 rows
-// (X 16-byte readable, k % 4 == 0).  Block (g, rb) as above; wave w owns tile rows
-// 16 w .. 16 w + 15.  Lane l = (a, q4) with a = l % 16, q4 = l / 16; output register i of
-// an MFMA is D[4 q4 + i][a].  Per 64-column tile:
-//   X H^T: A = X[16 w + a][4 s + q4], B = H[16 n + a][4 s + q4] over s = 0..15;
-//   W_n H (residual): A = W_n[16 w + a][4 s + q4] (registers), B = H[4 s + q4][16 cb + a],
-//     the result lined up with X[16 w + 4 q4 + i][16 cb + a] read from LDS;
-//   H H^T (rb = 0): the 16 column steps split over the four waves, summed in wave order.
-template <int RP, bool RESID>
+// The same products with FP32 MFMA (16 x 16 x 4) when X rows are float4-readable
+// (k % 4 == 0, 16-byte aligned X).  Tiles hold RT rows x CT = 4096 / RT columns (RT = 64
+// for more than 32 rows, else 32 or 16, so that short unfoldings keep every wave busy);
+// block (g, rb) covers column chunk g and tile rows RT rb ...  Wave w owns rows
+// 16 (w % WR) .. + 15 and the 64 columns 64 (w / WR) .. + 63 of each tile (WR = RT / 16).
+// Lane l = (a, q4) with a = l % 16, q4 = l / 16; output register i of an MFMA is
+// D[4 q4 + i][a].  Per tile:
+//   X H^T: A = X[row0 + a][col0 + 4 s + q4], B = H[16 n + a][col0 + 4 s + q4], s = 0..15;
+//   W_n H (residual): A = W_n[row0 + a][4 s + q4] (registers), B = H[4 s + q4][col0 + 16 cb + a],
+//     lined up with X[row0 + 4 q4 + i][col0 + 16 cb + a] read from LDS;
+//   H H^T (rb = 0): the CT / 4 column steps split over the four waves.
+// Partials of waves that share rows, and the waves' H H^T parts, are added in wave order.
+template <int RP, bool RESID, int RT>
 __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
   constexpr int NB = (RP + 15) / 16;  // 16-wide rank blocks
   constexpr int RQ = NB * 16;         // ranks padded to a multiple of 16
-  constexpr int HPT = RQ / 4;         // H tile entries per thread
-  __shared__ __attribute__((aligned(16))) float sX[64][68];
-  __shared__ __attribute__((aligned(16))) float sH[RQ][68];
+  constexpr int CT = 4096 / RT;       // tile columns
+  constexpr int WR = RT / 16;         // waves along the rows
+  constexpr int WC = 4 / WR;          // waves along the columns
+  constexpr int HPT = RQ * CT / 256;  // H tile entries per thread
+  constexpr int RPQ = RT / 4;         // tile rows per float4 load instruction group
+  __shared__ __attribute__((aligned(16))) float sX[RT][CT + 4];
+  __shared__ __attribute__((aligned(16))) float sH[RQ][CT + 4];
   __shared__ double sRes[4];
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63, la = ln & 15, lq = ln >> 4;
+  const int wr = wv % WR, wc = wv / WR;
+  const int row0 = 16 * wr, col0 = 64 * wc;
   const int m = b.m, r = b.r;
   const int64_t k = b.k;
   const float* __restrict__ H = init ? b.Hb[0] : b.Hb[b.st->nxt];
   const int g = blockIdx.x, rb = blockIdx.y;
   const int64_t c0 = (int64_t)g * b.chunk, c1 = min(k, c0 + b.chunk);
-  const int mrows = min(64, m - 64 * rb);
+  const int mrows = min(RT, m - RT * rb);
   float wop[RQ / 4];
 #pragma unroll
   for (int s4 = 0; s4 < RQ / 4; ++s4) {
-    const int row = 64 * rb + 16 * wv + la, c = 4 * s4 + lq;
+    const int row = RT * rb + row0 + la, c = 4 * s4 + lq;
     wop[s4] = RESID ? bmask(b.Wn[(int64_t)min(row, m - 1) * r + min(c, r - 1)], row < m && c < r) : 0.f;
   }
   v4f accx[NB];
@@ -314,10 +324,10 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
   auto issue = [&](float4 (&xr)[4], float (&hr)[HPT], int64_t j0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (16 * q < mrows) {
+      if (RPQ * q < mrows) {  // load groups wholly beyond m are skipped
         const int e = tid + 256 * q;
-        const int i = e >> 4, j4 = (e & 15) * 4;
-        const int xi = 64 * rb + i;
+        const int i = e / (CT / 4), j4 = (e % (CT / 4)) * 4;
+        const int xi = RT * rb + i;
         const int64_t gj = j0 + j4;
         const bool ok = xi < m && gj < c1;
         xr[q] = *reinterpret_cast<const float4*>(b.X + (int64_t)min(xi, m - 1) * k + (ok ? gj : c0));
@@ -326,7 +336,7 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
 #pragma unroll
     for (int t = 0; t < HPT; ++t) {
       const int e = tid + 256 * t;
-      const int c = e >> 6, jj = e & 63;
+      const int c = e / CT, jj = e % CT;
       hr[t] = H[(int64_t)min(c, r - 1) * k + min(j0 + jj, c1 - 1)];
     }
   };
@@ -334,28 +344,28 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
-      const int i = e >> 4, j4 = (e & 15) * 4;
-      const bool ok = 16 * q < mrows && 64 * rb + i < m && j0 + j4 < c1;
+      const int i = e / (CT / 4), j4 = (e % (CT / 4)) * 4;
+      const bool ok = RPQ * q < mrows && RT * rb + i < m && j0 + j4 < c1;
       *reinterpret_cast<float4*>(&sX[i][j4]) = ok ? xr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int t = 0; t < HPT; ++t) {
       const int e = tid + 256 * t;
-      const int c = e >> 6, jj = e & 63;
+      const int c = e / CT, jj = e % CT;
       sH[c][jj] = (c < r && j0 + jj < c1) ? hr[t] : 0.f;
     }
   };
   auto compute = [&]() {
 #pragma unroll 4
     for (int s4 = 0; s4 < 16; ++s4) {
-      const float av = sX[16 * wv + la][4 * s4 + lq];
+      const float av = sX[row0 + la][col0 + 4 * s4 + lq];
 #pragma unroll
       for (int n = 0; n < NB; ++n)
-        accx[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sH[16 * n + la][4 * s4 + lq], accx[n], 0, 0, 0);
+        accx[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sH[16 * n + la][col0 + 4 * s4 + lq], accx[n], 0, 0, 0);
     }
     if (rb == 0) {
 #pragma unroll
-      for (int s4 = 4 * wv; s4 < 4 * wv + 4; ++s4) {
+      for (int s4 = wv * (CT / 16); s4 < (wv + 1) * (CT / 16); ++s4) {
         float op[NB];
 #pragma unroll
         for (int n = 0; n < NB; ++n) op[n] = sH[16 * n + la][4 * s4 + lq];
@@ -372,42 +382,55 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
         v4f d = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s4 = 0; s4 < RQ / 4; ++s4)
-          d = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[s4], sH[4 * s4 + lq][16 * cb + la], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[s4], sH[4 * s4 + lq][col0 + 16 * cb + la], d, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double dl = (double)sX[16 * wv + 4 * lq + i][16 * cb + la] - (double)d[i];
+          const double dl = (double)sX[row0 + 4 * lq + i][col0 + 16 * cb + la] - (double)d[i];
           res += dl * dl;  // 0 outside the matrix
         }
       }
     }
   };
   issue(xr0, hr0, c0);
-  if (c0 + 64 < c1) issue(xr1, hr1, c0 + 64);
-  for (int64_t j0 = c0; j0 < c1; j0 += 128) {
+  if (c0 + CT < c1) issue(xr1, hr1, c0 + CT);
+  for (int64_t j0 = c0; j0 < c1; j0 += 2 * CT) {
     __syncthreads();
     store(xr0, hr0, j0);
     __syncthreads();
-    if (j0 + 128 < c1) issue(xr0, hr0, j0 + 128);
+    if (j0 + 2 * CT < c1) issue(xr0, hr0, j0 + 2 * CT);
     compute();
-    if (j0 + 64 < c1) {
+    if (j0 + CT < c1) {
       __syncthreads();
-      store(xr1, hr1, j0 + 64);
+      store(xr1, hr1, j0 + CT);
       __syncthreads();
-      if (j0 + 192 < c1) issue(xr1, hr1, j0 + 192);
+      if (j0 + 3 * CT < c1) issue(xr1, hr1, j0 + 3 * CT);
       compute();
     }
   }
+  // LDS scratch for the wave sums (sX is free now): [4 waves][NB * NB][64 lanes][4]
+  float* sG = &sX[0][0];
   float* dst = b.part + (int64_t)g * b.part_stride;
+  if (WC > 1) {
+    __syncthreads();
 #pragma unroll
-  for (int n = 0; n < NB; ++n)
+    for (int n = 0; n < NB; ++n)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = 64 * rb + 16 * wv + 4 * lq + i, c = 16 * n + la;
-      if (row < m && c < r) dst[(int64_t)row * r + c] = accx[n][i];
-    }
+      for (int i = 0; i < 4; ++i) sG[((wv * NB + n) * 64 + ln) * 4 + i] = accx[n][i];
+    __syncthreads();
+  }
+  if (wc == 0) {
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v = accx[n][i];
+        for (int c2 = 1; c2 < WC; ++c2) v += sG[(((c2 * WR + wr) * NB + n) * 64 + ln) * 4 + i];
+        const int row = RT * rb + row0 + 4 * lq + i, c = 16 * n + la;
+        if (row < m && c < r) dst[(int64_t)row * r + c] = v;
+      }
+  }
   if (rb == 0) {
     __syncthreads();
-    float* sG = &sX[0][0];  // [4 waves][NB * NB][64 lanes][4]: at most 16 KB, within sX
 #pragma unroll
     for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -846,9 +869,17 @@ template <int RP>
 hipError_t bcd_xht(const BcdArgs& b, bool resid, hipStream_t s) {
   const dim3 grid((unsigned)b.G, (unsigned)((b.m + 63) / 64));
   const bool xv = b.k % 4 == 0 && aligned(b.X, 16);
-  if (xv && b.m > 32) {  // MFMA products
-    if (resid) k_bcd_xhtm<RP, true><<<grid, 256, 0, s>>>(b, 0);
-    else k_bcd_xhtm<RP, false><<<grid, 256, 0, s>>>(b, 1);
+  if (xv) {  // MFMA products; tiles of 64, 32 or 16 rows (grid.y is 1 below 64 rows)
+    if (b.m > 32) {
+      if (resid) k_bcd_xhtm<RP, true, 64><<<grid, 256, 0, s>>>(b, 0);
+      else k_bcd_xhtm<RP, false, 64><<<grid, 256, 0, s>>>(b, 1);
+    } else if (b.m > 16) {
+      if (resid) k_bcd_xhtm<RP, true, 32><<<grid, 256, 0, s>>>(b, 0);
+      else k_bcd_xhtm<RP, false, 32><<<grid, 256, 0, s>>>(b, 1);
+    } else {
+      if (resid) k_bcd_xhtm<RP, true, 16><<<grid, 256, 0, s>>>(b, 0);
+      else k_bcd_xhtm<RP, false, 16><<<grid, 256, 0, s>>>(b, 1);
+    }
     NTT_BCD_CHECK();
     return hipSuccess;
   }

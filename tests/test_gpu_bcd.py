@@ -82,6 +82,8 @@ SHAPES = [
     # MFMA products (more than 32 rows, k % 4 == 0) at paddings 16 and 32, ragged last row
     # block
     (96, 1000, 24), (70, 3000, 32), (260, 4096, 16),
+    # MFMA products on 32-row and 16-row tiles (128 and 256 columns), ragged last tile
+    (30, 2000, 28), (14, 5000, 11), (32, 4100, 8),
 ]
 
 
