@@ -106,6 +106,16 @@ typedef struct {
                            have at most 4194240 rows. */
   double bcd_delta;     /* BCD: cap of the extrapolation weights, in [0, 1) (0.9999 is
                            usual; 0 turns extrapolation off) */
+  int64_t stream_cols;  /* 0: A is device memory.  > 0: A is HOST memory (pinned for full
+                           copy speed; it must stay valid until the stream has finished)
+                           and stage 1 is out of core: every pass over X_1 (norm, each MU
+                           iteration, final objective) copies it to the device in column
+                           blocks of stream_cols columns, so only the blocks, W and H_1 are
+                           resident.  The blocks' X H^T and H H^T are added in block order
+                           before the W-update, so the iterates are MU's.  Later stages are
+                           resident as usual.  MU in FP32 with given ranks and a fixed
+                           iteration count only (nmf 0, precision FP32, rank_eps 0, tol 0,
+                           no NTT_RECORD_OBJECTIVE), ntt_decompose only. */
 } ntt_config;
 
 typedef struct {

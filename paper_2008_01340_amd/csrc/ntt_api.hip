@@ -229,6 +229,12 @@ struct ntt_plan_s {
   // BCD (Alg.3): the two other H buffers, W before and candidate, X H^T and H H^T of the
   // kept H, W_n^T W_n, the state block
   size_t off_bh[2] = {0, 0}, off_bwp = 0, off_bwn = 0, off_bxh = 0, off_bhh = 0, off_bgw = 0, off_bst = 0;
+  // stage 1 streamed from host memory (stream_cols > 0): column blocks of kblk columns,
+  // their shapes (full blocks, last block), the staging buffers of X and H, the reduced
+  // products of one block, and per-block sums
+  int64_t kblk = 0, nblk = 0;
+  Stage sst[2];
+  size_t off_xs = 0, off_hs = 0, off_redtmp = 0, off_bsum = 0;
   rocblas_handle rb = nullptr;  // created on first use by the rank rule
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
@@ -308,6 +314,12 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     if (!(cfg->bcd_delta >= 0.0 && cfg->bcd_delta < 1.0))
       return fail(NTT_ERR_INVALID_ARG, "bcd_delta must be in [0, 1)");
   }
+  if (cfg->stream_cols < 0) return fail(NTT_ERR_INVALID_ARG, "stream_cols < 0");
+  const bool streamed = cfg->stream_cols > 0;
+  if (streamed && (bcd || cfg->precision != NTT_PREC_FP32 || eps_mode || cfg->tol != 0.0 ||
+                   (cfg->flags & NTT_RECORD_OBJECTIVE)))
+    return fail(NTT_ERR_INVALID_ARG,
+                "stream_cols: MU in FP32 with given ranks, tol = 0 and no objective trace");
   int64_t total = 1;
   for (int i = 0; i < d; ++i) {
     if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
@@ -426,6 +438,16 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     }
     p->total_iters += cfg->max_iters;
   }
+  if (streamed) {
+    // stage 1 in column blocks: the full blocks' shape and the last block's
+    const int64_t m1 = p->dims[0], k1 = total / p->dims[0];
+    const int64_t kb = std::min<int64_t>(cfg->stream_cols, k1);
+    p->kblk = kb;
+    p->nblk = (k1 + kb - 1) / kb;
+    Stage tt{};
+    plan_stage(1, m1, kb, (int)p->eff[1], p->sst[0], tt);
+    plan_stage(1, m1, k1 - (p->nblk - 1) * kb, (int)p->eff[1], p->sst[1], tt);
+  }
   if (bcd && m_max > 64 * 65535) {
     delete p;
     return fail(NTT_ERR_INVALID_ARG, "BCD: an unfolding has more than 4194240 rows");
@@ -464,6 +486,13 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     p->eigws_size = (size_t)32 << 20;
     p->eigws_size += 4 * gram_max * sizeof(double);
     p->off_eigws = off; off = align_up(off + p->eigws_size, 256);
+  }
+  if (streamed) {
+    const size_t m1 = (size_t)p->dims[0], r1 = (size_t)p->eff[1];
+    p->off_xs = off; off = align_up(off + m1 * (size_t)p->kblk * sizeof(float), 256);
+    p->off_hs = off; off = align_up(off + r1 * (size_t)p->kblk * sizeof(float), 256);
+    p->off_redtmp = off; off = align_up(off + (m1 * r1 + r1 * r1) * sizeof(double), 256);
+    p->off_bsum = off; off = align_up(off + (size_t)p->nblk * sizeof(double), 256);
   }
   if (bcd) {
     p->off_bh[0] = off; off = align_up(off + bh_size * sizeof(float), 256);
@@ -590,6 +619,27 @@ struct NttJob {
   std::vector<double> fhist;
   bool bcd = false;  // the stage runs Alg.3 (BCD) instead of MU
   BcdArgs ba{};
+  bool streamed = false;  // stage 1 with X in host memory, passed over in column blocks
+
+  // column block b of the streamed stage: width, shape, staging copies
+  int64_t blk_w(int64_t b) const { return std::min(p->kblk, st().k - b * p->kblk); }
+  const Stage& blk_stage(int64_t b) const { return b == p->nblk - 1 ? p->sst[1] : p->sst[0]; }
+  float* xs() const { return c.at<float>(p->off_xs); }
+  float* hs() const { return c.at<float>(p->off_hs); }
+  hipError_t stage_in(int64_t b, bool with_h) {
+    const int64_t j0 = b * p->kblk, w = blk_w(b), k = st().k;
+    hipError_t e = hipMemcpy2DAsync(xs(), (size_t)w * 4, A + j0, (size_t)k * 4, (size_t)w * 4,
+                                    (size_t)st().m, hipMemcpyHostToDevice, c.s);
+    if (e != hipSuccess || !with_h) return e;
+    return hipMemcpy2DAsync(hs(), (size_t)w * 4, H + j0, (size_t)k * 4, (size_t)w * 4, (size_t)st().r,
+                            hipMemcpyDeviceToDevice, c.s);
+  }
+  hipError_t stage_out_h(int64_t b) {
+    const int64_t j0 = b * p->kblk, w = blk_w(b), k = st().k;
+    return hipMemcpy2DAsync(H + j0, (size_t)k * 4, hs(), (size_t)w * 4, (size_t)w * 4, (size_t)st().r,
+                            hipMemcpyDeviceToDevice, c.s);
+  }
+  PassArgs blk_args(int64_t b) const { return pass_args(c, blk_stage(b), xs(), hs(), W, (float)p->cfg.eps); }
 
   const Stage& st() const { return p->st[l - 1]; }
   const Stage& es() const { return trans ? p->tst[l - 1] : p->st[l - 1]; }  // as iterated
@@ -610,7 +660,8 @@ struct NttJob {
       for (int i = 0; i < plan->d - 1; ++i) initH[i] = iH[i];
     trace = trace_;
     record = (plan->cfg.flags & NTT_RECORD_OBJECTIVE) && trace_;
-    profile = (plan->cfg.flags & NTT_PROFILE) && want_report && plan->cfg.nmf == NTT_NMF_MU;
+    profile = (plan->cfg.flags & NTT_PROFILE) && want_report && plan->cfg.nmf == NTT_NMF_MU &&
+              plan->cfg.stream_cols == 0;
     want_final = record || want_report || plan->cfg.tol > 0.0;
     l = 1;
     t = 0;
@@ -709,8 +760,19 @@ struct NttJob {
     W = cores[l - 1];
     const int64_t mr = s.m * s.r, rk = (int64_t)s.r * s.k;
     const bool validate = (l == 1) && (cfg.flags & NTT_VALIDATE_INPUT);
-    HIP_TRY(launch_sumsq(X, s.m * s.k, c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
-                         c.scal(l) + SCAL_NX2, q));
+    streamed = (l == 1) && cfg.stream_cols > 0;
+    if (streamed) {  // ||X||^2 (and the input check) over the column blocks
+      double* bsum = c.at<double>(p->off_bsum);
+      for (int64_t b = 0; b < p->nblk; ++b) {
+        HIP_TRY(stage_in(b, false));
+        HIP_TRY(launch_sumsq(xs(), s.m * blk_w(b), c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
+                             bsum + b, q));
+      }
+      HIP_TRY(launch_sum_doubles(bsum, (int)p->nblk, 1.0, c.scal(l) + SCAL_NX2, q));
+    } else {
+      HIP_TRY(launch_sumsq(X, s.m * s.k, c.rpart(), kSumsqBlocks, c.ints(), validate ? 1 : 0,
+                           c.scal(l) + SCAL_NX2, q));
+    }
     if (validate && validate_now) {
       int flag = 0;
       HIP_TRY(hipMemcpyAsync(&flag, c.ints(), sizeof(int), hipMemcpyDeviceToHost, q));
@@ -722,10 +784,10 @@ struct NttJob {
     if (initH[l - 1]) HIP_TRY(launch_copy(H, initH[l - 1], rk, q));
     else HIP_TRY(launch_init_uniform(H, rk, cfg.seed, 2ull * l + 1, q));
     bcd = cfg.nmf == NTT_NMF_BCD;
-    trans = !bcd && s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    trans = !bcd && !streamed && s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     const Stage& e = es();
-    one_wg = !bcd && !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
-    pro = !bcd && s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    one_wg = !bcd && !streamed && !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
+    pro = !bcd && !streamed && s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     pro_done = false;
     const float eps = (float)cfg.eps;
     if (trans) {
@@ -740,7 +802,7 @@ struct NttJob {
       pa = pass_args(c, s, X, H, W, eps);
     }
     pa_bf = pa;
-    bf_iters = (e.bf16 && !bcd) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    bf_iters = (e.bf16 && !bcd && !streamed) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
     if (bf_iters > 0) {
       HIP_TRY(launch_cast_bf16(c.xb(), pa.X, s.m * s.k, q));
       pa_bf.Xb = c.xb();
@@ -884,6 +946,7 @@ struct NttJob {
   // may end the stage early); *stage_done is set when no iterations remain.
   ntt_status iterate(int budget, bool* stage_done) {
     if (bcd) return iterate_bcd(budget, stage_done);
+    if (streamed) return iterate_streamed(budget, stage_done);
     if (trans) return iterate_transposed(budget, stage_done);
     if (pro) return iterate_prologue(budget, stage_done);
     const ntt_config& cfg = p->cfg;
@@ -992,6 +1055,42 @@ struct NttJob {
     return NTT_OK;
   }
 
+  // Stage 1 out of core: per MU iteration, every column block is copied in (X from host
+  // memory, its H columns from H_1), its pass updates H and writes its X H^T, H H^T
+  // partials, which are reduced and added in block order; H goes back; then one
+  // W-update from the sums.
+  ntt_status iterate_streamed(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    hipStream_t q = c.s;
+    const Stage& s = st();
+    const int64_t E = s.m * s.r + (int64_t)s.r * s.r;
+    double* redtmp = c.at<double>(p->off_redtmp);
+    FinArgs fw = fa;
+    fw.rpart = nullptr;
+    fw.trace = nullptr;
+    fw.Wout = nullptr;
+    while (budget > 0 && t < cfg.max_iters) {
+      for (int64_t b = 0; b < p->nblk; ++b) {
+        const Stage& sb = blk_stage(b);
+        HIP_TRY(stage_in(b, true));
+        HIP_TRY(run_pass(q, sb, blk_args(b), true, false));
+        FinArgs fb = fa;
+        fb.part_stride = (int64_t)sb.part_stride;
+        fb.G = sb.G;
+        fb.red = redtmp;
+        HIP_TRY(launch_reduce(fb, q));
+        HIP_TRY(launch_add_doubles(c.red(), redtmp, E, b == 0 ? 1 : 0, q));
+        HIP_TRY(stage_out_h(b));
+      }
+      HIP_TRY(launch_wupdate_red(fw, q));
+      ++t;
+      --budget;
+      final_known = false;
+    }
+    *stage_done = t >= cfg.max_iters;
+    return NTT_OK;
+  }
+
   // The stage's T iterations in prologue mode (no stopping checks), then W_T.
   ntt_status iterate_prologue(int budget, bool* stage_done) {
     const ntt_config& cfg = p->cfg;
@@ -1075,6 +1174,20 @@ struct NttJob {
   ntt_status finish_stage() {
     const ntt_config& cfg = p->cfg;
     if (iters[l - 1] == 0) iters[l - 1] = t;
+    if (streamed) {  // the final objective over the column blocks
+      if (want_final) {
+        double* bsum = c.at<double>(p->off_bsum);
+        for (int64_t b = 0; b < p->nblk; ++b) {
+          const Stage& sb = blk_stage(b);
+          HIP_TRY(stage_in(b, true));
+          HIP_TRY(run_pass(c.s, sb, blk_args(b), false, true));
+          HIP_TRY(launch_resid_sum(c.rpart(), resid_blocks(sb), bsum + b, nullptr, c.s));
+        }
+        HIP_TRY(launch_sum_doubles(bsum, (int)p->nblk, 1.0, c.scal(l) + SCAL_OBJ, c.s));
+        final_known = true;
+      }
+      streamed = false;
+    }
     if (bcd) {  // decision on the last candidate; the kept H into the stage's buffer
       BcdArgs b = ba;
       b.trace = (record && t >= 1) ? trace + trace_off + (t - 1) : nullptr;
@@ -1156,7 +1269,8 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
     for (auto& e : p->stage_ev) HIP_TRY(hipEventCreate(&e));
     p->events_ready = true;
   }
-  const bool profile = (cfg.flags & NTT_PROFILE) && report && cfg.nmf == NTT_NMF_MU;
+  const bool profile = (cfg.flags & NTT_PROFILE) && report && cfg.nmf == NTT_NMF_MU &&
+                       cfg.stream_cols == 0;
   if (profile && (int64_t)p->prof_events.size() < 2 * (int64_t)cfg.max_iters) {
     while (p->prof_events.size() < 2 * (size_t)cfg.max_iters) {
       hipEvent_t e;
@@ -1317,6 +1431,10 @@ extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_
     if (cfgs[i].nmf != NTT_NMF_MU) {
       delete b;
       return fail(NTT_ERR_INVALID_ARG, "batched mode runs MU (nmf = 0)");
+    }
+    if (cfgs[i].stream_cols != 0) {
+      delete b;
+      return fail(NTT_ERR_INVALID_ARG, "batched mode takes device inputs (stream_cols = 0)");
     }
     if (cfgs[i].rank_eps != 0.0) {
       delete b;

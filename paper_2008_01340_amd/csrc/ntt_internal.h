@@ -172,6 +172,10 @@ hipError_t launch_reduce(const FinArgs& f, hipStream_t s);
 // The W-update of launch_finalize alone, from the reduced partials in f.red.
 hipError_t launch_wupdate_red(const FinArgs& f, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s);
+// acc = src (first != 0) or acc += src over n doubles
+hipError_t launch_add_doubles(double* acc, const double* src, int64_t n, int first, hipStream_t s);
+// out[0] = scale * (fixed-order sum of part[0..n))
+hipError_t launch_sum_doubles(const double* part, int n, double scale, double* out, hipStream_t s);
 hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* trace, hipStream_t s);
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
 

@@ -3165,6 +3165,27 @@ hipError_t launch_reduce(const FinArgs& f, hipStream_t s) {
   return hipSuccess;
 }
 
+// acc = src (first) or acc + src, elementwise, FP64: the column blocks of a streamed
+// stage add their reduced products in block order.
+__global__ void k_add_doubles(double* __restrict__ acc, const double* __restrict__ src, int64_t n,
+                              int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] = first ? src[i] : acc[i] + src[i];
+}
+
+hipError_t launch_add_doubles(double* acc, const double* src, int64_t n, int first, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_add_doubles<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(acc, src, n, first);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_sum_doubles(const double* part, int n, double scale, double* out, hipStream_t s) {
+  k_sum_doubles<<<1, 64, 0, s>>>(part, n, scale, out, nullptr);
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_zero_ints<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);

@@ -65,6 +65,7 @@ class NttConfig(C.Structure):
         ("rank_eps", C.c_double),
         ("nmf", C.c_int32),
         ("bcd_delta", C.c_double),
+        ("stream_cols", C.c_int64),
     ]
 
 
@@ -215,9 +216,10 @@ class Plan:
 
     def __init__(self, dims, ranks, max_iters, tol=0.0, check_every=10, eps=1e-12, seed=0,
                  precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, rank_eps=0.0,
-                 nmf="mu", delta=0.9999):
+                 nmf="mu", delta=0.9999, stream_cols=0):
         """``nmf``: "mu" (multiplicative updates) or "bcd" (Alg.3, extrapolation cap
-        ``delta``)."""
+        ``delta``).  ``stream_cols`` > 0: the input is in host memory and stage 1 streams
+        it in column blocks of that many columns."""
         lib = load()
         self.dims = [int(n) for n in dims]
         self.ranks = [int(r) for r in ranks]
@@ -228,7 +230,7 @@ class Plan:
                              C.cast(self._ranks, C.POINTER(C.c_int64)), int(max_iters), float(tol),
                              int(check_every), float(eps), int(seed) & ((1 << 64) - 1),
                              int(precision), int(fp32_tail_iters), int(flags), float(rank_eps),
-                             _NMF[nmf], float(delta))
+                             _NMF[nmf], float(delta), int(stream_cols))
         self.max_iters = int(max_iters)
         self.rank_eps = float(rank_eps)
         self.handle = C.c_void_p()
@@ -324,33 +326,38 @@ def _stream_handle(torch, stream):
 def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10,
               precision=NTT_PREC_FP32, fp32_tail_iters=20, flags=0, init_W=None, init_H=None,
               record_objective=False, plan=None, workspace=None, cores=None, stream=None,
-              want_report=True, rank_eps=0.0, nmf="mu", delta=0.9999):
+              want_report=True, rank_eps=0.0, nmf="mu", delta=0.9999, stream_cols=0,
+              device="cuda:0"):
     """Decompose a float32 CUDA tensor; allocates cores/workspace with torch if not given.
 
     ``nmf="bcd"`` runs Alg.3 (BCD with extrapolation cap ``delta``) instead of MU.
+    ``stream_cols`` > 0: ``A`` is a CPU tensor (pinned for full copy speed) and stage 1
+    streams it to ``device`` in column blocks; the cores come back on ``device``.
 
     With rank_eps > 0 the ranks are chosen by the rule of Alg.2 (``ranks`` are caps);
     the returned cores are views of the (cap-sized) buffers at the chosen ranks."""
     import torch
-    assert A.is_cuda and A.dtype == torch.float32 and A.is_contiguous()
+    assert A.dtype == torch.float32 and A.is_contiguous()
+    assert (not A.is_cuda) if stream_cols > 0 else A.is_cuda
+    dev = torch.device(device) if stream_cols > 0 else A.device
     dims = list(A.shape)
     if record_objective:
         flags |= NTT_RECORD_OBJECTIVE
     if plan is None:
         plan = Plan(dims, ranks, max_iters, tol=tol, check_every=check_every, eps=eps, seed=seed,
                     precision=precision, fp32_tail_iters=fp32_tail_iters, flags=flags,
-                    rank_eps=rank_eps, nmf=nmf, delta=delta)
+                    rank_eps=rank_eps, nmf=nmf, delta=delta, stream_cols=stream_cols)
     if plan.rank_eps > 0.0:
         want_report = True  # the chosen ranks come back in the report
     nbytes, eff, _ = plan.workspace()
     if workspace is None:
-        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=A.device)
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
     if cores is None:
-        cores = [torch.empty((eff[k], dims[k], eff[k + 1]), dtype=torch.float32, device=A.device)
+        cores = [torch.empty((eff[k], dims[k], eff[k + 1]), dtype=torch.float32, device=dev)
                  for k in range(len(dims))]
     trace = None
     if record_objective:
-        trace = torch.zeros(plan.max_iters * (len(dims) - 1), dtype=torch.float64, device=A.device)
+        trace = torch.zeros(plan.max_iters * (len(dims) - 1), dtype=torch.float64, device=dev)
     iw = None if init_W is None else [None if t is None else t.data_ptr() for t in init_W]
     ih = None if init_H is None else [None if t is None else t.data_ptr() for t in init_H]
     rep = ntt_decompose(plan, _stream_handle(torch, stream), workspace.data_ptr(), A.data_ptr(),

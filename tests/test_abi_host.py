@@ -90,6 +90,12 @@ def test_plan_strict_ranks_errors():
     ({"nmf": "bcd", "delta": -0.5}, (4, 5), (1, 2, 1)),
     ({"nmf": "bcd", "delta": float("nan")}, (4, 5), (1, 2, 1)),
     ({"nmf": "bcd"}, (5000000, 2), (1, 1, 1)),  # BCD: more rows than its grid takes
+    ({"stream_cols": -1}, (4, 5), (1, 2, 1)),
+    ({"stream_cols": 64, "precision": 1}, (4, 5), (1, 2, 1)),  # streaming: MU in FP32 only
+    ({"stream_cols": 64, "nmf": "bcd"}, (4, 5), (1, 2, 1)),
+    ({"stream_cols": 64, "rank_eps": 0.1}, (4, 5), (1, 2, 1)),
+    ({"stream_cols": 64, "tol": 1e-3}, (4, 5), (1, 2, 1)),
+    ({"stream_cols": 64, "flags": 4}, (4, 5), (1, 2, 1)),  # no objective trace
 ])
 def test_plan_rejects_invalid_configs(kw, dims, ranks):
     args = {"max_iters": 10}
@@ -186,3 +192,17 @@ def test_bcd_workspace_adds_two_h_buffers():
     mu = ntt.Plan(dims, ranks, 10).workspace()[0]
     bcd = ntt.Plan(dims, ranks, 10, nmf="bcd").workspace()[0]
     assert bcd >= mu + 2 * 8 * 32 * 32 * 4
+
+
+def test_streamed_plan_adds_staging_and_batch_rejects_it(lib):
+    dims, ranks = (32, 32, 32, 32), (1, 8, 8, 8, 1)
+    resident = ntt.Plan(dims, ranks, 10).workspace()[0]
+    streamed = ntt.Plan(dims, ranks, 10, stream_cols=1000).workspace()[0]
+    # staging for a 32 x 1000 block of X and an 8 x 1000 block of H
+    assert streamed >= resident + (32 + 8) * 1000 * 4
+    d, r = ntt._i64([4, 5]), ntt._i64([1, 2, 1])
+    cfg = ntt.NttConfig(2, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)),
+                        ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)), 5, 0.0, 10, 1e-12, 0,
+                        0, 0, 0, 0.0, 0, 0.9999, 64)
+    h = ctypes.c_void_p()
+    assert lib.ntt_batch_plan(1, ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
