@@ -25,7 +25,7 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
-EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "bcd", "batched", "serving")
+EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "bcd", "streamed", "batched", "serving")
 # HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8w<8> on 512
 # workgroups, W-update prologue): rocprofv3 FETCH_SIZE (82,023.8 KiB) and WRITE_SIZE
 # (33,408.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
@@ -213,6 +213,40 @@ def bcd(ntt, S, torch, mu_err, mu_ms):
     progress(f"bcd: {ms:.1f} ms, rel err {err:.4e} (MU {mu_err:.4e}), corrections "
              f"{res.report['corrections']}")
     del A
+    return out
+
+
+def streamed(ntt, S, torch, iters=3, cols=1 << 20):
+    """The out-of-core first stage on the paper's workload: the 256^4 FP32 tensor (17.2 GB)
+    in pinned host memory, stage 1 streamed in blocks of 2^20 columns (1 GB of X each),
+    a few MU iterations per stage; against the same iterations with the tensor resident."""
+    w = S.workload("tt256x4_r10")
+    Ad = _tt_on_gpu(ntt, S, torch, w)
+    Ah = torch.empty(tuple(Ad.shape), dtype=torch.float32, pin_memory=True)
+    Ah.copy_(Ad)
+    torch.cuda.synchronize()
+    progress("streamed: 256^4 tensor in pinned host memory")
+    ranks = w.target_ranks
+    out = {"workload": f"{w.name}: {w.note}; {iters} MU iterations per stage, stage 1 streamed "
+                       f"from pinned host memory in blocks of {cols} columns"}
+    for mode in ("resident", "streamed"):
+        kw = {"stream_cols": cols} if mode == "streamed" else {}
+        A = Ah if mode == "streamed" else Ad
+        plan = ntt.Plan(w.dims, ranks, iters, seed=w.seed, **kw)
+        res = ntt.decompose(A, ranks, iters, plan=plan, want_report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ntt.decompose(A, ranks, iters, plan=plan, cores=res.cores)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        # stage 1 passes over X in both modes: the norm, T iterations, the final objective
+        passes = iters + 2
+        x_bytes = 4.0 * Ad.numel()
+        out[mode] = {"ms": ms, "stage_ms": res.report["ms"], "rel_error": ntt.rel_error(Ad, res.cores),
+                     "stage1_ms_per_x_pass": res.report["ms"][0] / passes,
+                     "stage1_x_gbs": x_bytes * passes / (res.report["ms"][0] * 1e-3) / 1e9}
+        progress(f"streamed: {mode}: {ms:.1f} ms, stage 1 {res.report['ms'][0]:.1f} ms")
+    del Ad, Ah
     return out
 
 
@@ -415,6 +449,9 @@ def main():
         torch.cuda.empty_cache()
     if "bcd" in extras:
         out["bcd"] = bcd(ntt, S, torch, err, ms)
+        torch.cuda.empty_cache()
+    if "streamed" in extras:
+        out["streamed"] = streamed(ntt, S, torch)
         torch.cuda.empty_cache()
     if "batched" in extras:
         out["batched"] = batched(ntt, S, torch)

@@ -233,6 +233,7 @@ class Plan:
                              _NMF[nmf], float(delta), int(stream_cols))
         self.max_iters = int(max_iters)
         self.rank_eps = float(rank_eps)
+        self.stream_cols = int(stream_cols)
         self.handle = C.c_void_p()
         _check(lib.ntt_plan(C.byref(self.cfg), C.byref(self.handle)), "ntt_plan")
 
@@ -338,6 +339,8 @@ def decompose(A, ranks, max_iters, *, eps=1e-12, seed=0, tol=0.0, check_every=10
     the returned cores are views of the (cap-sized) buffers at the chosen ranks."""
     import torch
     assert A.dtype == torch.float32 and A.is_contiguous()
+    if plan is not None:
+        stream_cols = plan.stream_cols
     assert (not A.is_cuda) if stream_cols > 0 else A.is_cuda
     dev = torch.device(device) if stream_cols > 0 else A.device
     dims = list(A.shape)
