@@ -151,10 +151,13 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out);
 ntt_status ntt_plan_workspace(ntt_plan_t plan, size_t* bytes, int64_t* eff_ranks,
                               double* compression);
 
-/* Run the sweep (Alg.2 with MU as the NMF, ranks given).
+/* Run the sweep (Alg.2 with MU or, with nmf = NTT_NMF_BCD, Alg.3 as the NMF; ranks given,
+ * or chosen by the rule of Alg.2 when rank_eps > 0).
  *   workspace : device, >= ntt_plan_workspace bytes, 256-byte aligned; contents on
  *               entry are ignored, on exit unspecified.
- *   A         : device, n_1*...*n_d floats, read only (never written).
+ *   A         : n_1*...*n_d floats, read only (never written): device memory, or host
+ *               memory when the plan's stream_cols > 0 (then copied in column blocks
+ *               during the call; pinned memory gives the full copy rate).
  *   cores     : host array of d device pointers; cores[k] receives G_{k+1} as
  *               r_k x n_{k+1} x r_{k+1} floats (eff ranks).  Must not alias A or the
  *               workspace.

@@ -772,12 +772,15 @@ __global__ __launch_bounds__(256) void k_bcd_h(BcdArgs b) {
 
 // The H step with the rows of W_n^T X split over RG thread groups (short unfoldings, where
 // one thread per column gives too few workgroups): a workgroup takes CT = 256 / RG
-// columns; thread (g, col) sums rows i = g, g + RG, ... of each 64-row chunk; the RG
-// partial sums are added in order in LDS and CT threads apply the step to their column.
+// columns; thread (g, col) sums rows i = g, g + RG, ... of each chunk of W_n (256 rows at
+// RG = 16, so one round of loads for m <= 256; 64 rows at RG = 4, where 16 loads per
+// thread in flight already cover the latency); the RG partial sums are added in order in
+// LDS and CT threads apply the step to their column.
 template <int RP, int RG>
 __global__ __launch_bounds__(256) void k_bcd_hs(BcdArgs b) {
   constexpr int CT = 256 / RG;
-  __shared__ float sW[64][RP + 1];
+  constexpr int CH = RG >= 16 ? 256 : 64;  // rows of W_n per chunk (measured best)
+  __shared__ float sW[CH][RP + 1];
   __shared__ float sG[RP][RP + 1];
   __shared__ float sAcc[RG][CT][RP + 1];
   const int tid = threadIdx.x;
@@ -792,20 +795,21 @@ __global__ __launch_bounds__(256) void k_bcd_hs(BcdArgs b) {
   float acc[RP];
 #pragma unroll
   for (int c = 0; c < RP; ++c) acc[c] = 0.f;
-  for (int i0 = 0; i0 < m; i0 += 64) {
+  for (int i0 = 0; i0 < m; i0 += CH) {
+    // the chunk's X loads go out first, unconditionally: rows past m are clamped and
+    // meet zero rows of sW
+    constexpr int NU = CH / RG;
+    float xs[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) xs[u] = b.X[(int64_t)min(i0 + grp + u * RG, m - 1) * k + jc];
     __syncthreads();
-    for (int e = tid; e < 64 * RP; e += 256) {
+    for (int e = tid; e < CH * RP; e += 256) {
       const int i = e / RP, c = e % RP;
       sW[i][c] = bmask(b.Wn[(int64_t)min(i0 + i, m - 1) * r + min(c, r - 1)], i0 + i < m && c < r);
     }
     __syncthreads();
-    // all 64 / RG rows of the chunk in flight at once (sW is zero beyond m)
-    float xs[64 / RG];
 #pragma unroll
-    for (int u = 0; u < 64 / RG; ++u)
-      xs[u] = b.X[(int64_t)min(i0 + grp + u * RG, m - 1) * k + jc];
-#pragma unroll
-    for (int u = 0; u < 64 / RG; ++u) {
+    for (int u = 0; u < NU; ++u) {
       const float x = act ? xs[u] : 0.f;
 #pragma unroll
       for (int c = 0; c < RP; ++c) acc[c] = fmaf(sW[grp + u * RG][c], x, acc[c]);
