@@ -13,6 +13,10 @@
  * MU, H first then W, with eps added to the denominators and a clamp at zero:
  *     H <- max(0, H .* (W^T X) ./ ((W^T W) H + eps))
  *     W <- max(0, W .* (X H^T) ./ (W (H H^T) + eps))
+ * Options of ntt_config: the BCD NMF of Alg.3 instead of MU (nmf), the ranks chosen per
+ * stage by the singular-value rule of Alg.2 (rank_eps), a BF16 copy of X for the
+ * products (precision), and an input kept in host memory and streamed through the
+ * device in column blocks (stream_cols).
  *
  * Conventions for every entry point
  *   - Arrays are row-major (C order, last index fastest) float32 unless stated.
@@ -77,7 +81,7 @@ typedef struct {
   int32_t d;            /* number of modes, 2..NTT_MAX_DIMS */
   const int64_t* dims;  /* host, d entries n_1..n_d, each >= 1 */
   const int64_t* ranks; /* host, d+1 entries r_0..r_d with r_0 = r_d = 1, inner >= 1 */
-  int32_t max_iters;    /* MU iterations per stage (>= 0) */
+  int32_t max_iters;    /* NMF iterations per stage (>= 0) */
   double tol;           /* 0: run exactly max_iters.  > 0: stop early at t % check_every == 0
                            when sqrt(2 f_t)/||X_l|| <= tol or f_{t-K} - f_t <= tol f_{t-K},
                            f_t = 1/2 ||X_l - W_t H_t||_F^2 evaluated explicitly in FP64 */

@@ -1,9 +1,10 @@
 // ntt_api.hip -- plan, workspace layout, stage executor and the C ABI of ntt.h.
 //
-// The executor runs the sweep of Alg.2 with MU as the NMF (ranks given, not chosen by
-// the SVD threshold rule).  Stage l factors X_l, an (r_{l-1} n_l) x (n_{l+1}...n_d)
-// row-major matrix that is a zero-copy view of the input (l = 1) or of the previous
-// stage's H.  W is updated in place inside the caller's core buffer l (its C-order
+// The executor runs the sweep of Alg.2 with MU as the NMF, or the BCD of Alg.3
+// (ntt_bcd.hip); the ranks are given, or chosen per stage by the singular-value rule of
+// Alg.2.  Stage l factors X_l, an (r_{l-1} n_l) x (n_{l+1}...n_d) row-major matrix that
+// is a zero-copy view of the input (l = 1) or of the previous stage's H; with host input
+// (stream_cols > 0) stage 1 reads X_1 in column blocks copied from host memory.  W is updated in place inside the caller's core buffer l (its C-order
 // layout r_{l-1} x n_l x r_l is exactly W, m x r_l); H lives in one of two workspace
 // buffers (ping-pong, so X_l and H_l never alias), except that the last stage's H is
 // written straight into core d.
