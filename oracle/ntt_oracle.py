@@ -254,7 +254,8 @@ def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
     Returns a dict with the kept pair W, H, ``corrections`` (how many iterations were
     dropped), ``kept`` (per iteration: True when kept), ``objective`` (the objective of
     each iteration's candidate pair, kept or not), ``t`` and ``w`` (the extrapolation
-    sequence after each iteration), and ``snaps[t] = (W, H)`` after t iterations.
+    sequence after each iteration), ``wW`` and ``wH`` (the weights the next iteration
+    extrapolates with), and ``snaps[t] = (W, H)`` after t iterations.
     """
     X = np.asarray(X, dtype=np.float64)
     W, H = bcd_normalise(X, W0, H0)
@@ -267,7 +268,7 @@ def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
     snaps = {}
     if 0 in snapshots:
         snaps[0] = (W.copy(), H.copy())
-    kept, f_hist, t_hist, w_hist = [], [], [], []
+    kept, f_hist, t_hist, w_hist, ww_hist, wh_hist = [], [], [], [], [], []
     for it in range(1, iters + 1):
         Wn, _ = bcd_step_W(XHt, HHt, Wm)
         WtW = Wn.T @ Wn
@@ -277,7 +278,7 @@ def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
         if f >= obj:  # correction (B6)
             kept.append(False)
             Wm, Hm = W, H
-            w = 0.0
+            w = wW = wH = 0.0
         else:  # extrapolation (B7)
             kept.append(True)
             tp = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * t * t))
@@ -294,10 +295,13 @@ def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
             t, obj = tp, f
         t_hist.append(t)
         w_hist.append(w)
+        ww_hist.append(wW)
+        wh_hist.append(wH)
         if it in snapshots:
             snaps[it] = (W.copy(), H.copy())
     return {"W": W, "H": H, "iters": iters, "corrections": kept.count(False), "kept": kept,
             "objective": np.array(f_hist), "t": np.array(t_hist), "w": np.array(w_hist),
+            "wW": np.array(ww_hist), "wH": np.array(wh_hist),
             "snaps": snaps, "norm_x": math.sqrt(float(np.sum(X * X)))}
 
 

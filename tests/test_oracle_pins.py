@@ -491,3 +491,34 @@ def test_bcd_sweep_reaches_lower_error_than_mu():
         res = O.ntt_decompose(A, (1, 4, 4, 1), 200, nmf=nmf)
         e[nmf] = O.rel_error(A, O.tt_reconstruct(res["cores"]))
     assert e["bcd"] < 0.5 * e["mu"]
+
+
+def test_bcd_extrapolation_weights_are_capped_by_the_gram_norm_ratios():
+    # with a small delta the caps bind: every applied weight is min(w, delta sqrt(ratio))
+    # with the ratio of the partner block's Gram norms at the two last kept iterates,
+    # recomputed here from the snapshots; and each next candidate is the block steps
+    # from the points extrapolated with those weights
+    rng = _rng(46)
+    X = rng.random((25, 40))
+    W0, H0 = rng.random((25, 4)), rng.random((4, 40))
+    T, delta = 12, 0.1
+    res = O.bcd_nmf(X, W0, H0, T, delta=delta, snapshots=tuple(range(T + 1)))
+    assert all(res["kept"])
+    fro = lambda M: math.sqrt(float(np.sum(M * M)))
+    binding = 0
+    for it in range(2, T + 1):  # weights chosen after iteration it (iterates it-1 -> it)
+        Wa, Ha = res["snaps"][it - 1]
+        Wb, Hb = res["snaps"][it]
+        w = res["w"][it - 1]
+        capW = delta * math.sqrt(fro(Ha @ Ha.T) / fro(Hb @ Hb.T))
+        capH = delta * math.sqrt(fro(Wa.T @ Wa) / fro(Wb.T @ Wb))
+        assert res["wW"][it - 1] == pytest.approx(min(w, capW), rel=1e-12)
+        assert res["wH"][it - 1] == pytest.approx(min(w, capH), rel=1e-12)
+        binding += (capW < w) + (capH < w)
+        if it < T:  # the candidate of iteration it + 1 starts from the extrapolated points
+            Wm = Wb + res["wW"][it - 1] * (Wb - Wa)
+            Hm = Hb + res["wH"][it - 1] * (Hb - Ha)
+            Wn, _ = O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wm)
+            Hn, _ = O.bcd_step_H(Wn.T @ X, Wn.T @ Wn, Hm)
+            assert res["objective"][it] == pytest.approx(_f(X, Wn, Hn), rel=1e-12)
+    assert binding > 0
