@@ -377,6 +377,9 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
       }
     }
     if (RESID) {
+      // the lane's 16 squared residuals of the tile in FP32 (each difference carries the
+      // rounding of the FP32 product d already), their sum added to the FP64 total
+      float tsum = 0.f;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
         v4f d = v4f{0.f, 0.f, 0.f, 0.f};
@@ -385,10 +388,11 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[s4], sH[4 * s4 + lq][col0 + 16 * cb + la], d, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double dl = (double)sX[row0 + 4 * lq + i][col0 + 16 * cb + la] - (double)d[i];
-          res += dl * dl;  // 0 outside the matrix
+          const float dl = sX[row0 + 4 * lq + i][col0 + 16 * cb + la] - d[i];
+          tsum = fmaf(dl, dl, tsum);  // 0 outside the matrix
         }
       }
+      res += (double)tsum;
     }
   };
   issue(xr0, hr0, c0);
