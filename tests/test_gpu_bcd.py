@@ -238,3 +238,42 @@ def test_bcd_full_size_first_unfolding_per_iterate():
         eH = rel(host(g.cores[1]).reshape(8, -1), Ho)
         say(f"  t={t}: W {eW:.2e} H {eH:.2e}")
         assert eW <= TOL and eH <= TOL
+
+
+def test_bcd_zero_input_drops_every_iteration():
+    say("case: BCD on an all-zero 20 x 30 matrix, rank 3, T=5")
+    X = np.zeros((20, 30), dtype=np.float32)
+    W0, H0 = O.init_factors(1, 1, 20, 3, 30)
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, 5)
+    res = ntt.decompose(dev(X), (1, 3, 1), 5, init_W=[dev(W0)], init_H=[dev(H0)], nmf="bcd")
+    assert ref["corrections"] == 5 == res.report["corrections"][0]
+    for c in res.cores:
+        assert float(c.abs().max()) == 0.0
+    assert res.report["objective"][0] == 0.0
+
+
+def test_bcd_zero_rows_and_columns_match_oracle():
+    say("case: BCD 30 x 52 with a zero row and two zero columns, rank 4")
+    rng = np.random.default_rng(3)
+    X = rng.random((30, 52)).astype(np.float32)
+    X[4, :] = 0.0
+    X[:, 7] = 0.0
+    X[:, 20] = 0.0
+    W0, H0 = O.init_factors(2, 1, 30, 4, 52)
+    ref = O.bcd_nmf(X.astype(np.float64), W0, H0, 30, snapshots=(1, 5, 30))
+    assert np.all(margins(ref) > MARGIN)
+    for t in (1, 5, 30):
+        g = ntt.decompose(dev(X), (1, 4, 1), t, init_W=[dev(W0)], init_H=[dev(H0)], nmf="bcd")
+        Wo, Ho = ref["snaps"][t]
+        Wg, Hg = host(g.cores[0]).reshape(30, 4), host(g.cores[1]).reshape(4, 52)
+        assert rel(Wg, Wo) <= TOL and rel(Hg, Ho) <= TOL, t
+        assert Wg.min() >= 0 and Hg.min() >= 0
+
+
+def test_bcd_rejects_negative_input():
+    say("case: BCD with a negative entry and the input check")
+    X = np.ones((10, 40), dtype=np.float32)
+    X[3, 17] = -1.0
+    with pytest.raises(ntt.NttError) as e:
+        ntt.decompose(dev(X), (1, 2, 1), 5, nmf="bcd", flags=ntt.NTT_VALIDATE_INPUT)
+    assert e.value.status == ntt.NTT_ERR_NEGATIVE_INPUT
