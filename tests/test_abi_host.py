@@ -206,3 +206,29 @@ def test_streamed_plan_adds_staging_and_batch_rejects_it(lib):
                         0, 0, 0, 0.0, 0, 0.9999, 64)
     h = ctypes.c_void_p()
     assert lib.ntt_batch_plan(1, ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    # the binding's ctypes structs against sizeof/offsetof compiled from include/ntt.h
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "ntt.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ntt_config), sizeof(ntt_report),\n'
+        "         offsetof(ntt_config, nmf), offsetof(ntt_config, bcd_delta),\n"
+        "         offsetof(ntt_config, stream_cols), offsetof(ntt_report, corrections));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I" + inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(ntt.NttConfig), ctypes.sizeof(ntt.NttReport),
+            ntt.NttConfig.nmf.offset, ntt.NttConfig.bcd_delta.offset,
+            ntt.NttConfig.stream_cols.offset, ntt.NttReport.corrections.offset]
+    assert got == want
