@@ -235,7 +235,7 @@ struct ntt_plan_s {
   // products of one block, and per-block sums
   int64_t kblk = 0, nblk = 0;
   Stage sst[2];
-  size_t off_xs = 0, off_hs = 0, off_redtmp = 0, off_bsum = 0;
+  size_t off_xs = 0, off_hs = 0, off_redtmp = 0, off_bsum = 0, off_gram2 = 0;
   rocblas_handle rb = nullptr;  // created on first use by the rank rule
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
@@ -317,10 +317,9 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   }
   if (cfg->stream_cols < 0) return fail(NTT_ERR_INVALID_ARG, "stream_cols < 0");
   const bool streamed = cfg->stream_cols > 0;
-  if (streamed && (bcd || cfg->precision != NTT_PREC_FP32 || eps_mode || cfg->tol != 0.0 ||
+  if (streamed && (bcd || cfg->precision != NTT_PREC_FP32 || cfg->tol != 0.0 ||
                    (cfg->flags & NTT_RECORD_OBJECTIVE)))
-    return fail(NTT_ERR_INVALID_ARG,
-                "stream_cols: MU in FP32 with given ranks, tol = 0 and no objective trace");
+    return fail(NTT_ERR_INVALID_ARG, "stream_cols: MU in FP32, tol = 0 and no objective trace");
   int64_t total = 1;
   for (int i = 0; i < d; ++i) {
     if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
@@ -446,8 +445,26 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     p->kblk = kb;
     p->nblk = (k1 + kb - 1) / kb;
     Stage tt{};
+    const int64_t last = k1 - (p->nblk - 1) * kb;
     plan_stage(1, m1, kb, (int)p->eff[1], p->sst[0], tt);
-    plan_stage(1, m1, k1 - (p->nblk - 1) * kb, (int)p->eff[1], p->sst[1], tt);
+    plan_stage(1, m1, last, (int)p->eff[1], p->sst[1], tt);
+    if (eps_mode) {
+      // the rule may choose any r_1 up to the cap: the block stages at every rank; the
+      // Gram of X_1 is the n_1 x n_1 sum of the blocks' row Grams
+      for (int64_t r_ = 1; r_ < p->eff[1]; ++r_) {
+        Stage s2{};
+        plan_stage(1, m1, kb, (int)r_, s2, tt);
+        plan_stage(1, m1, last, (int)r_, s2, tt);
+      }
+      for (int64_t w : {kb, last}) {
+        int ns = 1;
+        size_t pd = 0;
+        gram_rows_plan(m1, w, &ns, &pd);
+        grp_max = std::max(grp_max, pd);
+      }
+      gram_max = std::max(gram_max, (size_t)m1 * (size_t)m1);
+      n_max = std::max(n_max, m1);
+    }
   }
   if (bcd && m_max > 64 * 65535) {
     delete p;
@@ -487,6 +504,10 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     p->eigws_size = (size_t)32 << 20;
     p->eigws_size += 4 * gram_max * sizeof(double);
     p->off_eigws = off; off = align_up(off + p->eigws_size, 256);
+    if (streamed) {  // the Gram of one column block of X_1
+      p->off_gram2 = off;
+      off = align_up(off + (size_t)p->dims[0] * (size_t)p->dims[0] * sizeof(double), 256);
+    }
   }
   if (streamed) {
     const size_t m1 = (size_t)p->dims[0], r1 = (size_t)p->eff[1];
@@ -686,9 +707,20 @@ struct NttJob {
     const int64_t m = p->eff[l - 1] * p->dims[l - 1];
     int64_t k = 1;
     for (int j = l; j < d(); ++j) k *= p->dims[j];
-    const float* Xl = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
-    HIP_TRY(launch_gram(Xl, m, k, c.grp(), c.gram(), q));
-    const int n = (int)std::min(m, k);
+    const bool blocks = l == 1 && cfg.stream_cols > 0;  // X_1 in host memory
+    int n = (int)std::min(m, k);
+    if (blocks) {  // the m x m Gram as the sum of the column blocks' row Grams
+      double* g2 = c.at<double>(p->off_gram2);
+      for (int64_t b = 0; b < p->nblk; ++b) {
+        HIP_TRY(stage_in(b, false));
+        HIP_TRY(launch_gram_rows(xs(), m, blk_w(b), c.grp(), g2, q));
+        HIP_TRY(launch_add_doubles(c.gram(), g2, m * m, b == 0 ? 1 : 0, q));
+      }
+      n = (int)m;
+    } else {
+      const float* Xl = (l == 1) ? A : reinterpret_cast<const float*>(c.ws + p->off_h[(l - 2) & 1]);
+      HIP_TRY(launch_gram(Xl, m, k, c.grp(), c.gram(), q));
+    }
     if (!p->rb && rocblas_create_handle(&p->rb) != rocblas_status_success) {
       p->rb = nullptr;
       return fail(NTT_ERR_DEVICE, "rocblas_create_handle failed");
@@ -733,6 +765,11 @@ struct NttJob {
     const int64_t r = std::min(std::min(p->cap[l], rk), std::min(m, k));
     p->eff[l] = r;
     stage_shape(cfg, m, k, (int)r, p->st[l - 1], p->tst[l - 1]);
+    if (blocks) {  // the column blocks' shapes at the chosen rank
+      Stage tt{};
+      stage_shape(cfg, m, p->kblk, (int)r, p->sst[0], tt);
+      stage_shape(cfg, m, k - (p->nblk - 1) * p->kblk, (int)r, p->sst[1], tt);
+    }
     p->compression = compression_of(d(), p->dims, p->eff);
     // graphs captured for an earlier shape of this stage
     for (size_t i = 0; i < p->graphs.size();) {

@@ -186,5 +186,9 @@ hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
 // partial size in doubles for an m x k matrix.
 void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles);
 hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s);
+// The m x m Gram X X^T whatever the shape (a column block of a streamed unfolding; the
+// blocks' Grams are added by the caller); the split and partial size for it.
+void gram_rows_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles);
+hipError_t launch_gram_rows(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s);
 
 }  // namespace ntt

@@ -3222,18 +3222,28 @@ void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
   *part_doubles = (size_t)npairs * (size_t)ns * 4096;
 }
 
-hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s) {
+void gram_rows_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
+  const int64_t nb = (m + 63) / 64;
+  const int64_t npairs = nb * (nb + 1) / 2;
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024 / npairs, (k + 1023) / 1024));
+  *nsplit = (int)ns;
+  *part_doubles = (size_t)npairs * (size_t)ns * 4096;
+}
+
+static hipError_t launch_gram_impl(const float* X, int64_t m, int64_t k, bool rows, double* part,
+                                   double* G, hipStream_t s) {
   if (m < 1 || k < 1) return hipErrorInvalidValue;
   GramArgs g{};
   g.X = X;
   g.m = m;
   g.k = k;
-  g.trans = m > k ? 1 : 0;
-  g.n = (int)std::min(m, k);
+  g.trans = (!rows && m > k) ? 1 : 0;
+  g.n = (int)(g.trans ? k : m);
   g.nb = (g.n + 63) / 64;
   size_t pd = 0;
-  gram_plan(m, k, &g.nsplit, &pd);
-  const int64_t L = std::max(m, k);
+  if (rows) gram_rows_plan(m, k, &g.nsplit, &pd);
+  else gram_plan(m, k, &g.nsplit, &pd);
+  const int64_t L = g.trans ? m : k;
   g.chunk = ((L + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
   g.part = part;
   g.G = G;
@@ -3243,6 +3253,14 @@ hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, doubl
   k_gram_reduce<<<(unsigned)npairs, 256, 0, s>>>(g);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s) {
+  return launch_gram_impl(X, m, k, false, part, G, s);
+}
+
+hipError_t launch_gram_rows(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s) {
+  return launch_gram_impl(X, m, k, true, part, G, s);
 }
 
 }  // namespace ntt

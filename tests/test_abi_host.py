@@ -93,7 +93,7 @@ def test_plan_strict_ranks_errors():
     ({"stream_cols": -1}, (4, 5), (1, 2, 1)),
     ({"stream_cols": 64, "precision": 1}, (4, 5), (1, 2, 1)),  # streaming: MU in FP32 only
     ({"stream_cols": 64, "nmf": "bcd"}, (4, 5), (1, 2, 1)),
-    ({"stream_cols": 64, "rank_eps": 0.1}, (4, 5), (1, 2, 1)),
+    ({"stream_cols": 64, "rank_eps": 0.1}, (3000, 4), (1, 2, 1)),  # streamed rule: n_1 > 2048
     ({"stream_cols": 64, "tol": 1e-3}, (4, 5), (1, 2, 1)),
     ({"stream_cols": 64, "flags": 4}, (4, 5), (1, 2, 1)),  # no objective trace
 ])

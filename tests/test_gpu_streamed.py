@@ -125,3 +125,19 @@ def test_streamed_full_size_32pow5_equals_resident_sweep():
     e_st, e_rs = ntt.rel_error(Ad, st.cores), ntt.rel_error(Ad, rs.cores)
     say(f"  rel err streamed {e_st:.6e} resident {e_rs:.6e}")
     assert e_st == pytest.approx(e_rs, rel=1e-5)
+
+
+def test_streamed_rank_rule_matches_resident_and_oracle():
+    """The rank rule of Alg.2 on a streamed first stage: the Gram of X_1 is summed over the
+    column blocks; the ranks and cores equal the resident run's."""
+    say("case: streamed sweep with the rank rule, 24 x 20 x 30 x 16, caps 8, rank_eps 0.02")
+    dims, caps = (24, 20, 30, 16), (1, 8, 8, 8, 1)
+    A = S.noisy_tensor(dims, (1, 6, 5, 4, 1), seed=7, noise="mult", level=0.01)
+    ref = O.ntt_decompose(A, caps, 40, seed=3, rank_eps=0.02)
+    st = ntt.decompose(pinned(A), caps, 40, seed=3, rank_eps=0.02, stream_cols=700)
+    rs = ntt.decompose(dev(A), caps, 40, seed=3, rank_eps=0.02)
+    say(f"  ranks streamed {st.report['eff_ranks']} resident {rs.report['eff_ranks']} oracle {ref['ranks']}")
+    assert list(st.report["eff_ranks"]) == list(rs.report["eff_ranks"]) == list(ref["ranks"])
+    for l, (cs, cr, co) in enumerate(zip(st.cores, rs.cores, ref["cores"])):
+        assert rel(host(cs), host(cr)) <= TOL, l
+        assert rel(host(cs), co) <= TOL, l
