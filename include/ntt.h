@@ -117,9 +117,11 @@ typedef struct {
                            blocks of stream_cols columns, so only the blocks, W and H_1 are
                            resident.  The blocks' X H^T and H H^T are added in block order
                            before the W-update, so the iterates are MU's.  Later stages are
-                           resident as usual.  MU in FP32 with given ranks and a fixed
-                           iteration count only (nmf 0, precision FP32, rank_eps 0, tol 0,
-                           no NTT_RECORD_OBJECTIVE), ntt_decompose only. */
+                           resident as usual.  With rank_eps > 0 the rank rule takes the
+                           n_1 x n_1 Gram of X_1 as the sum of the blocks' Grams (n_1 <=
+                           2048).  MU in FP32 with a fixed iteration count only (nmf 0,
+                           precision FP32, tol 0, no NTT_RECORD_OBJECTIVE), ntt_decompose
+                           only. */
 } ntt_config;
 
 typedef struct {
