@@ -246,6 +246,19 @@ def streamed(ntt, S, torch, iters=3, cols=1 << 20):
                      "stage1_ms_per_x_pass": res.report["ms"][0] / passes,
                      "stage1_x_gbs": x_bytes * passes / (res.report["ms"][0] * 1e-3) / 1e9}
         progress(f"streamed: {mode}: {ms:.1f} ms, stage 1 {res.report['ms'][0]:.1f} ms")
+    # the paper's large-tensor workflow: ranks chosen by the rule of Alg.2 while X stays in
+    # host memory (caps 8, so that every unfolding's shorter side is at most 2048;
+    # threshold 0.01)
+    caps = (1, 8, 8, 8, 1)
+    plan = ntt.Plan(w.dims, caps, iters, seed=w.seed, stream_cols=cols, rank_eps=0.01)
+    t0 = time.perf_counter()
+    res = ntt.decompose(Ah, caps, iters, plan=plan)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out["streamed_rank_rule"] = {"rank_eps": 0.01, "caps": list(caps), "ranks": res.ranks, "ms": ms,
+                                 "stage_ms": res.report["ms"], "rel_error": ntt.rel_error(Ad, res.cores),
+                                 "compression": res.report["compression_ratio"]}
+    progress(f"streamed: rank rule: ranks {res.ranks}, {ms:.1f} ms")
     del Ad, Ah
     return out
 
