@@ -102,8 +102,9 @@ typedef struct {
                            compactly at the chosen ranks into its buffer (sized by the
                            caps).  ntt_decompose only (batched and server plans: 0). */
   int32_t nmf;          /* ntt_nmf (0: MU).  NTT_NMF_BCD runs exactly max_iters iterations
-                           per stage (tol must be 0), in FP32 (precision NTT_PREC_FP32),
-                           ntt_decompose only; it ignores eps and NTT_PROFILE, and with
+                           per stage (tol must be 0), in FP32 (precision NTT_PREC_FP32), in
+                           ntt_decompose and ntt_decompose_batch (not the server); it
+                           ignores eps and NTT_PROFILE, and with
                            NTT_RECORD_OBJECTIVE stores the objective of every iteration's
                            candidate pair (kept or dropped, FP64 residual).  Its workspace
                            adds two r_l x (n_{l+1}..n_d) buffers per stage; unfoldings may

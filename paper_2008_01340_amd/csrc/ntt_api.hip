@@ -1466,10 +1466,6 @@ extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_
       delete b;
       return fail(NTT_ERR_INVALID_ARG, "batched mode takes no RECORD/PROFILE/VALIDATE flags");
     }
-    if (cfgs[i].nmf != NTT_NMF_MU) {
-      delete b;
-      return fail(NTT_ERR_INVALID_ARG, "batched mode runs MU (nmf = 0)");
-    }
     if (cfgs[i].stream_cols != 0) {
       delete b;
       return fail(NTT_ERR_INVALID_ARG, "batched mode takes device inputs (stream_cols = 0)");

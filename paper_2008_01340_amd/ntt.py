@@ -399,8 +399,8 @@ class Batch:
     """Owns an ntt_batch_t built from one config per problem."""
 
     def __init__(self, problems, max_iters, eps=1e-12, precision=NTT_PREC_FP32,
-                 fp32_tail_iters=20, tol=0.0, check_every=10):
-        """problems: list of (dims, ranks, seed)."""
+                 fp32_tail_iters=20, tol=0.0, check_every=10, nmf="mu", delta=0.9999):
+        """problems: list of (dims, ranks, seed); ``nmf``: "mu" or "bcd" for all of them."""
         lib = load()
         self.problems = [(list(map(int, dm)), list(map(int, rk)), int(sd)) for dm, rk, sd in problems]
         self._keep = []
@@ -410,7 +410,8 @@ class Batch:
             self._keep += [a, b]
             cfgs[i] = NttConfig(len(dm), C.cast(a, C.POINTER(C.c_int64)), C.cast(b, C.POINTER(C.c_int64)),
                                 int(max_iters), float(tol), int(check_every), float(eps),
-                                sd & ((1 << 64) - 1), int(precision), int(fp32_tail_iters), 0)
+                                sd & ((1 << 64) - 1), int(precision), int(fp32_tail_iters), 0,
+                                0.0, _NMF[nmf], float(delta))
         self.handle = C.c_void_p()
         _check(lib.ntt_batch_plan(len(self.problems), cfgs, C.byref(self.handle)), "ntt_batch_plan")
         nbytes = C.c_size_t()
@@ -460,12 +461,13 @@ def ntt_decompose_batch(batch: Batch, stream: int, workspace: int, A_ptrs, core_
 
 def decompose_batch(tensors, ranks_list, max_iters, seeds, *, eps=1e-12, precision=NTT_PREC_FP32,
                     fp32_tail_iters=20, batch=None, workspace=None, cores=None, stream=None,
-                    want_reports=True):
+                    want_reports=True, nmf="mu", delta=0.9999):
     """Decompose a list of float32 CUDA tensors in one batched call."""
     import torch
     if batch is None:
         batch = Batch([(list(t.shape), rk, sd) for t, rk, sd in zip(tensors, ranks_list, seeds)],
-                      max_iters, eps=eps, precision=precision, fp32_tail_iters=fp32_tail_iters)
+                      max_iters, eps=eps, precision=precision, fp32_tail_iters=fp32_tail_iters,
+                      nmf=nmf, delta=delta)
     dev = tensors[0].device
     if workspace is None:
         workspace = torch.empty(max(batch.workspace_bytes, 256), dtype=torch.uint8, device=dev)

@@ -175,7 +175,7 @@ def test_batch_plan_validation_and_workspace():
     assert lib.ntt_batch_plan(0, None, None) == ntt.NTT_ERR_INVALID_ARG
 
 
-def test_unknown_nmf_and_batched_bcd_are_rejected(lib):
+def test_unknown_nmf_is_rejected_and_batched_bcd_is_planned(lib):
     dims, ranks = ntt._i64([4, 5]), ntt._i64([1, 2, 1])
     cfg = ntt.NttConfig(2, ctypes.cast(dims, ctypes.POINTER(ctypes.c_int64)),
                         ctypes.cast(ranks, ctypes.POINTER(ctypes.c_int64)), 5, 0.0, 10, 1e-12, 0,
@@ -183,8 +183,9 @@ def test_unknown_nmf_and_batched_bcd_are_rejected(lib):
     h = ctypes.c_void_p()
     assert lib.ntt_plan(ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
     assert "nmf" in lib.ntt_last_error().decode()
-    cfg.nmf = ntt.NTT_NMF_BCD
-    assert lib.ntt_batch_plan(1, ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_ERR_INVALID_ARG
+    cfg.nmf = ntt.NTT_NMF_BCD  # batched mode takes BCD problems
+    assert lib.ntt_batch_plan(1, ctypes.byref(cfg), ctypes.byref(h)) == ntt.NTT_OK
+    lib.ntt_batch_destroy(h)
 
 
 def test_bcd_workspace_adds_two_h_buffers():

@@ -277,3 +277,19 @@ def test_bcd_rejects_negative_input():
     with pytest.raises(ntt.NttError) as e:
         ntt.decompose(dev(X), (1, 2, 1), 5, nmf="bcd", flags=ntt.NTT_VALIDATE_INPUT)
     assert e.value.status == ntt.NTT_ERR_NEGATIVE_INPUT
+
+
+def test_bcd_batched_results_equal_standalone_results_bitwise():
+    say("case: batch of 5 uneven problems with BCD vs ntt_decompose one by one")
+    probs = [((6, 7, 5), (1, 3, 4, 1), 11), ((16, 16, 16), (1, 4, 4, 1), 1),
+             ((9, 20, 8, 6), (1, 5, 6, 3, 1), 5), ((30, 40, 12), (1, 12, 9, 1), 8),
+             ((64, 33, 50), (1, 10, 12, 1), 3)]
+    tensors = [dev(S.contract_cores(S.random_cores(d, r, seed=s))) for d, r, s in probs]
+    T = 60
+    cores, reps, _ = ntt.decompose_batch(tensors, [r for _, r, _ in probs], T,
+                                         [s for _, _, s in probs], nmf="bcd")
+    for (d, r, s), A, cb, rb in zip(probs, tensors, cores, reps):
+        one = ntt.decompose(A, r, T, seed=s, nmf="bcd")
+        for x, y in zip(cb, one.cores):
+            assert torch.equal(x, y), (d, r)
+        assert rb["corrections"] == one.report["corrections"]
