@@ -103,7 +103,7 @@ typedef struct {
                            caps).  ntt_decompose only (batched and server plans: 0). */
   int32_t nmf;          /* ntt_nmf (0: MU).  NTT_NMF_BCD runs exactly max_iters iterations
                            per stage (tol must be 0), in FP32 (precision NTT_PREC_FP32), in
-                           ntt_decompose and ntt_decompose_batch (not the server); it
+                           ntt_decompose, ntt_decompose_batch and server requests; it
                            ignores eps and NTT_PROFILE, and with
                            NTT_RECORD_OBJECTIVE stores the objective of every iteration's
                            candidate pair (kept or dropped, FP64 residual).  Its workspace
@@ -260,6 +260,8 @@ typedef struct {
   int32_t fp32_tail_iters;
   const float* host_A;    /* host input (pinned for an overlapped copy); must stay valid
                              until the request is running */
+  int32_t nmf;            /* ntt_nmf: NTT_NMF_MU (0) or NTT_NMF_BCD (Alg.3, FP32 only) */
+  double bcd_delta;       /* BCD: cap of the extrapolation weights, in [0, 1) */
 } ntt_request;
 
 enum {

@@ -1775,6 +1775,8 @@ extern "C" ntt_status ntt_server_submit(ntt_server_t sv, const ntt_request* rq, 
   c.precision = rq->precision;
   c.fp32_tail_iters = rq->fp32_tail_iters;
   c.flags = 0;
+  c.nmf = rq->nmf;
+  c.bcd_delta = rq->bcd_delta;
   ntt_plan_t p = nullptr;
   ntt_status st = ntt_plan(&c, &p);
   if (st != NTT_OK) return st;

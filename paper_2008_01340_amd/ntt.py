@@ -111,7 +111,8 @@ class NttServerConfig(C.Structure):
 class NttRequest(C.Structure):
     _fields_ = [("d", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("ranks", C.POINTER(C.c_int64)),
                 ("max_iters", C.c_int32), ("eps", C.c_double), ("seed", C.c_uint64),
-                ("precision", C.c_int32), ("fp32_tail_iters", C.c_int32), ("host_A", C.c_void_p)]
+                ("precision", C.c_int32), ("fp32_tail_iters", C.c_int32), ("host_A", C.c_void_p),
+                ("nmf", C.c_int32), ("bcd_delta", C.c_double)]
 
 
 class NttRequestInfo(C.Structure):
@@ -495,13 +496,14 @@ class Server:
         self._shapes = {}
 
     def submit(self, host_A, ranks, max_iters, seed=0, eps=1e-12, precision=NTT_PREC_FP32,
-               fp32_tail_iters=20) -> int:
-        """host_A: a CPU float32 torch tensor (pinned for an overlapped copy)."""
+               fp32_tail_iters=20, nmf="mu", delta=0.9999) -> int:
+        """host_A: a CPU float32 torch tensor (pinned for an overlapped copy); ``nmf``: "mu"
+        or "bcd"."""
         dims = list(host_A.shape)
         a, b = _i64(dims), _i64(ranks)
         rq = NttRequest(len(dims), C.cast(a, C.POINTER(C.c_int64)), C.cast(b, C.POINTER(C.c_int64)),
                         int(max_iters), float(eps), int(seed) & ((1 << 64) - 1), int(precision),
-                        int(fp32_tail_iters), host_A.data_ptr())
+                        int(fp32_tail_iters), host_A.data_ptr(), _NMF[nmf], float(delta))
         rid = C.c_int64()
         _check(load().ntt_server_submit(self.handle, C.byref(rq), C.byref(rid)), "ntt_server_submit")
         self._inputs[rid.value] = host_A

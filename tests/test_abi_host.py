@@ -221,9 +221,10 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     src.write_text(
         '#include <stddef.h>\n#include <stdio.h>\n#include "ntt.h"\n'
         "int main(void) {\n"
-        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ntt_config), sizeof(ntt_report),\n'
+        '  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ntt_config), sizeof(ntt_report),\n'
         "         offsetof(ntt_config, nmf), offsetof(ntt_config, bcd_delta),\n"
-        "         offsetof(ntt_config, stream_cols), offsetof(ntt_report, corrections));\n"
+        "         offsetof(ntt_config, stream_cols), offsetof(ntt_report, corrections),\n"
+        "         sizeof(ntt_request), offsetof(ntt_request, bcd_delta));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run([gcc, "-std=c99", "-I" + inc, str(src), "-o", str(exe)], check=True)
@@ -231,5 +232,6 @@ def test_struct_layouts_match_the_c_header(tmp_path):
                                           text=True).stdout.split()]
     want = [ctypes.sizeof(ntt.NttConfig), ctypes.sizeof(ntt.NttReport),
             ntt.NttConfig.nmf.offset, ntt.NttConfig.bcd_delta.offset,
-            ntt.NttConfig.stream_cols.offset, ntt.NttReport.corrections.offset]
+            ntt.NttConfig.stream_cols.offset, ntt.NttReport.corrections.offset,
+            ctypes.sizeof(ntt.NttRequest), ntt.NttRequest.bcd_delta.offset]
     assert got == want

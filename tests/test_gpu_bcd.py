@@ -293,3 +293,32 @@ def test_bcd_batched_results_equal_standalone_results_bitwise():
         for x, y in zip(cb, one.cores):
             assert torch.equal(x, y), (d, r)
         assert rb["corrections"] == one.report["corrections"]
+
+
+def test_bcd_serving_results_equal_standalone_results():
+    say("case: serving 4 BCD requests, 25 iterations per tick")
+    probs = [((6, 7, 5), (1, 3, 4, 1), 11), ((16, 16, 16), (1, 4, 4, 1), 1),
+             ((9, 20, 8, 6), (1, 5, 6, 3, 1), 5), ((64, 33, 50), (1, 10, 12, 1), 3)]
+    T = 60
+    host_t = [S.contract_cores(S.random_cores(d, r, seed=s)) for d, r, s in probs]
+    srv = ntt.Server(1 << 30, max_slots=4, iters_per_tick=25)
+    ids = []
+    for a, (d, r, s) in zip(host_t, probs):
+        h = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
+        h.copy_(torch.from_numpy(a))
+        ids.append(srv.submit(h, r, T, seed=s, nmf="bcd"))
+    alone = [ntt.decompose(dev(a), r, T, seed=s, nmf="bcd") for a, (d, r, s) in zip(host_t, probs)]
+    pending = dict(zip(ids, range(len(ids))))
+    ticks = 0
+    while pending:
+        srv.tick()
+        ticks += 1
+        for rid in list(pending):
+            if srv.info(rid)["state"] != ntt.NTT_REQ_DONE:
+                continue
+            i = pending.pop(rid)
+            for x, y in zip(srv.cores(rid), alone[i].cores):
+                assert torch.equal(x, y), probs[i]
+            srv.release(rid)
+        assert ticks < 100000
+    srv.close()
