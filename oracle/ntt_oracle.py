@@ -193,8 +193,11 @@ def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
 #       square root is read as this norm; the Frobenius norm bounds the spectral norm,
 #       the Lipschitz constant of the block gradient, from above, so every plain step
 #       descends); a zero L takes no gradient step (the block is only projected);
-#   B3  no per-iteration L1 normalisation of W: it would rescale W H without a matching
-#       rescale of H, and the block-coordinate method the paper cites has none;
+#   B3  after each W step, W is divided by its entrywise L1 norm, the sum of its entries
+#       (W >= 0 after the projection), as the W block of the listing prints; the W^T W
+#       and the H step that follow use the normalised W, so H absorbs the scale; a zero
+#       W is left as it is.  ``normalise=None`` drops this step (an earlier reading of
+#       the listing, kept for comparison only);
 #   B4  the starting objective is 1/2 ||X||_F^2 (the objective at W = H = 0; the
 #       listing prints ||X|| without the square);
 #   B5  the random factors are scaled to ||W||_F = ||H||_F = sqrt(||X||_F) and form the
@@ -223,6 +226,13 @@ def bcd_step_W(XHt, HHt, Wm):
     return np.maximum(0.0, Wm - (Wm @ HHt - XHt) / L), L
 
 
+def bcd_normalise_l1(W):
+    """B3: W divided by its entrywise L1 norm (the sum of |w_ij|); a zero W is returned
+    unchanged."""
+    s = float(np.sum(np.abs(W)))
+    return W / s if s > 0.0 else W
+
+
 def bcd_step_H(WtX, WtW, Hm):
     """The H block step of Alg.3 (B2) from the extrapolated H_m, given W^T X and W^T W of
     the new W.  Column j of the result depends only on column j of W^T X and H_m.
@@ -248,8 +258,11 @@ def bcd_normalise(X, W0, H0):
     return W, H
 
 
-def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
+def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=(), normalise="l1"):
     """NMF of X by Alg.3 (BCD with extrapolation and correction) from (W0, H0).
+
+    ``normalise="l1"`` (the listing) divides every new W by its entrywise L1 norm before
+    the H step (B3); ``None`` leaves it out.
 
     Returns a dict with the kept pair W, H, ``corrections`` (how many iterations were
     dropped), ``kept`` (per iteration: True when kept), ``objective`` (the objective of
@@ -271,6 +284,8 @@ def bcd_nmf(X, W0, H0, iters, delta=0.9999, snapshots=()):
     kept, f_hist, t_hist, w_hist, ww_hist, wh_hist = [], [], [], [], [], []
     for it in range(1, iters + 1):
         Wn, _ = bcd_step_W(XHt, HHt, Wm)
+        if normalise == "l1":
+            Wn = bcd_normalise_l1(Wn)
         WtW = Wn.T @ Wn
         Hn, LH = bcd_step_H(Wn.T @ X, WtW, Hm)
         f = objective(X, Wn, Hn)
@@ -326,9 +341,10 @@ def eps_rank(X, eps) -> int:
 # ---------------------------------------------------------------- the nTT sweep
 def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
                   inits=None, record_objective=False, snapshots=(), rank_eps=0.0,
-                  nmf="mu", delta=0.9999):
+                  nmf="mu", delta=0.9999, bcd_normalise="l1"):
     """Alg.2 with MU (``nmf="mu"``) or Alg.3 (``nmf="bcd"``, fixed ``iters`` per stage,
-    extrapolation cap ``delta``) as the NMF: returns cores and per-stage details.
+    extrapolation cap ``delta``, W normalisation ``bcd_normalise`` as in ``bcd_nmf``) as
+    the NMF: returns cores and per-stage details.
 
     ``A`` is the d-way tensor (converted to float64, C order).  ``ranks`` has d+1
     entries with r_0 = r_d = 1.  With ``rank_eps`` = 0 they are the TT ranks (clamped as
@@ -354,7 +370,7 @@ def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
         else:
             W0, H0 = init_factors(seed, l, m, rl, k)
         if nmf == "bcd":
-            res = bcd_nmf(X, W0, H0, iters, delta, snapshots)
+            res = bcd_nmf(X, W0, H0, iters, delta, snapshots, bcd_normalise)
         else:
             res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots)
         res.update({"X": X, "W0": W0, "H0": H0, "m": m, "k": k, "r": rl})
@@ -399,8 +415,3 @@ def rel_error(A, Ahat) -> float:
     D = A - np.asarray(Ahat, dtype=np.float64)
     return math.sqrt(float(np.sum(D * D))) / math.sqrt(float(np.sum(A * A)))
 
-
-def ntt_flops(shapes, iters_per_stage) -> float:
-    """Algorithmic flops of the MU sweep: 4mkr + 4(m+k)r^2 per iteration per stage."""
-    return float(sum(t * (4.0 * m * k * r + 4.0 * (m + k) * r * r)
-                     for (m, k, r), t in zip(shapes, iters_per_stage)))

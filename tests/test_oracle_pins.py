@@ -346,6 +346,32 @@ def test_sweep_near_exact_recovery_improves_with_iterations():
     assert errs[2] < 0.05
 
 
+@pytest.mark.parametrize("f,nx,tol,K,first_stop", [
+    # ||X|| = 1 keeps the residual test off (sqrt(2 f) > 0.25 for every f here).  K = 2:
+    # the fall 200 -> 80 is large; 80 -> 60 is exactly tol * f_{t-K} = 20 (tol = 0.25),
+    # and the rule stops on equality, at t = 4
+    ([200.0, 150.0, 80.0, 70.0, 60.0, 5.0], 1.0, 0.25, 2, 4),
+    # the same with f_4 one unit in the last place below 60: the fall is 20 + 2^-47, no
+    # stop at t = 4; 60 -> 50 at t = 6 is within 15
+    ([200.0, 150.0, 80.0, 70.0, float(np.nextafter(60.0, 0.0)), 55.0, 50.0], 1.0, 0.25, 2, 6),
+    # relative residual sqrt(2 f)/||X|| = 1/4 exactly at t = 3 (f = 0.5, ||X|| = 4):
+    # stops on equality although the objective still falls fast
+    ([800.0, 200.0, 50.0, 0.5], 4.0, 0.25, 1, 3),
+    # f just above 0.5: the residual test fails, the fall from 50 to 0.50000001 is large
+    ([800.0, 200.0, 50.0, 0.5 + 1e-8, 0.5 + 1e-8], 4.0, 0.25, 1, 4),
+    # checks only at multiples of K = 3: the flat stretch at t = 1, 2 is not seen; the
+    # fall 5 -> 4.6 at t = 6 is within tol * 5 = 0.5
+    ([10.0, 10.0, 10.0, 5.0, 4.8, 4.7, 4.6], 1e-3, 0.1, 3, 6),
+])
+def test_stop_rule_hand_built_objective_sequences(f, nx, tol, K, first_stop):
+    # sequences whose first stop is worked out by hand (the rule of a tolerance budget:
+    # at t % K == 0, sqrt(2 f_t)/||X|| <= tol, or f_{t-K} - f_t <= tol f_{t-K}); swapping
+    # f_t and f_{t-K}, or < for <=, moves the first stop
+    stops = [t for t in range(1, len(f)) if O.stop_now(f, t, nx, tol, K)]
+    assert stops and stops[0] == first_stop
+    assert not O.stop_now(f, first_stop, nx, 0.0, K)  # tol = 0: fixed iteration count
+
+
 def test_stop_rule_on_tolerance():
     X = _nonneg(20, 30, 13)
     W0, H0 = O.init_factors(1, 1, 20, 3, 30)
@@ -465,8 +491,9 @@ def test_bcd_correction_returns_to_the_last_kept_pair():
     Wc, Hc = res["snaps"][c]
     assert np.array_equal(Wb, Wc) and np.array_equal(Hb, Hc)
     assert res["objective"][c - 1] >= _f(X, Wb, Hb)  # the dropped candidate was no better
-    # the next iteration is a plain (unextrapolated) step from the kept pair
-    Wn, _ = O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wb)
+    # the next iteration is a plain (unextrapolated) step from the kept pair, W
+    # normalised to unit entrywise L1 norm before the H step
+    Wn = O.bcd_normalise_l1(O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wb)[0])
     Hn, _ = O.bcd_step_H(Wn.T @ X, Wn.T @ Wn, Hb)
     assert res["objective"][c] == pytest.approx(_f(X, Wn, Hn), rel=1e-12)
     if res["kept"][c]:
@@ -518,7 +545,67 @@ def test_bcd_extrapolation_weights_are_capped_by_the_gram_norm_ratios():
         if it < T:  # the candidate of iteration it + 1 starts from the extrapolated points
             Wm = Wb + res["wW"][it - 1] * (Wb - Wa)
             Hm = Hb + res["wH"][it - 1] * (Hb - Ha)
-            Wn, _ = O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wm)
+            Wn = O.bcd_normalise_l1(O.bcd_step_W(X @ Hb.T, Hb @ Hb.T, Wm)[0])
             Hn, _ = O.bcd_step_H(Wn.T @ X, Wn.T @ Wn, Hm)
             assert res["objective"][it] == pytest.approx(_f(X, Wn, Hn), rel=1e-12)
     assert binding > 0
+
+
+def test_bcd_W_has_unit_l1_norm_after_every_kept_step():
+    # Alg.3's W block ends with W /= ||W||_1: every kept W (after the first kept
+    # iteration) sums to 1; without the step (normalise=None) it does not
+    rng = _rng(47)
+    X = rng.random((24, 35)) * 4.0
+    W0, H0 = rng.random((24, 3)), rng.random((3, 35))
+    T = 40
+    res = O.bcd_nmf(X, W0, H0, T, snapshots=tuple(range(1, T + 1)))
+    first = res["kept"].index(True) + 1
+    for t in range(first, T + 1):
+        W = res["snaps"][t][0]
+        assert abs(sum(float(v) for v in W.ravel()) - 1.0) <= 1e-12, t
+        assert W.min() >= 0.0
+    plain = O.bcd_nmf(X, W0, H0, T, normalise=None)
+    assert abs(float(np.sum(plain["W"])) - 1.0) > 1e-3
+
+
+def test_bcd_one_iteration_rank1_hand_worked():
+    # X = [[1, 2, 3], [2, 4, 6]] = (1, 2)^T (1, 2, 3).  At r = 1 both block steps are
+    # exact non-negative least squares (the Frobenius norm of a 1 x 1 Gram is the exact
+    # Lipschitz constant), so from any positive start one iteration gives:
+    #   W step: w_i = <x_i, h>/|h|^2, proportional to (1, 2) (the rows of X are);
+    #   L1 normalisation: w = (1/3, 2/3);
+    #   H step: h_j = <w, x_j>/|w|^2 = (5/3, 10/3, 5) / (5/9) = (3, 6, 9);
+    # so W H = X, objective 0 < 1/2 ||X||^2 = 35: the pair is kept.
+    X = np.array([[1.0, 2.0, 3.0], [2.0, 4.0, 6.0]])
+    res = O.bcd_nmf(X, np.array([[0.7], [0.2]]), np.array([[0.5, 0.9, 0.1]]), 1)
+    assert res["kept"] == [True]
+    assert np.allclose(res["W"], [[1.0 / 3.0], [2.0 / 3.0]], rtol=1e-14, atol=0)
+    assert np.allclose(res["H"], [[3.0, 6.0, 9.0]], rtol=1e-13, atol=0)
+    assert res["objective"][0] <= 1e-24
+
+
+def test_bcd_one_iteration_rank1_by_explicit_loops():
+    # the first iteration of Alg.3 at r = 1 on a random non-negative matrix, written out
+    # with loops: the B5 scaling, the exact NNLS W step, the L1 normalisation, the exact
+    # NNLS H step of the normalised W, and the kept decision against 1/2 ||X||^2
+    rng = _rng(48)
+    m, k = 5, 7
+    X = rng.random((m, k))
+    w0, h0 = rng.random(m), rng.random(k)
+    nx = math.sqrt(sum(X[i, j] ** 2 for i in range(m) for j in range(k)))
+    nw = math.sqrt(sum(v * v for v in w0))
+    nh = math.sqrt(sum(v * v for v in h0))
+    h = [v / nh * math.sqrt(nx) for v in h0]
+    hh = sum(v * v for v in h)
+    w = [max(0.0, sum(X[i, j] * h[j] for j in range(k)) / hh) for i in range(m)]
+    s1 = sum(w)
+    w = [v / s1 for v in w]
+    ww = sum(v * v for v in w)
+    hn = [max(0.0, sum(w[i] * X[i, j] for i in range(m)) / ww) for j in range(k)]
+    f = 0.5 * sum((X[i, j] - w[i] * hn[j]) ** 2 for i in range(m) for j in range(k))
+    res = O.bcd_nmf(X, w0.reshape(m, 1), h0.reshape(1, k), 1)
+    assert res["kept"] == [f < 0.5 * nx * nx]
+    assert np.allclose(res["W"][:, 0], w, rtol=1e-12, atol=0)
+    assert np.allclose(res["H"][0], hn, rtol=1e-12, atol=0)
+    assert res["objective"][0] == pytest.approx(f, rel=1e-12)
+    assert nw > 0
