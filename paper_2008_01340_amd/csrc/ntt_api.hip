@@ -1226,14 +1226,17 @@ struct NttJob {
       }
       streamed = false;
     }
+    // the trace slot of the last iterate: with BCD it holds the last candidate's objective
+    // (written by the decision on it), which need not be the kept pair's
+    double* last_slot = (record && t >= 1) ? trace + trace_off + (t - 1) : nullptr;
     if (bcd) {  // decision on the last candidate; the kept H into the stage's buffer
       BcdArgs b = ba;
-      b.trace = (record && t >= 1) ? trace + trace_off + (t - 1) : nullptr;
+      b.trace = last_slot;
       HIP_TRY(launch_bcd_finish(b, c.s));
       bcd = false;
+      last_slot = nullptr;
     }
-    if (want_final && !final_known)
-      HIP_TRY(residual_now((record && t >= 1) ? trace + trace_off + (t - 1) : nullptr));
+    if (want_final && !final_known) HIP_TRY(residual_now(last_slot));
     if (trans) {  // W = H'^T, H = W'^T
       const Stage& s = st();
       HIP_TRY(launch_transpose(c.hp(), W, s.r, s.m, c.s));

@@ -11,7 +11,9 @@
 //                stay and the next steps start from the kept pair without extrapolation.
 //                (b) W_m = W + w_W (W - W_prev) and the W step
 //                W_n = max(0, W_m - (W_m H H^T - X H^T) / ||H H^T||_F), in FP64 on FP32
-//                data, and G = W_n^T W_n (FP64, rows in order).
+//                data, then W_n /= sum(W_n) (the L1 normalisation the W block of Alg.3
+//                ends with; W_n >= 0, and a zero W_n is left as it is), and
+//                G = W_n^T W_n of the normalised W_n (FP64, rows in order).
 //   k_bcd_h      one thread per column: H_m = H + w_H (H - H_prev), W_n^T X, and the H step
 //                H_n = max(0, H_m - (G H_m - W_n^T X) / ||G||_F) into the candidate buffer.
 //   k_bcd_xht    X H_n^T and H_n H_n^T partials per column chunk, and per workgroup the
@@ -462,8 +464,9 @@ __global__ __launch_bounds__(256) void k_bcd_xhtm(BcdArgs b, int init) {
 }
 
 // The decision on the previous candidate (unless this is the stage's first step), then,
-// unless `final_step`, the W step and G = W_n^T W_n.  One workgroup; thread tid owns rows
-// tid, tid + 256, ... in every phase, so it only re-reads global data it wrote itself.
+// unless `final_step`, the W step, its L1 normalisation and G = W_n^T W_n.  One workgroup;
+// thread tid owns rows tid, tid + 256, ... in every phase, so it only re-reads global data
+// it wrote itself.
 // The kernel is latency-bound: every load it needs for the decision and for its first
 // 256 rows is issued at once, the sums go through one barrier, and every thread then
 // takes the (identical) decision itself.
@@ -471,7 +474,7 @@ template <int RP>
 __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
   __shared__ float sWn[256][RP + 1];
   __shared__ double sHH[RP][RP + 1];
-  __shared__ double sPart[3][4];  // per-wave sums: objective, ||H_n H_n^T||^2, ||G||^2
+  __shared__ double sPart[4][4];  // per-wave sums: objective, ||H_n H_n^T||^2, ||G||^2, sum(W_n)
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int m = b.m, r = b.r;
   const int64_t mr = (int64_t)m * r;
@@ -590,9 +593,7 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
   }
   __syncthreads();
   const double wW = s.wW, LW = s.gH;
-  // G = W_n^T W_n with FP64 MFMA (16 x 16 x 4): wave wv takes rows 64 wv .. 64 wv + 63 of
-  // each 256-row chunk, four rows a step, the lane (a, bq) feeding W_n[row 4 st + bq][a]
-  // as both operands; output register i of lane l is G[4 i + l / 16][l % 16]
+  // accumulators of G = W_n^T W_n
   constexpr int NT = (RP + 15) / 16;
   v4d gm[NT][NT];
 #pragma unroll
@@ -600,12 +601,17 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) gm[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
   const int la = ln & 15, lb = ln >> 4;
+  // (1) the W step from the extrapolated point, row by row; the entry sum of W_n for its
+  // L1 norm.  With one 256-row chunk the unnormalised rows stay in registers (FP64);
+  // with more they go to Wn as FP32 and are read back by the same thread in (2).
+  const bool one_chunk = m <= 256;
+  double wd[RP];
+  double wsum = 0.0;
   for (int i0 = 0; i0 < m; i0 += 256) {
     if (i0 > 0) load_rows(i0);
     const int i = i0 + tid;
-    float wo[RP];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) wo[c] = 0.f;
+    for (int c = 0; c < RP; ++c) wd[c] = 0.0;
     if (i < m) {
       double wm[RP], xh[RP];
 #pragma unroll
@@ -631,8 +637,35 @@ __global__ __launch_bounds__(256) void k_bcd_step(BcdArgs b, int final_step) {
 #pragma unroll
           for (int q = 0; q < RP; ++q) gr += wm[q] * sHH[q][c];
           const double v = LW > 0.0 ? wm[c] - gr / LW : wm[c];
-          wo[c] = (float)std::max(0.0, v);
-          b.Wn[(int64_t)i * r + c] = wo[c];
+          wd[c] = std::max(0.0, v);
+          wsum += wd[c];
+          if (!one_chunk) b.Wn[(int64_t)i * r + c] = (float)wd[c];
+        }
+      }
+    }
+  }
+  wsum = bcd_wave_sum(wsum);
+  if (ln == 0) sPart[3][wv] = wsum;
+  __syncthreads();
+  const double l1 = ((sPart[3][0] + sPart[3][1]) + sPart[3][2]) + sPart[3][3];
+  const double l1d = l1 > 0.0 ? l1 : 1.0;  // a zero W_n stays as it is
+  // (2) W_n / ||W_n||_1 into Wn, and G = W_n^T W_n with FP64 MFMA (16 x 16 x 4): wave wv
+  // takes rows 64 wv .. 64 wv + 63 of each 256-row chunk, four rows a step, the lane
+  // (a, bq) feeding W_n[row 4 st + bq][a] as both operands; output register i of lane l is
+  // G[4 i + l / 16][l % 16]
+  for (int i0 = 0; i0 < m; i0 += 256) {
+    const int i = i0 + tid;
+    float wo[RP];
+#pragma unroll
+    for (int c = 0; c < RP; ++c) wo[c] = 0.f;
+    if (i < m) {
+#pragma unroll
+      for (int c = 0; c < RP; ++c) {
+        if (c < r) {
+          const int64_t e = (int64_t)i * r + c;
+          const double v = one_chunk ? wd[c] : (double)b.Wn[e];
+          wo[c] = (float)(v / l1d);
+          b.Wn[e] = wo[c];
         }
       }
     }
