@@ -152,12 +152,13 @@ def stop_now(f_hist, t, nx, tol, check_every) -> bool:
 
 
 def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
-           record_objective=False, snapshots=()):
+           record_objective=False, snapshots=(), objective_at=()):
     """NMF of X by MU from (W0, H0); returns a dict with W, H, iters, objective, snaps.
 
     ``objective[t]`` is the explicit objective after t full iterations (index 0 = init),
     filled when ``record_objective`` or ``tol > 0``.  ``snaps[t] = (W_t, H_t)`` for t in
-    ``snapshots``.
+    ``snapshots``; ``objective_at_t[t]`` is the explicit objective after t iterations for
+    t in ``objective_at`` (the same quantity as ``objective[t]``, only at chosen t).
     """
     X = np.asarray(X, dtype=np.float64)
     W = np.array(W0, dtype=np.float64)
@@ -165,7 +166,7 @@ def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
     want_obj = record_objective or tol > 0
     nx = math.sqrt(float(np.sum(X * X)))
     f_hist = [objective(X, W, H)] if want_obj else []
-    snaps = {}
+    snaps, f_at = {}, {}
     if 0 in snapshots:
         snaps[0] = (W.copy(), H.copy())
     t_done = 0
@@ -174,12 +175,14 @@ def mu_nmf(X, W0, H0, iters, eps=1e-12, tol=0.0, check_every=10,
         t_done = t
         if want_obj:
             f_hist.append(objective(X, W, H))
+        if t in objective_at:
+            f_at[t] = f_hist[t] if want_obj else objective(X, W, H)
         if t in snapshots:
             snaps[t] = (W.copy(), H.copy())
         if want_obj and stop_now(f_hist, t, nx, tol, check_every):
             break
     return {"W": W, "H": H, "iters": t_done, "objective": np.array(f_hist),
-            "snaps": snaps, "norm_x": nx}
+            "snaps": snaps, "objective_at_t": f_at, "norm_x": nx}
 
 
 # ---------------------------------------------------------------- NMF by BCD (Alg.3)
@@ -341,7 +344,7 @@ def eps_rank(X, eps) -> int:
 # ---------------------------------------------------------------- the nTT sweep
 def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
                   inits=None, record_objective=False, snapshots=(), rank_eps=0.0,
-                  nmf="mu", delta=0.9999, bcd_normalise="l1"):
+                  nmf="mu", delta=0.9999, bcd_normalise="l1", objective_at=()):
     """Alg.2 with MU (``nmf="mu"``) or Alg.3 (``nmf="bcd"``, fixed ``iters`` per stage,
     extrapolation cap ``delta``, W normalisation ``bcd_normalise`` as in ``bcd_nmf``) as
     the NMF: returns cores and per-stage details.
@@ -351,7 +354,8 @@ def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
     in ``effective_ranks``); with ``rank_eps`` > 0 each inner rank is chosen at its stage
     by ``eps_rank`` of the current unfolding (Alg.2) and ``ranks`` only caps it.
     ``inits`` optionally maps stage l (1-based) to (W0, H0); otherwise the seeded
-    uniform init of ``init_factors`` is used.
+    uniform init of ``init_factors`` is used.  ``snapshots`` and ``objective_at`` (MU) are
+    passed to every stage's NMF.
     """
     A = np.asarray(A, dtype=np.float64)
     dims = list(A.shape)
@@ -372,7 +376,8 @@ def ntt_decompose(A, ranks, iters, eps=1e-12, seed=0, tol=0.0, check_every=10,
         if nmf == "bcd":
             res = bcd_nmf(X, W0, H0, iters, delta, snapshots, bcd_normalise)
         else:
-            res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots)
+            res = mu_nmf(X, W0, H0, iters, eps, tol, check_every, record_objective, snapshots,
+                         objective_at)
         res.update({"X": X, "W0": W0, "H0": H0, "m": m, "k": k, "r": rl})
         stages.append(res)
         cores.append(res["W"].reshape(r[l - 1], dims[l - 1], rl))
