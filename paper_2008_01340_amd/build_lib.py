@@ -12,33 +12,54 @@ SOURCES = ["csrc/ntt_kernels.hip", "csrc/ntt_bcd.hip", "csrc/ntt_api.hip"]
 LIB = os.path.join(HERE, "libntt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+COMPILE_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
     "-Wno-unused-command-line-argument",
-    # rocSOLVER (symmetric eigenvalues for the rank rule) and the rocBLAS handle it runs on
-    "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",
 ]
+# rocSOLVER (symmetric eigenvalues for the rank rule) and the rocBLAS handle it runs on
+LINK_FLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC", "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
+
+
+def _filter(stderr: str) -> str:
+    # hipcc's host pass does not know the packed-fp32 feature; keep other warnings
+    return "\n".join(l for l in stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
 
 
 def build(verbose: bool = True) -> str:
-    """Compile every HIP source into paper_2008_01340_amd/libntt.so; returns its path."""
-    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    """Compile every HIP source (in parallel, one object each) and link
+    paper_2008_01340_amd/libntt.so; returns its path."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))
+        cmd = [HIPCC] + COMPILE_FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                 text=True)))
+    failed = False
+    for src, obj, pr in procs:
+        out, err = pr.communicate()
+        msg = _filter(out + err)
+        if pr.returncode != 0:
+            failed = True
+            sys.stderr.write(msg + "\n")
+        elif verbose and msg:
+            sys.stderr.write(msg + "\n")
+    if failed:
+        raise RuntimeError("hipcc failed compiling libntt.so's sources")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
+    cmd = [HIPCC] + [o for _, o, _ in procs] + LINK_FLAGS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libntt.so")
-    if verbose and res.stderr.strip():
-        # hipcc's host pass does not know the packed-fp32 feature; keep other warnings
-        lines = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l]
-        if any(l.strip() for l in lines):
-            sys.stderr.write("\n".join(lines) + "\n")
+        raise RuntimeError("hipcc failed linking libntt.so")
     os.replace(tmp, LIB)
     return LIB
 
