@@ -199,6 +199,20 @@ ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_t* ranks, c
                          const float* const* cores, void* workspace, size_t workspace_bytes,
                          double* rel_err, void* stream);
 
+/* ntt_rel_error for callers that cannot allocate device memory or pass a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and result as ntt_rel_error without the workspace: the partial sums go
+ * to a fixed device array of NTT_REL_ERROR_STATIC_BYTES inside the library (one per GPU,
+ * held until the process ends; its address is looked up once per device), so the call
+ * allocates nothing.  Limit: n_1*...*n_{d-1} <= 33,554,368 (the 256^4 tensor has
+ * 16,777,216); larger tensors return NTT_ERR_WORKSPACE_TOO_SMALL.  Every call overwrites
+ * the array before reading it.  Calls that overlap on one GPU (other threads, or other
+ * streams not ordered with this one) share the array and race: serialise them. */
+#define NTT_REL_ERROR_STATIC_BYTES (8u << 20)
+ntt_status ntt_rel_error_static(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                const float* A, const float* const* cores, double* rel_err,
+                                void* stream);
+
 /* Eq.(4) for arbitrary ranks (host only). */
 double ntt_compression_ratio(int32_t d, const int64_t* dims, const int64_t* ranks);
 

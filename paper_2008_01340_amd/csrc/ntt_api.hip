@@ -1434,6 +1434,55 @@ extern "C" ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_
   return NTT_OK;
 }
 
+// ------------------------------------------------------------------ Eq.(3) without allocation
+// The per-block partial sums of ntt_rel_error_static live in a file-scope device array
+// (each GPU holds its own copy for the life of the process).  Host code never passes the
+// array's name to a kernel or a copy: its device address is taken once per device with
+// hipGetSymbolAddress, with that device current, and that address is used instead.
+namespace {
+constexpr size_t kStaticScratchDoubles = NTT_REL_ERROR_STATIC_BYTES / sizeof(double);
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+ntt_status static_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(NTT_ERR_DEVICE, "no current HIP device (or device index beyond 63)");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(NTT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return NTT_OK;
+}
+}  // namespace
+
+extern "C" ntt_status ntt_rel_error_static(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                           const float* A, const float* const* cores, double* rel_err,
+                                           void* stream) {
+  size_t need = 0;
+  ntt_status st = ntt_tt_workspace(d, dims, ranks, &need);
+  if (st != NTT_OK) return st;
+  if (need > NTT_REL_ERROR_STATIC_BYTES)
+    return fail(NTT_ERR_WORKSPACE_TOO_SMALL,
+                "tensor too large for ntt_rel_error_static: n_1...n_{d-1} must be at most " +
+                    std::to_string((NTT_REL_ERROR_STATIC_BYTES / sizeof(double) - 2) / 2 * 64) +
+                    " (use ntt_rel_error with a workspace)");
+  double* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != NTT_OK) return st;
+  return ntt_rel_error(d, dims, ranks, A, cores, ws, NTT_REL_ERROR_STATIC_BYTES, rel_err, stream);
+}
+
 // ------------------------------------------------------------------ batched mode (a9)
 // Independent decompositions of uneven shape and rank, advanced stage level by stage
 // level.  At each level, unfoldings small enough for one workgroup (m <= 256, k <= 64,

@@ -39,7 +39,8 @@ NTT_PROFILE = 8
 
 EXPORTED = [
     "ntt_plan", "ntt_plan_workspace", "ntt_decompose", "ntt_tt_workspace", "ntt_reconstruct",
-    "ntt_rel_error", "ntt_compression_ratio", "ntt_plan_destroy", "ntt_status_string",
+    "ntt_rel_error", "ntt_rel_error_static", "ntt_compression_ratio", "ntt_plan_destroy",
+    "ntt_status_string",
     "ntt_last_error", "ntt_version", "ntt_batch_plan", "ntt_batch_workspace",
     "ntt_decompose_batch", "ntt_batch_destroy", "ntt_server_create", "ntt_server_submit",
     "ntt_server_tick", "ntt_server_info", "ntt_server_cores", "ntt_server_release",
@@ -156,6 +157,9 @@ def load(path: str = LIB_PATH):
     lib.ntt_rel_error.argtypes = [C.c_int32, i64p, i64p, P, C.POINTER(P), P, C.c_size_t,
                                   C.POINTER(C.c_double), P]
     lib.ntt_rel_error.restype = C.c_int
+    lib.ntt_rel_error_static.argtypes = [C.c_int32, i64p, i64p, P, C.POINTER(P),
+                                         C.POINTER(C.c_double), P]
+    lib.ntt_rel_error_static.restype = C.c_int
     lib.ntt_compression_ratio.argtypes = [C.c_int32, i64p, i64p]
     lib.ntt_compression_ratio.restype = C.c_double
     lib.ntt_plan_destroy.argtypes = [P]
@@ -299,6 +303,14 @@ def ntt_rel_error(dims, ranks, A: int, cores, workspace: int, workspace_bytes: i
     _check(load().ntt_rel_error(len(dims), _i64(dims), _i64(ranks), C.c_void_p(A), _ptrs(cores),
                                 C.c_void_p(workspace), workspace_bytes, C.byref(out),
                                 C.c_void_p(stream)), "ntt_rel_error")
+    return float(out.value)
+
+
+def ntt_rel_error_static(dims, ranks, A: int, cores, stream: int = 0) -> float:
+    out = C.c_double()
+    _check(load().ntt_rel_error_static(len(dims), _i64(dims), _i64(ranks), C.c_void_p(A),
+                                       _ptrs(cores), C.byref(out), C.c_void_p(stream)),
+           "ntt_rel_error_static")
     return float(out.value)
 
 
