@@ -76,6 +76,9 @@ typedef enum {
 #define NTT_VALIDATE_INPUT 2u   /* check A >= 0 and finite before the sweep */
 #define NTT_RECORD_OBJECTIVE 4u /* explicit FP64 objective of every iterate into objective_trace */
 #define NTT_PROFILE 8u          /* fill ntt_report.pass_ms with per-launch kernel timings */
+#define NTT_NO_COOP 16u         /* every stage keeps one launch per pass and W-update (no
+                                   whole-stage cooperative launch for m <= 256, r <= 16,
+                                   k <= 32768); the iterates are the same up to summation order */
 
 typedef struct {
   int32_t d;            /* number of modes, 2..NTT_MAX_DIMS */

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/ntt_kernels.hip", "csrc/ntt_bcd.hip", "csrc/ntt_api.hip"]
+SOURCES = ["csrc/ntt_kernels.hip", "csrc/ntt_bcd.hip", "csrc/ntt_coop.hip", "csrc/ntt_api.hip"]
 LIB = os.path.join(HERE, "libntt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -91,6 +91,10 @@ struct Stage {
   size_t part_stride = 0;  // floats between the per-workgroup partials of this stage
   // generic stages whose transposed problem (X^T = H^T W^T) fits the fused passes
   bool trans_ok = false;
+  // the whole stage in one cooperative launch (m <= 256, r <= 16, 64 < k <= 32768):
+  // 16-column groups per workgroup and workgroups
+  bool coop_ok = false;
+  int coop_ng = 0, coop_G = 0;
   int G_pre = 1;          // transposed problem: column chunks of its first X H^T pass
   int64_t chunk_pre = 0;
 };
@@ -176,6 +180,11 @@ void stage_shape(const ntt_config& cfg, int64_t m, int64_t k, int r, Stage& s, S
   s.r = r;
   classify_stage(s, cfg.precision);
   if (s.kind == PASS_GENERIC) generic_chunks(s, &s.G, &s.chunk);
+  s.coop_ok = stage_coop_ok(m, k, r);
+  if (s.coop_ok) {
+    s.coop_ng = stage_coop_ng(k);
+    s.coop_G = stage_coop_grid(k, s.coop_ng);
+  }
   if (!s.fused) {
     // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
     // this one shifted by half a step, and its rows (k) may fit the fused passes
@@ -240,6 +249,10 @@ struct ntt_plan_s {
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
+  // stages may run as one cooperative launch (standalone plans; batched and served
+  // problems run concurrently on several streams and keep one launch per pass)
+  bool coop_allowed = true;
+  size_t off_coop = 0;  // barrier flags of the cooperative stage (32 per workgroup)
   // replayable blocks of MU iterations, one per (stage, block length, buffers)
   struct GraphEntry {
     int stage, iters;
@@ -396,6 +409,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
     gmax = std::max(gmax, s.G);
     gfin = std::max(gfin, s.G);
     part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
+    if (s.coop_ok) part_floats = std::max(part_floats, (size_t)s.coop_G * E);
     if (l < d - 1) {
       const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
       hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
@@ -495,6 +509,7 @@ ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   p->off_s = off; off = align_up(off + s_size, 256);
   p->off_wb = off; off = align_up(off + wb_size, 256);
   p->off_gpart = off; off = align_up(off + (size_t)((m_max + 255) / 256) * (32 * 32 + 1) * sizeof(double), 256);
+  p->off_coop = off; off = align_up(off + (size_t)512 * 32 * sizeof(unsigned), 256);
   if (eps_mode) {
     p->off_grp = off; off = align_up(off + grp_max * sizeof(double), 256);
     p->off_gram = off; off = align_up(off + gram_max * sizeof(double), 256);
@@ -642,6 +657,7 @@ struct NttJob {
   bool bcd = false;  // the stage runs Alg.3 (BCD) instead of MU
   BcdArgs ba{};
   bool streamed = false;  // stage 1 with X in host memory, passed over in column blocks
+  bool coop = false;      // the stage's iterations run in cooperative whole-stage launches
 
   // column block b of the streamed stage: width, shape, staging copies
   int64_t blk_w(int64_t b) const { return std::min(p->kblk, st().k - b * p->kblk); }
@@ -825,7 +841,10 @@ struct NttJob {
     trans = !bcd && !streamed && s.trans_ok && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     const Stage& e = es();
     one_wg = !bcd && !streamed && !trans && !record && !profile && stage_1wg_ok(s.m, s.k, s.r);
-    pro = !bcd && !streamed && s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
+    coop = p->coop_allowed && !(cfg.flags & NTT_NO_COOP) && s.coop_ok && !bcd && !streamed && !trans &&
+           !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1 &&
+           s.coop_G <= stage_coop_max_grid(s.coop_ng);
+    pro = !bcd && !streamed && !coop && s.pro_ok && !trans && !one_wg && !record && !profile && cfg.tol == 0.0 && cfg.max_iters >= 1;
     pro_done = false;
     const float eps = (float)cfg.eps;
     if (trans) {
@@ -840,7 +859,8 @@ struct NttJob {
       pa = pass_args(c, s, X, H, W, eps);
     }
     pa_bf = pa;
-    bf_iters = (e.bf16 && !bcd && !streamed) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    // (a cooperative stage keeps X on chip: it reads X once per launch, in FP32)
+    bf_iters = (e.bf16 && !bcd && !streamed && !coop) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
     if (bf_iters > 0) {
       HIP_TRY(launch_cast_bf16(c.xb(), pa.X, s.m * s.k, q));
       pa_bf.Xb = c.xb();
@@ -984,6 +1004,7 @@ struct NttJob {
   // may end the stage early); *stage_done is set when no iterations remain.
   ntt_status iterate(int budget, bool* stage_done) {
     if (bcd) return iterate_bcd(budget, stage_done);
+    if (coop) return iterate_coop(budget, stage_done);
     if (streamed) return iterate_streamed(budget, stage_done);
     if (trans) return iterate_transposed(budget, stage_done);
     if (pro) return iterate_prologue(budget, stage_done);
@@ -1058,6 +1079,36 @@ struct NttJob {
     }
     *stage_done = stop || t >= cfg.max_iters;
     if (stop) iters[l - 1] = t;
+    return NTT_OK;
+  }
+
+  // MU iterations of a stage in cooperative whole-stage launches (X, H and W on chip);
+  // W, H and W^T W are read at the start of a launch and written at its end, so launches
+  // of a few iterations each continue one another.  A barrier time-out sets ints[8].
+  ntt_status iterate_coop(int budget, bool* stage_done) {
+    const ntt_config& cfg = p->cfg;
+    const Stage& s = st();
+    const int block = std::min(budget, cfg.max_iters - t);
+    if (block > 0) {
+      CoopArgs a{};
+      a.X = X;
+      a.W = W;
+      a.H = H;
+      a.GW = c.gw();
+      a.part = c.part();
+      a.red = c.red();
+      a.flags = c.at<unsigned>(p->off_coop);
+      a.status = c.ints() + 8;
+      a.m = (int)s.m;
+      a.r = s.r;
+      a.k = s.k;
+      a.iters = block;
+      a.eps = (float)cfg.eps;
+      HIP_TRY(launch_stage_coop(a, s.coop_ng, s.coop_G, c.s));
+      t += block;
+      final_known = false;
+    }
+    *stage_done = t >= cfg.max_iters;
     return NTT_OK;
   }
 
@@ -1343,7 +1394,10 @@ extern "C" ntt_status ntt_decompose(ntt_plan_t p, void* stream, void* workspace,
   }
   std::vector<double> sc((size_t)SCAL_COUNT * (d - 1), 0.0);
   if (report) HIP_TRY(job.fetch_scalars(sc.data()));
+  int coop_status = 0;
+  HIP_TRY(hipMemcpyAsync(&coop_status, job.c.ints() + 8, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (coop_status != 0) return fail(NTT_ERR_DEVICE, "a cooperative stage's grid barrier timed out");
   if (report) {
     ntt_report rep;
     job.fill_report(sc.data(), &rep);
@@ -1531,6 +1585,7 @@ extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_
       delete b;
       return st;
     }
+    p->coop_allowed = false;  // problems run concurrently on several streams
     b->plans.push_back(p);
     b->ws_off.push_back(off);
     off = align_up(off + p->total, 256);
@@ -1832,6 +1887,7 @@ extern "C" ntt_status ntt_server_submit(ntt_server_t sv, const ntt_request* rq, 
   ntt_plan_t p = nullptr;
   ntt_status st = ntt_plan(&c, &p);
   if (st != NTT_OK) return st;
+  p->coop_allowed = false;  // requests run concurrently on several streams
   auto* q = new Request();
   q->id = sv->next_id++;
   q->plan = p;

@@ -66,6 +66,23 @@ struct StageArgs {
   float eps;
 };
 
+// A whole stage of MU iterations in one cooperative launch (m <= 256, r <= 16, k <= 32768):
+// G workgroups of 16 NG columns each, X and H on chip for all iterations.
+struct CoopArgs {
+  const float* X;    // m x k
+  float* W;          // m x r, read at entry, written at exit
+  float* H;          // r x k, read at entry, written at exit
+  float* GW;         // 16 x 16 W^T W (FP32), read at entry, written at exit
+  float* part;       // G x (m r + r r) partials
+  double* red;       // m r + r r sums (FP64)
+  unsigned* flags;   // barrier flags, 32 per workgroup (zeroed by the launcher)
+  int* status;       // set to 1 when a barrier timed out
+  int m, r;
+  int64_t k;
+  int iters;
+  float eps;
+};
+
 // Work-list of up to NTT_STAGE_LIST small stages passed by value as a kernel argument.
 #define NTT_STAGE_LIST 64
 struct StageList {
@@ -161,6 +178,13 @@ hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
 int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)
 hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s);
 hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s);
+// Cooperative whole-stage kernel: eligibility, 16-column groups per workgroup, grid, the
+// largest grid the device holds at once for that instance (0 when unknown), and the launch.
+bool stage_coop_ok(int64_t m, int64_t k, int r);
+int stage_coop_ng(int64_t k);
+int stage_coop_grid(int64_t k, int ng);
+int stage_coop_max_grid(int ng);
+hipError_t launch_stage_coop(const CoopArgs& c, int ng, int G, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s);
 // X H^T and H H^T partials alone (column chunks of `chunk`), as the generic pass writes them

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 
+#include "ntt_device.h"
 #include "ntt_internal.h"
 
 // Tuning knobs (compile-time): minimum waves per SIMD requested from the
@@ -33,81 +34,6 @@
 #endif
 
 namespace ntt {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// D[4*(l/16)+i][l%16] += sum_s A[l%16][s] * B[s][l%16]; A from lane a+16s, B from lane n+16s.
-__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Order LDS accesses of one wavefront (LDS is in order per wave; this stops the
-// compiler from moving accesses across the point).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// `v` where `ok`, else 0, for a value loaded from a clamped (always valid) address.
-// Written as a multiply rather than a select so that the load stays unconditional: a
-// select lets the compiler sink the load into a branch that waits for every memory
-// operation in flight, which serialises loads and defeats prefetching.
-__device__ __forceinline__ float zmask(float v, bool ok) { return v * (ok ? 1.f : 0.f); }
-__device__ __forceinline__ double zmask(double v, bool ok) { return v * (ok ? 1.0 : 0.0); }
-
-__device__ __forceinline__ v4d mfma16_f64(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// One row of the W-update in FP64 on FP32 data (shared by k_wupdate and the pass
-// prologues, so that both give the same bits): out[c] = max(0, w[c] n[c] / (sum_q w[q]
-// G_H[q][c] + eps)) for c < r, 0 beyond; *dot accumulates <out, n>.
-template <int RB>
-__device__ __forceinline__ void wupdate_row(const float (&wrow)[RB], const double (&nrow)[RB],
-                                            const double (*sGH)[RB + 1], int r, float eps,
-                                            float* out, double* dot) {
-#pragma unroll
-  for (int c = 0; c < RB; ++c) {
-    double dw = 0.0;
-#pragma unroll
-    for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
-    const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)eps));
-    const float wf = (c < r) ? (float)wn : 0.f;
-    out[c] = wf;
-    *dot += (double)wf * nrow[c];
-  }
-}
-
-// Wavefront w's part of the Gram of the rows in LDS (FP64 MFMA, 16 x 16 x 4 tiles): rows
-// 64 w + 4 st + (0..3) for st = 0, 1, ..., in order, stopping at NROWS (rows from the
-// first zero row on contribute exact zeros, so stopping early does not change the bits).
-template <int RB, int NT, int NROWS>
-__device__ __forceinline__ void gram_rows_f64(const float (*sWc)[RB + 1], v4d (&acc)[NT][NT],
-                                              int w, int a, int b) {
-#pragma unroll 4
-  for (int st = 0; st < 16; ++st) {
-    if (64 * w + 4 * st >= NROWS) break;
-    const int row = 64 * w + 4 * st + b;
-    double opnd[NT];
-#pragma unroll
-    for (int h = 0; h < NT; ++h) {
-      const int c = 16 * h + a;
-      opnd[h] = (c < RB) ? (double)sWc[row][c < RB ? c : 0] : 0.0;
-    }
-#pragma unroll
-    for (int h = 0; h < NT; ++h)
-#pragma unroll
-      for (int q = 0; q < NT; ++q) acc[h][q] = mfma16_f64(opnd[h], opnd[q], acc[h][q]);
-  }
-}
-
 
 // ------------------------------------------------------------------ SplitMix64 init
 // Value i of stream `tag`: SplitMix64 finaliser of seed + GAMMA (tag 2^32 + i + 1);
@@ -225,15 +151,6 @@ __global__ __launch_bounds__(256) void k_gram_w(const float* __restrict__ W, int
 }
 
 // ------------------------------------------------------------------ fused MU pass
-// x / y by the hardware reciprocal and one Newton-Raphson correction
-// (q0 = x r, e = x - y q0, q = q0 + e r): within about 1 ulp for normal y.
-__device__ __forceinline__ float fast_div(float x, float y) {
-  const float r = __builtin_amdgcn_rcpf(y);
-  const float q0 = x * r;
-  const float e = fmaf(-y, q0, x);
-  return fmaf(e, r, q0);
-}
-
 // X element loads: FP32 storage, or the BF16 shadow (widened exactly to FP32).
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 

@@ -36,6 +36,7 @@ NTT_STRICT_RANKS = 1
 NTT_VALIDATE_INPUT = 2
 NTT_RECORD_OBJECTIVE = 4
 NTT_PROFILE = 8
+NTT_NO_COOP = 16
 
 EXPORTED = [
     "ntt_plan", "ntt_plan_workspace", "ntt_decompose", "ntt_tt_workspace", "ntt_reconstruct",

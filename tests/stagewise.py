@@ -18,14 +18,15 @@ from parity import cols_rel, rows_rel
 
 
 def stagewise_parity(ntt, to_dev, to_host, A, ranks, T, seed, sweep_cores, snaps=None,
-                     objective_every=0, eps=1e-12, say=print, first_stage_ref=None):
+                     objective_every=0, eps=1e-12, say=print, first_stage_ref=None, flags=0):
     """Per-iterate parity of every stage of the sweep of ``A`` at the effective ``ranks``.
 
     Returns a list of per-stage dicts: the worst row / column error over ``snaps`` (default
     (T,)), and with ``objective_every`` the worst relative objective error of every such
     iterate from a trace-recording run (the GPU's trace launch) against the oracle's.
     ``first_stage_ref``: the oracle's stage-1 result when already computed (stage 1's input
-    is the tensor itself, the same on both sides), with those snapshots and objectives."""
+    is the tensor itself, the same on both sides), with those snapshots and objectives.
+    ``flags`` go to the GPU's two-way runs (the launch mode of the sweep under test)."""
     snaps = tuple(snaps) if snaps else (T,)
     assert T in snaps
     dims = list(A.shape)
@@ -44,7 +45,8 @@ def stagewise_parity(ntt, to_dev, to_host, A, ranks, T, seed, sweep_cores, snaps
         Xd = to_dev(X)
         worst = 0.0
         for t in snaps:
-            g = ntt.decompose(Xd, (1, r, 1), t, eps=eps, init_W=[to_dev(W0)], init_H=[to_dev(H0)])
+            g = ntt.decompose(Xd, (1, r, 1), t, eps=eps, init_W=[to_dev(W0)], init_H=[to_dev(H0)],
+                              flags=flags)
             Wg = to_host(g.cores[0]).reshape(m, r)
             Hg = to_host(g.cores[1]).reshape(r, k)
             Wo, Ho = ref["snaps"][t]

@@ -234,7 +234,7 @@ def test_wide_pass_prologue_equals_separate_w_update_bitwise(m, k, r):
     X = dev(rng.random((m, k)) + 0.01)
     T = 30
     rec = ntt.decompose(X, (1, r, 1), T, seed=5, record_objective=True)
-    fast = ntt.decompose(X, (1, r, 1), T, seed=5)
+    fast = ntt.decompose(X, (1, r, 1), T, seed=5, flags=ntt.NTT_NO_COOP)
     for cr, cf in zip(rec.cores, fast.cores):
         assert torch.equal(cr, cf)
 
@@ -256,6 +256,41 @@ def test_degenerate_shapes_match_oracle(m, k, r):
     res = ntt.decompose(dev(X), (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)])
     assert rows_rel(host(res.cores[0]).reshape(m, r), ref["W"]) <= TOL
     assert cols_rel(host(res.cores[1]).reshape(r, k), ref["H"]) <= TOL
+
+
+@pytest.mark.parametrize("m,k,r", [
+    (256, 32768, 8),   # the 32^5 workload's second unfolding: 256 workgroups of 128 columns
+    (256, 1024, 8),    # its third: 64 workgroups of 16 columns
+    (200, 20001, 16),  # ragged rows, a ragged last workgroup
+    (130, 5000, 13), (33, 777, 5), (7, 100, 3), (256, 65, 16), (1, 3000, 1),
+])
+def test_cooperative_stage_matches_oracle_and_the_per_pass_launches(m, k, r):
+    # m <= 256, r <= 16, 64 < k <= 32768 run as one cooperative launch per stage (X and H
+    # on chip, grid barriers between the H-update, the reduction and the W-update)
+    say(f"case: cooperative stage m={m} k={k} r={r}")
+    rng = np.random.default_rng(m * 31 + k + r)
+    X = (rng.random((m, k)) + 0.05).astype(np.float32)
+    W0, H0 = O.init_factors(9, 1, m, r, k)
+    T = 50
+    ref = O.mu_nmf(X.astype(np.float64), W0, H0, T, snapshots=(1, 7, T))
+    Xd = dev(X)
+    for t in (1, 7, T):
+        g = ntt.decompose(Xd, (1, r, 1), t, init_W=[dev(W0)], init_H=[dev(H0)])
+        Wg, Hg = host(g.cores[0]).reshape(m, r), host(g.cores[1]).reshape(r, k)
+        Wo, Ho = ref["snaps"][t]
+        ew, eh = rows_rel(Wg, Wo), cols_rel(Hg, Ho)
+        say(f"  t={t}: W rows {ew:.2e} H columns {eh:.2e}")
+        assert ew <= TOL and eh <= TOL, (t, ew, eh)
+        assert Wg.min() >= 0 and Hg.min() >= 0
+    # the same iterates as the one-launch-per-pass path (within the bar), bitwise
+    # reproducible, and the report's objective that of the returned factors
+    per = ntt.decompose(Xd, (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)], flags=ntt.NTT_NO_COOP)
+    again = ntt.decompose(Xd, (1, r, 1), T, init_W=[dev(W0)], init_H=[dev(H0)])
+    assert rows_rel(host(per.cores[0]).reshape(m, r), Wo) <= TOL
+    for x, y in zip(g.cores, again.cores):
+        assert torch.equal(x, y)
+    f = O.objective(X.astype(np.float64), Wg, Hg)
+    assert obj_close(g.report["objective"][0], f, ref["norm_x"] ** 2)
 
 
 def test_zero_rows_and_columns_match_oracle():
@@ -660,7 +695,8 @@ def test_batched_results_equal_standalone_results_bitwise():
     cores, reps, _ = ntt.decompose_batch(tensors, [rk for _, rk, _ in probs], T,
                                          [sd for _, _, sd in probs])
     for (dm, rk, sd), A, cs, rep in zip(probs, tensors, cores, reps):
-        alone = ntt.decompose(A, rk, T, seed=sd)
+        # batched problems keep one launch per pass, as a standalone run with NTT_NO_COOP
+        alone = ntt.decompose(A, rk, T, seed=sd, flags=ntt.NTT_NO_COOP)
         for x, y in zip(cs, alone.cores):
             assert torch.equal(x, y), (dm, rk)
         assert rep["iters"] == [T] * (len(dm) - 1)
@@ -716,11 +752,14 @@ def test_serving_results_equal_standalone_results_and_budget_defers_admission():
     arena = 2 * max(need) + 4096
     srv = ntt.Server(arena, max_slots=4, iters_per_tick=25)
     ids = [srv.submit(_pinned(a), rk, T, seed=sd) for a, (dm, rk, sd) in zip(host_t, probs)]
-    alone = [ntt.decompose(dev(A), rk, T, seed=sd) for A, (dm, rk, sd) in zip(host_t, probs)]
+    # served requests keep one launch per pass, as a standalone run with NTT_NO_COOP
+    alone = [ntt.decompose(dev(A), rk, T, seed=sd, flags=ntt.NTT_NO_COOP)
+             for A, (dm, rk, sd) in zip(host_t, probs)]
     # the standalone results against the oracle, per iterate stage by stage: a served
     # result equal to its standalone result bit for bit is then within the bar too
     for A, (dm, rk, sd), al in zip(host_t, probs, alone):
-        for st_ in stagewise_parity(ntt, dev, host, A, al.ranks, T, sd, al.cores, say=say):
+        for st_ in stagewise_parity(ntt, dev, host, A, al.ranks, T, sd, al.cores, say=say,
+                                    flags=ntt.NTT_NO_COOP):
             assert st_["worst"] <= TOL, (dm, st_)
     pending = dict(zip(ids, range(len(ids))))
     max_active = 0
@@ -758,7 +797,7 @@ def test_serving_rejects_oversize_and_cancels():
     srv.release(r1)  # cancel while running (or queued)
     while srv.info(r2)["state"] != ntt.NTT_REQ_DONE:
         srv.tick()
-    alone = ntt.decompose(dev(a), (1, 3, 4, 1), 30, seed=3)
+    alone = ntt.decompose(dev(a), (1, 3, 4, 1), 30, seed=3, flags=ntt.NTT_NO_COOP)
     for x, y in zip(srv.cores(r2), alone.cores):
         assert torch.equal(x, y)
     srv.release(r2)
@@ -789,7 +828,7 @@ def test_serving_bf16_results_match_oracle_error_and_standalone_bits():
             dm, rk, sd = probs[i]
             A = host_t[i]
             served = srv.cores(rid)
-            alone = ntt.decompose(dev(A), rk, T, seed=sd, **kw)
+            alone = ntt.decompose(dev(A), rk, T, seed=sd, flags=ntt.NTT_NO_COOP, **kw)
             for x, y in zip(served, alone.cores):
                 assert torch.equal(x, y), probs[i]
             ref = O.ntt_decompose(A, rk, T, seed=sd)
