@@ -1519,6 +1519,278 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LW(PassArgs p) {
   }
 }
 
+// ------------------------------------------------------------------ wide row-split pass, BF16 MFMA
+// The wide row-split update pass for a BF16 copy of X (precision mode) on BF16 matrix
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  X stays BF16 as loaded; the
+// FP32 factors enter each product as two BF16 terms, f = hi + lo with hi = bf16(f) and
+// lo = bf16(f - hi) (round to nearest even), so that W^T X and X H_new^T carry the
+// rounding of X alone (every BF16 x BF16 product is exact in FP32).  D_H = G_W H, the
+// epilogue and H_new H_new^T stay FP32 as in k_mu_pass_LW, whose structure and partials
+// this pass shares, in steps of 128 columns so that every load still covers 4 rows x
+// 256 contiguous bytes:
+//   lane (a, b) holds X[row0 + 4i + b][j0 + 8a .. 8a + 7] for the row quads i;
+//   W^T X (K = rows): for column set q (columns j0 + 8a + q, q = 0..7) the K slot 8b + u
+//   of an MFMA is row row0 + 32 gq + 4u + b (u = 0..7, row quads 8 gq .. 8 gq + 7), so
+//   the lane's own values of eight row quads are its B operand; W^T is laid out to match;
+//   epilogue: wave q' < 4 takes column sets q' and q' + 4;
+//   X H_new^T (K = columns): each 16-row block goes through a per-wave BF16 tile; lane
+//   (a, b) reads X[row a][c0 + 8b .. 8b + 7] and H_new[a][c0 + 8b ..] (c0 = 0, 32, 64, 96).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_bits_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+// hi and lo BF16 parts of eight FP32 values, packed two per 32-bit word
+__device__ __forceinline__ void split_bf8(const float (&f)[8], bf8& hi, bf8& lo) {
+  u4v h, l;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t h0 = bf16_bits_rne(f[2 * j]), h1 = bf16_bits_rne(f[2 * j + 1]);
+    const uint32_t l0 = bf16_bits_rne(f[2 * j] - __uint_as_float(h0 << 16));
+    const uint32_t l1 = bf16_bits_rne(f[2 * j + 1] - __uint_as_float(h1 << 16));
+    h[j] = h0 | (h1 << 16);
+    l[j] = l0 | (l1 << 16);
+  }
+  hi = __builtin_bit_cast(bf8, h);
+  lo = __builtin_bit_cast(bf8, l);
+}
+__device__ __forceinline__ v4f mfma32bf(const bf8& a, const bf8& b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// BF16 value q (0..7) of a raw 8 x BF16 load
+__device__ __forceinline__ uint32_t bf_at(const uint4& v, int q) {
+  const uint32_t w = (q < 2) ? v.x : (q < 4) ? v.y : (q < 6) ? v.z : v.w;
+  return (q & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+template <int MBW, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mu_pass_LWB(PassArgs p) {
+  constexpr int NQ = 4 * MBW;  // row quads per wave
+  constexpr int NG8 = NQ / 8;  // MFMA row groups (eight row quads each) per wave
+  constexpr int SN = 20;       // row stride of the W^T X parts: [column index][rank]
+  constexpr int ST = 132;      // row stride of the 128-column H_new tile (floats)
+  constexpr int SB = 136;      // row stride of the per-wave BF16 X tile (halves, 16-byte rows)
+  static_assert(NW >= 4 && NQ % 8 == 0, "four epilogue waves; whole row groups");
+  __shared__ __attribute__((aligned(16))) float sNH[8][NW][16 * SN];
+  __shared__ __attribute__((aligned(16))) float sHn[16 * ST];
+  __shared__ __attribute__((aligned(16))) uint16_t sT[NW][16 * SB];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = lane & 15, b = lane >> 4;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int row0 = w * 16 * MBW;
+
+  const int64_t nsteps = (k + 127) >> 7;
+  const int64_t nblk = gridDim.x;
+  const bool vec_ok = ((k & 7) == 0) && ((reinterpret_cast<uintptr_t>(p.Xb) & 15) == 0) &&
+                      ((reinterpret_cast<uintptr_t>(p.H) & 15) == 0);
+  int64_t xrow[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) xrow[i] = (int64_t)min(row0 + 4 * i + b, m - 1) * k;
+  const float* hrow[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) hrow[kk] = p.H + (int64_t)min(4 * b + kk, r - 1) * k;
+  uint16_t* sTw = sT[w];
+
+  // raw BF16 loads of a step: X[row0 + 4i + b][j0 + 8a .. 8a + 7]; wave q' < 4 also
+  // H[4b + kk][j0 + 8a + q' + 4s] (the ragged path masks X here)
+  auto load_step = [&](int64_t st, uint4 (&x)[NQ], float (&hv)[2][4]) {
+    const int64_t j0 = st << 7;
+    if (vec_ok && (j0 + 128 <= k)) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) x[i] = *reinterpret_cast<const uint4*>(p.Xb + xrow[i] + j0 + 8 * a);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t col = j0 + 8 * a + q;
+          const uint32_t raw = p.Xb[xrow[i] + min(col, k - 1)];
+          v[q] = (col < k && row0 + 4 * i + b < m) ? raw : 0u;
+        }
+        x[i] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+      }
+    }
+    if (w < 4) {
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const int64_t colc = min(j0 + 8 * a + w + 4 * sx, k - 1);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) hv[sx][kk] = hrow[kk][colc];
+      }
+    }
+  };
+
+  // W^T as the A operand of W^T X: row group gq, K slot 8b + u <-> row row0 + 32 gq + 4u + b
+  bf8 wa_hi[NG8], wa_lo[NG8];
+#pragma unroll
+  for (int gq = 0; gq < NG8; ++gq) {
+    float f[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = row0 + 32 * gq + 4 * u + b;
+      f[u] = zmask(p.W[(int64_t)min(row, m - 1) * r + min(a, r - 1)], row < m && a < r);
+    }
+    split_bf8(f, wa_hi[gq], wa_lo[gq]);
+  }
+  float gw[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) gw[kk] = p.GW[a * 16 + 4 * b + kk];
+
+  v4f accW[MBW];
+  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // the next step's loads are issued before the current step is processed
+  uint4 xn[NQ];
+  float hn_[2][4];
+  if (blockIdx.x < nsteps) load_step(blockIdx.x, xn, hn_);
+  for (int64_t st = blockIdx.x; st < nsteps; st += nblk) {
+    const int64_t j0 = st << 7;
+    const bool full = vec_ok && (j0 + 128 <= k);
+    uint4 x[NQ];
+    float hv[2][4];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) x[i] = xn[i];
+#pragma unroll
+    for (int sx = 0; sx < 2; ++sx)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) hv[sx][kk] = hn_[sx][kk];
+    if (st + nblk < nsteps) load_step(st + nblk, xn, hn_);
+
+    // A: parts of W^T X of the eight column sets, stored as [a][rank 4b + i]
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      v4f nh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int gq = 0; gq < NG8; ++gq) {
+        u4v xb;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          xb[j] = bf_at(x[8 * gq + 2 * j], q) | (bf_at(x[8 * gq + 2 * j + 1], q) << 16);
+        const bf8 xv = __builtin_bit_cast(bf8, xb);
+        nh = mfma32bf(wa_hi[gq], xv, nh);
+        nh = mfma32bf(wa_lo[gq], xv, nh);
+      }
+      *reinterpret_cast<float4*>(&sNH[q][w][a * SN + 4 * b]) = make_float4(nh[0], nh[1], nh[2], nh[3]);
+    }
+    __syncthreads();
+
+    // B: the epilogue of column sets q = w and w + 4: columns j0 + 8a + q
+    if (w < 4) {
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const int q = w + 4 * sx;
+        float4 n4 = *reinterpret_cast<const float4*>(&sNH[q][0][a * SN + 4 * b]);
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) {
+          const float4 v = *reinterpret_cast<const float4*>(&sNH[q][ww][a * SN + 4 * b]);
+          n4.x += v.x;
+          n4.y += v.y;
+          n4.z += v.z;
+          n4.w += v.w;
+        }
+        const float nv[4] = {n4.x, n4.y, n4.z, n4.w};
+        const int64_t col = j0 + 8 * a + q;
+        float hq[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) hq[kk] = zmask(hv[sx][kk], 4 * b + kk < r && col < k);
+        v4f dh = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dh = mfma16(gw[kk], hq[kk], dh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 4 * b + i;
+          const float qv = fmaxf(0.f, fast_div(hq[i] * nv[i], dh[i] + p.eps));
+          sHn[c * ST + 8 * a + q] = (c < r) ? qv : 0.f;
+        }
+      }
+    }
+    __syncthreads();
+
+    // C: store H_new; H_new H_new^T (FP32, wave g < 4: columns 32g .. 32g + 31); X H_new^T
+    // per row block on BF16 matrix cores
+    for (int e = tid; e < 16 * 32; e += 64 * NW) {
+      const int c = e >> 5, cq = 4 * (e & 31);
+      if (c < r) {
+        const float4 v = *reinterpret_cast<const float4*>(&sHn[c * ST + cq]);
+        float* dst = p.H + (int64_t)c * k + j0 + cq;
+        if (full) {
+          *reinterpret_cast<float4*>(dst) = v;
+        } else {
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (j0 + cq + q < k) dst[q] = vv[q];
+        }
+      }
+    }
+    if (w < 4) {
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2) {
+        const float4 h = *reinterpret_cast<const float4*>(&sHn[a * ST + 32 * w + 16 * t2 + 4 * b]);
+        accG = mfma16(h.x, h.x, accG);
+        accG = mfma16(h.y, h.y, accG);
+        accG = mfma16(h.z, h.z, accG);
+        accG = mfma16(h.w, h.w, accG);
+      }
+    }
+    // H_new[a][c0 + 8b .. 8b + 7] as hi + lo BF16, the B operand of X H_new^T
+    bf8 hn_hi[4], hn_lo[4];
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
+      const float4 f0 = *reinterpret_cast<const float4*>(&sHn[a * ST + 32 * h2 + 8 * b]);
+      const float4 f1 = *reinterpret_cast<const float4*>(&sHn[a * ST + 32 * h2 + 8 * b + 4]);
+      const float f[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+      split_bf8(f, hn_hi[h2], hn_lo[h2]);
+    }
+#pragma unroll
+    for (int blk = 0; blk < MBW; ++blk) {
+      // tile row 4j + b <- row quad 4 blk + j: X[row0 + 16 blk + rho][j0 + col] (BF16)
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<uint4*>(&sTw[(4 * j + b) * SB + 8 * a]) = x[4 * blk + j];
+      wave_sync();
+#pragma unroll
+      for (int h2 = 0; h2 < 4; ++h2) {
+        const uint4 t = *reinterpret_cast<const uint4*>(&sTw[a * SB + 32 * h2 + 8 * b]);
+        const bf8 xa = __builtin_bit_cast(bf8, u4v{t.x, t.y, t.z, t.w});
+        accW[blk] = mfma32bf(xa, hn_hi[h2], accW[blk]);
+        accW[blk] = mfma32bf(xa, hn_lo[h2], accW[blk]);
+      }
+    }
+  }
+
+  // partials: this wave's rows of X H_new^T; H_new H_new^T summed over waves 0..3
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+#pragma unroll
+  for (int blk = 0; blk < MBW; ++blk)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + 16 * blk + 4 * b + i;
+      if (row < m && a < r) dst[(int64_t)row * r + a] = accW[blk][i];
+    }
+  __syncthreads();
+  float* gbuf = &sNH[0][0][0];  // 4 x 256 floats, free after the last step
+  if (w < 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gbuf[w * 256 + (4 * b + i) * 16 + a] = accG[i];
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += 64 * NW) {
+    const int c = e / r, cc = e % r;
+    dst[(int64_t)m * r + e] = ((gbuf[c * 16 + cc] + gbuf[256 + c * 16 + cc]) + gbuf[512 + c * 16 + cc]) +
+                              gbuf[768 + c * 16 + cc];
+  }
+}
+
 // ------------------------------------------------------------------ row-chunked MU pass
 // For m beyond one workgroup: rows are cut into chunks of CR = 16 MBW NW rows, chunk y
 // taken by the workgroups with blockIdx.y = y, which visit the same 16-column groups for
@@ -2906,8 +3178,13 @@ int pass_L_batch(int cls, int rp) { return (rp == 16 && cls >= 0 && cls <= 3) ? 
 
 template <int MBW, int NW>
 static hipError_t pass_LW(const PassArgs& a, int grid, hipStream_t s) {
-  if (a.Xb != nullptr) k_mu_pass_LW<MBW, NW, true><<<grid, 64 * NW, 0, s>>>(a);
-  else k_mu_pass_LW<MBW, NW, false><<<grid, 64 * NW, 0, s>>>(a);
+  // BF16 X: BF16 matrix cores for waves of 32 rows (wider waves would spill registers)
+  if (a.Xb != nullptr) {
+    if constexpr (MBW == 2) k_mu_pass_LWB<MBW, NW><<<grid, 64 * NW, 0, s>>>(a);
+    else k_mu_pass_LW<MBW, NW, true><<<grid, 64 * NW, 0, s>>>(a);
+  } else {
+    k_mu_pass_LW<MBW, NW, false><<<grid, 64 * NW, 0, s>>>(a);
+  }
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
