@@ -25,12 +25,32 @@ def progress(msg):
     """Progress of the benchmark phases (stderr; the result is the one JSON line on stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFS = 157.3
+BF16_MFMA_PEAK_TFS = 2500.0
 EXTRAS = ("precision_mode", "paper_workload", "rank_rule", "bcd", "streamed", "batched", "serving")
-# HBM bytes per launch of the stage-1 pass of the 32^5 workload (k_mu_pass_r8w<8> on 512
-# workgroups, W-update prologue): rocprofv3 FETCH_SIZE (82,023.8 KiB) and WRITE_SIZE
-# (33,408.7 KiB) per dispatch, scaled by what the same counters read for a plain 1 GiB
-# copy (x2.00, x1.00).  Taken on the current pass kernel; re-measure when it changes.
-MEASURED_TRAFFIC = {"tt32x5_r8": 167.985e6 + 34.210e6}
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 summaries under
+    profiles/ (a line `traffic: kernel=... workload=... bytes=... source=... source_sha16=...`,
+    the kernel name written without spaces,
+    FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings).  None when no summary
+    has it, or when the kernel's source file changed since the counters were taken."""
+    import glob
+    import hashlib
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line[len("traffic:"):].split() if "=" in t)
+            if kv.get("kernel") != kernel.replace(" ", "") or kv.get("workload") != workload:
+                continue
+            src = os.path.join(ROOT, kv.get("source", ""))
+            if not os.path.isfile(src):
+                return None
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            return float(kv["bytes"]) if sha == kv.get("source_sha16") else None
+    return None
 
 
 def parse():
@@ -53,31 +73,41 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(A, w, seconds, bcd_seconds=0.0):
-    """The FP64 oracle on this host, on a bounded sample: MU iterations of stage 1."""
-    import numpy as np
+def _oracle_mu_rate(X, W, H, r, eps, seconds):
+    """MU iterations of the oracle on X for about `seconds`: (iterations, seconds, GFLOP/s)."""
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
-    X = A.reshape(A.shape[0], -1).astype(np.float64)
     m, k = X.shape
-    r = w.target_ranks[1]
-    W, H = O.init_factors(w.seed, 1, m, r, k)
     t0 = time.perf_counter()
     n = 0
     while True:
-        W, H = O.mu_step(X, W, H, w.eps)
+        W, H = O.mu_step(X, W, H, eps)
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds or n >= 500:
             break
-    flops = n * (4.0 * m * k * r + 4.0 * (m + k) * r * r)
-    out = {"value": flops / el / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+    return n, el, n * (4.0 * m * k * r + 4.0 * (m + k) * r * r) / el / 1e9
+
+
+def cpu_baseline(A, w, seconds, bcd_seconds=0.0):
+    """The FP64 oracle on this host, on a bounded sample: MU iterations of stage 1 with
+    all host cores, then with one thread."""
+    import numpy as np
+    import oracle as O
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    X = A.reshape(A.shape[0], -1).astype(np.float64)
+    m, k = X.shape
+    r = w.target_ranks[1]
+    W, H = O.init_factors(w.seed, 1, m, r, k)
+    n, el, rate = _oracle_mu_rate(X, W, H, r, w.eps, seconds)
+    with threadpool_limits(limits=1):
+        n1, el1, rate1 = _oracle_mu_rate(X, W, H, r, w.eps, seconds / 3)
+    out = {"value": rate, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
            "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}) of the same workload, "
-                     f"NumPy FP64, {el:.1f} s"}
+                     f"NumPy FP64, {el:.1f} s",
+           "one_thread": {"value": rate1, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                          "sample": f"{n1} MU iterations of the same stage 1, NumPy FP64 limited to "
+                                    f"one thread, {el1:.1f} s"}}
     if bcd_seconds > 0:
         # the BCD oracle (Alg.3) on the same first unfolding: ms per iteration
         W0, H0 = O.init_factors(w.seed, 1, m, r, k)
@@ -92,12 +122,19 @@ def cpu_baseline(A, w, seconds, bcd_seconds=0.0):
     return out
 
 
-def precision_mode(ntt, S, torch):
-    """128^4 rank-16 workload: FP32 sweep vs BF16 mode (last 20 iterations FP32)."""
+def precision_mode(ntt, S, torch, cpu_seconds=0.0):
+    """128^4 rank-16 workload: FP32 sweep vs BF16 mode (last 20 iterations FP32).  For each
+    mode, the roofline of the dominant kernel, the stage-1 pass, from HIP events around each
+    launch of a profiled sweep (BF16 mode: every iteration on the BF16 copy); with
+    cpu_seconds > 0, the oracle's MU iterations on the same first unfolding."""
+    import numpy as np
     w = S.workload("tt128x4_r16")
-    A = torch.from_numpy(w.tensor()).cuda()
+    A_host = w.tensor()
+    A = torch.from_numpy(A_host).cuda()
     out = {"workload": f"{w.name}: {w.note}"}
     progress("precision mode: 128^4 tensor generated")
+    m, k, r = w.dims[0], int(np.prod(w.dims[1:])), w.target_ranks[1]
+    kernels = {"fp32": "k_mu_pass_LW<2, 4, false>", "bf16": "k_mu_pass_LWB<2, 4>"}
     for name, prec in (("fp32", ntt.NTT_PREC_FP32), ("bf16", ntt.NTT_PREC_BF16_MIXED)):
         plan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed, precision=prec,
                         fp32_tail_iters=w.fp32_tail)
@@ -107,13 +144,48 @@ def precision_mode(ntt, S, torch):
         res = ntt.decompose(A, w.target_ranks, w.iters, plan=plan, cores=res.cores)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        out[name] = {"ms": ms, "gflop_per_s": res.report["total_gflop"] / (ms * 1e-3),
+        gflop = res.report["total_gflop"]
+        out[name] = {"ms": ms, "gflop_per_s": gflop / (ms * 1e-3),
+                     "mfma_frac_fp32_peak": gflop / (ms * 1e-3) / (FP32_MFMA_PEAK_TFS * 1e3),
                      "decomps_per_s": 1e3 / ms, "rel_error": ntt.rel_error(A, res.cores),
                      "stage_ms": res.report["ms"]}
-        progress(f"precision mode: {name} {ms:.1f} ms")
+        pplan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed, precision=prec,
+                         fp32_tail_iters=0, flags=ntt.NTT_PROFILE)
+        prep = ntt.decompose(A, w.target_ranks, w.iters, plan=pplan)
+        pass_ms = prep.report["pass_ms"][0]
+        xbytes = 2.0 if name == "bf16" else 4.0
+        bytes_launch = xbytes * m * k + 8.0 * r * k + 4.0 * m * r
+        flop_launch = 4.0 * m * k * r + 4.0 * (m + k) * r * r
+        ach = bytes_launch / (pass_ms * 1e-3) / 1e9
+        kern = kernels[name]
+        traffic = profiled_traffic(kern, w.name)
+        out[name]["roofline"] = {
+            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"{kern} stage 1 ({m}x{k}, r={r})", "pass_ms": pass_ms,
+            "bytes_per_launch": bytes_launch,
+            "tflops": flop_launch / (pass_ms * 1e-3) / 1e12,
+            "mfma_peak_tflops": BF16_MFMA_PEAK_TFS if name == "bf16" else FP32_MFMA_PEAK_TFS}
+        progress(f"precision mode: {name} {ms:.1f} ms, stage-1 pass {pass_ms * 1e3:.1f} us "
+                 f"({ach:.0f} GB/s)")
     out["bf16_speedup"] = out["fp32"]["ms"] / out["bf16"]["ms"]
     out["rel_error_gap"] = abs(out["bf16"]["rel_error"] - out["fp32"]["rel_error"])
     del A
+    if cpu_seconds > 0:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        import oracle as O
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        X = A_host.reshape(m, k).astype(np.float64)
+        W0, H0 = O.init_factors(w.seed, 1, m, r, k)
+        n, el, rate = _oracle_mu_rate(X, W0, H0, r, w.eps, cpu_seconds)
+        with threadpool_limits(limits=1):
+            n1, el1, rate1 = _oracle_mu_rate(X, W0, H0, r, w.eps, cpu_seconds / 2)
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} MU iterations of stage 1 ({m}x{k}, r={r}), NumPy FP64, {el:.1f} s",
+            "one_thread": {"value": rate1, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                           "sample": f"{n1} MU iterations of stage 1, one thread, {el1:.1f} s"}}
+        del X
     return out
 
 
@@ -440,7 +512,8 @@ def main():
         "rel_error": err,
         "stage_ms": rep_graph["ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(w.name),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("k_mu_pass_r8w<8, false>", w.name),
                      "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
                      "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
     }
@@ -452,7 +525,7 @@ def main():
         del A
         torch.cuda.empty_cache()
     if "precision_mode" in extras:
-        out["precision_mode"] = precision_mode(ntt, S, torch)
+        out["precision_mode"] = precision_mode(ntt, S, torch, 0.0 if args.no_cpu_baseline else 8.0)
         torch.cuda.empty_cache()
     if "paper_workload" in extras:
         out["paper_workload"] = paper_workload(ntt, S, torch)
