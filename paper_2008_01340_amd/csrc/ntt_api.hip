@@ -1803,16 +1803,86 @@ struct ntt_server_s {
   int64_t next_id = 1;
   double t0 = 0;
   std::vector<StageArgs> list_host;
+  // the grouped launches of a tick as one graph: one kernel node per register class, its
+  // work-list (a kernel argument by value) and grid set before each replay.  A ring of
+  // executable instances, each reused only once its previous replay has completed, so an
+  // update never touches the arguments of a replay still queued or running.
+  static const int kRing = 4;
+  hipGraph_t group_graph = nullptr;
+  hipGraphNode_t group_node[3] = {};
+  hipGraphExec_t group_exec[kRing] = {};
+  hipEvent_t ring_ev[kRing] = {};
+  bool ring_used[kRing] = {};
+  int ring_next = 0;
   ~ntt_server_s() {
     for (auto& kv : all) {
       if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
       delete kv.second->plan;
       delete kv.second;
     }
+    for (int i = 0; i < kRing; ++i) {
+      if (group_exec[i]) (void)hipGraphExecDestroy(group_exec[i]);
+      if (ring_ev[i]) (void)hipEventDestroy(ring_ev[i]);
+    }
+    if (group_graph) (void)hipGraphDestroy(group_graph);
     for (auto q : streams) (void)hipStreamDestroy(q);
     if (group_ev) (void)hipEventDestroy(group_ev);
   }
 };
+
+static const int kGroupNG[3] = {1, 2, 4};
+
+// kernel-node parameters of register class c running list L (one workgroup per entry,
+// at least one)
+static hipKernelNodeParams group_params(int c, StageList* L, void** args) {
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(stage_1wg_list_kernel(kGroupNG[c]));
+  kp.gridDim = dim3((unsigned)std::max(1, L->count));
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = 0;
+  args[0] = L;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+// the grouped-launch graph (three independent kernel nodes) and its ring of instances,
+// built on first use
+static hipError_t server_group_graph(ntt_server_s* sv) {
+  if (sv->group_graph) return hipSuccess;
+  hipError_t e = hipGraphCreate(&sv->group_graph, 0);
+  if (e != hipSuccess) return e;
+  for (int c = 0; c < 3; ++c) {
+    StageList empty{};
+    empty.count = 0;
+    void* args[1];
+    hipKernelNodeParams kp = group_params(c, &empty, args);
+    e = hipGraphAddKernelNode(&sv->group_node[c], sv->group_graph, nullptr, 0, &kp);
+    if (e != hipSuccess) return e;
+  }
+  for (int i = 0; i < ntt_server_s::kRing; ++i) {
+    e = hipGraphInstantiate(&sv->group_exec[i], sv->group_graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&sv->ring_ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// an instance whose previous replay has completed: the first idle one from the ring's
+// cursor, else the cursor's own once its replay ends (the host waits for that replay only)
+static hipError_t server_ring_slot(ntt_server_s* sv, int* slot) {
+  const int R = ntt_server_s::kRing;
+  for (int d = 0; d < R; ++d) {
+    const int i = (sv->ring_next + d) % R;
+    if (!sv->ring_used[i]) { *slot = i; return hipSuccess; }
+    const hipError_t q = hipEventQuery(sv->ring_ev[i]);
+    if (q == hipSuccess) { *slot = i; return hipSuccess; }
+    if (q != hipErrorNotReady) return q;
+  }
+  *slot = sv->ring_next;
+  return hipEventSynchronize(sv->ring_ev[sv->ring_next]);
+}
 
 // input + workspace and the slot go back when a request finishes; cores on release
 static void server_release_work(ntt_server_s* sv, Request* q) {
@@ -2030,7 +2100,20 @@ extern "C" ntt_status ntt_server_tick(ntt_server_t sv, int32_t* n_active, int32_
       L.a[L.count++] = sv->list_host[i];
     }
     for (int c = 0; c < 3; ++c)
-      HIP_TRY(launch_stage_1wg_list(lists[c], c == 0 ? 1 : (c == 1 ? 2 : 4), sv->group_stream));
+      if (lists[c].count > NTT_STAGE_LIST) return fail(NTT_ERR_INVALID_ARG, "too many grouped stages");
+    // one graph replay: each node's work-list and grid set for this tick
+    HIP_TRY(server_group_graph(sv));
+    int slot = 0;
+    HIP_TRY(server_ring_slot(sv, &slot));
+    for (int c = 0; c < 3; ++c) {
+      void* args[1];
+      hipKernelNodeParams kp = group_params(c, &lists[c], args);
+      HIP_TRY(hipGraphExecKernelNodeSetParams(sv->group_exec[slot], sv->group_node[c], &kp));
+    }
+    HIP_TRY(hipGraphLaunch(sv->group_exec[slot], sv->group_stream));
+    HIP_TRY(hipEventRecord(sv->ring_ev[slot], sv->group_stream));
+    sv->ring_used[slot] = true;
+    sv->ring_next = (slot + 1) % ntt_server_s::kRing;
     HIP_TRY(hipEventRecord(sv->group_ev, sv->group_stream));
     for (Request* q : grouped) {
       NttJob& j = q->job;

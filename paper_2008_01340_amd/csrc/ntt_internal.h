@@ -178,6 +178,9 @@ hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
 int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)
 hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s);
 hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s);
+// the grouped kernel instance for ng groups (a graph kernel node's function); its list
+// may be empty (the node then runs one workgroup that returns at once)
+const void* stage_1wg_list_kernel(int ng);
 // Cooperative whole-stage kernel: eligibility, 16-column groups per workgroup, grid, the
 // largest grid the device holds at once for that instance (0 when unknown), and the launch.
 bool stage_coop_ok(int64_t m, int64_t k, int r);

@@ -2158,6 +2158,7 @@ __global__ __launch_bounds__(256) void k_stage_1wg_grouped(const StageArgs* __re
 // grouped launch with the work-list passed by value (at most NTT_STAGE_LIST entries)
 template <int NG>
 __global__ __launch_bounds__(256) void k_stage_1wg_list(StageList L) {
+  if ((int)blockIdx.x >= L.count) return;  // a graph node may be launched with an empty list
   const StageArgs s = L.a[blockIdx.x];
   stage_1wg_body<NG>(s);
 }
@@ -3280,6 +3281,13 @@ hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s) {
 }
 
 int stage_1wg_ng(int64_t k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
+
+const void* stage_1wg_list_kernel(int ng) {
+  if (ng == 1) return reinterpret_cast<const void*>(k_stage_1wg_list<1>);
+  if (ng == 2) return reinterpret_cast<const void*>(k_stage_1wg_list<2>);
+  if (ng == 4) return reinterpret_cast<const void*>(k_stage_1wg_list<4>);
+  return nullptr;
+}
 
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
                                bool resid, hipStream_t s) {
