@@ -23,8 +23,14 @@
  *   - "device" pointers point into GPU memory of the current HIP device; "host"
  *     pointers into CPU memory.  All buffers are owned by the caller; the library
  *     keeps no pointer after a call returns.
- *   - The library allocates no device memory itself: ntt_decompose and ntt_rel_error
- *     take a caller-provided device workspace whose size the query functions report.
+ *   - The library allocates no device memory for data itself: ntt_decompose and
+ *     ntt_rel_error take a caller-provided device workspace whose size the query
+ *     functions report, and the server works inside the caller's arena.  Exceptions:
+ *     the rank rule (rank_eps > 0) creates one rocBLAS handle per plan on first use
+ *     (the eigensolver's scratch is set to a region of the workspace, but creating a
+ *     handle may allocate rocBLAS's own small device state); the streams, events and
+ *     graphs a plan, batch or server creates hold HIP runtime resources; and
+ *     ntt_rel_error_static uses a fixed 8 MiB device array of the library's.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
  *     enqueued on it; every function below returns after its work has completed.
  *   - Errors come back as ntt_status codes; no C++ exception crosses the ABI.  On
@@ -146,8 +152,9 @@ typedef struct {
 
 typedef struct ntt_plan_s* ntt_plan_t;
 
-/* Build a plan from a config (host only, no device work).  Validates the shape
- * (d in 2..16, n_k >= 1, r_0 = r_d = 1, product of dims below 2^62), clamps ranks to
+/* Build a plan for the sweep of Alg.2 (Sec. III-A), with MU (the NMF timed in Sec. IV-B)
+ * or the BCD of Alg.3 (Sec. III-B) as the NMF, from a config (host only, no device work).  Validates the shape
+ * (d in 2..16, n_k >= 1, r_0 = r_d = 1, product of dims at most 2^44), clamps ranks to
  * r_l <= min(r_{l-1} n_l, n_{l+1}...n_d) left to right (or fails with
  * NTT_ERR_RANK_INFEASIBLE under NTT_STRICT_RANKS), rejects an effective rank above
  * NTT_MAX_RANK, and lays out the workspace.  *out is owned by the caller and freed
@@ -235,6 +242,11 @@ ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_batch_t* ou
 /* Device workspace bytes for the whole batch (the sum of the problems' workspaces plus
  * a work-list area). */
 ntt_status ntt_batch_workspace(ntt_batch_t batch, size_t* bytes);
+
+/* Effective ranks of problem i (0 <= i < count): d+1 entries into eff_ranks (host), the
+ * same values ntt_plan_workspace gives for that problem's config; core k of problem i
+ * holds eff_ranks[k] x n_k x eff_ranks[k+1] floats. */
+ntt_status ntt_batch_eff_ranks(ntt_batch_t batch, int32_t i, int64_t* eff_ranks);
 
 /* Decompose every problem of the batch.
  *   A[i]       : device input of problem i (n_1...n_d floats, read only).

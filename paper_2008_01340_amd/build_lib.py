@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/ntt_kernels.hip", "csrc/ntt_bcd.hip", "csrc/ntt_coop.hip", "csrc/ntt_api.hip"]
+SOURCES = ["csrc/ntt_kernels.hip", "csrc/ntt_bcd.hip", "csrc/ntt_coop.hip", "csrc/ntt_api.hip",
+           "csrc/ntt_host.cpp"]
 LIB = os.path.join(HERE, "libntt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -35,8 +36,12 @@ def build(verbose: bool = True) -> str:
     os.makedirs(objdir, exist_ok=True)
     procs = []
     for src in SOURCES:
-        obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))
-        cmd = [HIPCC] + COMPILE_FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        if src.endswith(".cpp"):  # host-only C++ (no device code)
+            cmd = [HIPCC, "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
+                   "-c", os.path.join(HERE, src), "-o", obj]
+        else:
+            cmd = [HIPCC] + COMPILE_FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,

@@ -45,206 +45,13 @@ ntt_status fail(ntt_status s, const std::string& msg) {
       return fail(NTT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-#ifndef NTT_MAX_PASS_BLOCKS
-#define NTT_MAX_PASS_BLOCKS 1024
-#endif
-constexpr int kMaxPassBlocks = NTT_MAX_PASS_BLOCKS;  // persistent grid of the fused pass
-#ifndef NTT_R8_WIDE
-#define NTT_R8_WIDE 1
-#endif
-#ifndef NTT_R8W_CAP
-#define NTT_R8W_CAP 512
-#endif
-#ifndef NTT_L_MAX_BLOCKS
-#define NTT_L_MAX_BLOCKS 768
-#endif
-// grid cap of the row-split pass with 4 waves (three 256-thread workgroups per CU are
-// resident at its register use: one full round on 256 CUs); 8-wave classes keep 512
-constexpr int kMaxLBlocks = NTT_L_MAX_BLOCKS;
-#ifndef NTT_LW_MIN_STEPS
-#define NTT_LW_MIN_STEPS 256
-#endif
-constexpr int64_t kLWMinSteps = NTT_LW_MIN_STEPS;
-constexpr int kSumsqBlocks = 1024;
 constexpr int kGraphIters = 25;     // MU iterations per replayed graph
 constexpr size_t kMaxGraphs = 64;
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-enum PassKind { PASS_S = 0, PASS_L = 1, PASS_GENERIC = 2, PASS_C = 3 };
-
-struct Stage {
-  int64_t m = 0, k = 0;
-  int r = 0, rp = 16;
-  bool fused = true;  // one X pass per iteration whose workgroups also sum the residual
-                      // (PASS_S or PASS_L)
-  int kind = PASS_S;
-  int cls = 0;      // PASS_L: row class
-  int mb = 1;       // PASS_S: 16-row blocks
-  int nch = 0;      // PASS_C: row chunks
-  bool pro_ok = false;  // the update pass can apply the W-update in its prologue (r <= 8 pass)
-  bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
-  bool wide = false;   // PASS_L, PASS_S (r <= 8): update passes in 64-column steps
-  int G = 1;        // number of partials (pass workgroups or column chunks)
-  int64_t chunk = 0;  // generic: columns per chunk
-  bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X
-  size_t part_stride = 0;  // floats between the per-workgroup partials of this stage
-  // generic stages whose transposed problem (X^T = H^T W^T) fits the fused passes
-  bool trans_ok = false;
-  // the whole stage in one cooperative launch (m <= 256, r <= 16, 64 < k <= 32768):
-  // 16-column groups per workgroup and workgroups
-  bool coop_ok = false;
-  int coop_ng = 0, coop_G = 0;
-  int G_pre = 1;          // transposed problem: column chunks of its first X H^T pass
-  int64_t chunk_pre = 0;
-};
-
-// Pass kind, row class and workgroup count of an m x k, rank-r problem.
-void classify_stage(Stage& s, int precision) {
-  s.rp = s.r <= 16 ? 16 : 32;
-  const int64_t ngroups = (s.k + 15) / 16;
-  const double Ed = (double)s.m * s.r + (double)s.r * s.r;
-  // partials cost G E floats per iteration: keep them within ~10% of the X bytes,
-  // but use at least 256 workgroups when there are that many groups
-  const int64_t gcap = std::max<int64_t>(
-      256, std::min<int64_t>(kMaxPassBlocks, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
-  s.cls = pass_L_class(s.m, s.rp);
-#ifndef NTT_S_UPTO
-#define NTT_S_UPTO 32
-#endif
-  if (s.m <= 32 || (s.m <= NTT_S_UPTO && s.rp == 16 && ngroups >= 1024)) {
-    // one wavefront per 16-column group with all rows in registers: faster than splitting
-    // the rows over wavefronts up to 128 rows (no per-group barrier or cross-wave sum),
-    // once there are enough groups to occupy the GPU with one wavefront each
-    s.kind = PASS_S;
-    s.mb = s.m <= 16 ? 1 : (s.m <= 32 ? 2 : (s.m <= 64 ? 4 : 8));
-    // a grid of one resident round (workgroups per CU x 256 CUs) avoids a partly filled
-    // second round: three per CU for the r <= 8 pass and for 4 row blocks, two for 8
-    int64_t cap = gcap;
-    if (s.mb <= 2 && s.r <= 8) cap = std::min<int64_t>(gcap, 768);
-    if (s.mb == 4) cap = std::min<int64_t>(gcap, 768);
-    if (s.mb == 8) cap = std::min<int64_t>(gcap, 512);
-    // the r <= 8 pass in 64-column steps (one per wave) once there are enough of them
-    s.wide = NTT_R8_WIDE && s.mb <= 2 && s.r <= 8 && ngroups >= 4 * 4 * 256;
-    const int64_t units = s.wide ? ((ngroups + 3) / 4 + 3) / 4 : (ngroups + 3) / 4;
-    if (s.wide && s.mb == 2) cap = std::min<int64_t>(cap, NTT_R8W_CAP);  // two per CU at its registers
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, cap));
-  } else if (s.cls >= 0) {
-    s.kind = PASS_L;
-    // the batched update pass takes B whole groups per step; otherwise column groups
-    // in pairs once there are enough of them
-    // (the wide pass's 64-column steps leave too few workgroups below ~256 steps)
-    const int nb = ngroups >= 4 * kLWMinSteps ? pass_L_batch(s.cls, s.rp) : 0;
-    s.wide = nb > 0;
-    s.pairs = nb == 0 && ngroups >= 512;
-    const int64_t units = nb > 0 ? (ngroups + nb - 1) / nb : (s.pairs ? (ngroups + 1) / 2 : ngroups);
-    // one resident round of workgroups; partials up to ~25% of the X bytes
-    const int64_t gcap_l = std::max<int64_t>(
-        256, std::min<int64_t>(s.cls <= 2 ? kMaxLBlocks : 512,
-                               (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, gcap_l));
-  } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
-    s.kind = PASS_C;
-    s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
-    s.pairs = ngroups >= 512;
-    // the (G, nchunks) grid has enough workgroups at G = 128; more only adds partials
-    // (G (m r + r r) floats written and reduced per iteration)
-    const int64_t gcap_c = std::max<int64_t>(
-        128, std::min<int64_t>(1024, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
-    s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_c));
-  } else {
-    s.kind = PASS_GENERIC;
-  }
-  s.fused = s.kind == PASS_S || s.kind == PASS_L;
-  // (a prologue in the wide row-split pass was measured slower than the separate
-  // W-update launch: every workgroup waits for it before its first load)
-  s.pro_ok = s.kind == PASS_S && s.r <= 8 && s.m <= 32;
-  // BF16 X is read by the S passes at rank padding 16, the row-split and the row-chunked
-  // passes; stages the single-workgroup kernel takes (small unfoldings), the S pass at
-  // padding 32 and the generic path stay FP32
-  s.bf16 = precision == NTT_PREC_BF16_MIXED && !stage_1wg_ok(s.m, s.k, s.r) &&
-           (s.kind == PASS_L || s.kind == PASS_C || (s.kind == PASS_S && s.rp == 16));
-  const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
-  s.part_stride = align_up(E, 64);
-}
-
-void generic_chunks(const Stage& s, int* G, int64_t* chunk);
-
-// Classes of an m x k, rank-r stage (s) and of its transposed problem (t, when the stage
-// iterates transposed: s.trans_ok).
-void stage_shape(const ntt_config& cfg, int64_t m, int64_t k, int r, Stage& s, Stage& t) {
-  s = Stage{};
-  t = Stage{};
-  s.m = m;
-  s.k = k;
-  s.r = r;
-  classify_stage(s, cfg.precision);
-  if (s.kind == PASS_GENERIC) generic_chunks(s, &s.G, &s.chunk);
-  s.coop_ok = stage_coop_ok(m, k, r);
-  if (s.coop_ok) {
-    s.coop_ng = stage_coop_ng(k);
-    s.coop_G = stage_coop_grid(k, s.coop_ng);
-  }
-  if (!s.fused) {
-    // X^T (k x m) ~ H^T W^T: the MU iterations of the transposed problem are those of
-    // this one shifted by half a step, and its rows (k) may fit the fused passes
-    Stage u{};
-    u.m = s.k;
-    u.k = s.m;
-    u.r = s.r;
-    classify_stage(u, cfg.precision);
-    if (u.fused && cfg.tol == 0.0 && cfg.max_iters >= 1 && !stage_1wg_ok(u.m, u.k, u.r)) {
-      generic_chunks(u, &u.G_pre, &u.chunk_pre);
-      s.trans_ok = true;
-      t = u;
-    }
-  }
-}
-
-// Column chunks of the generic X H^T partials: enough for parallelism, while their
-// G (m r + r r) floats stay within ~1/4 of the X bytes.
-// floats between the column chunks' partials of the BCD products
-size_t bcd_part_stride(int64_t m, int r) { return align_up((size_t)m * r + (size_t)r * r, 64); }
-
-void generic_chunks(const Stage& s, int* G, int64_t* chunk) {
-  const double Ed = (double)s.m * s.r + (double)s.r * s.r;
-  const int64_t gcap_gen = std::max<int64_t>(1, (int64_t)(0.25 * (double)s.m * (double)s.k / Ed));
-  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((s.k + 255) / 256, 256), gcap_gen));
-  *chunk = (int64_t)align_up((size_t)((s.k + want - 1) / want), 64);
-  *G = (int)((s.k + *chunk - 1) / *chunk);
-}
-
 }  // namespace
 
-struct ntt_plan_s {
-  ntt_config cfg;
-  int d = 0;
-  int64_t dims[NTT_MAX_DIMS] = {};
-  int64_t eff[NTT_MAX_DIMS + 1] = {};
-  int64_t cap[NTT_MAX_DIMS + 1] = {};  // eff as planned (rank_eps > 0: the caps of the rule)
-  Stage st[NTT_MAX_DIMS];
-  Stage tst[NTT_MAX_DIMS];  // transposed problems of the stages with trans_ok
-  double compression = 0.0;
-  int64_t total_iters = 0;
-  // workspace layout (bytes)
-  size_t off_h[2] = {0, 0};
-  size_t off_part = 0, part_stride = 0, off_rpart = 0, off_red = 0, off_gw = 0;
-  size_t off_scal = 0, off_ints = 0, off_xb = 0, total = 0;
-  size_t off_xt = 0, off_wp = 0, off_hp = 0;  // X^T, H^T, W^T of a transposed stage
-  size_t off_s = 0;  // row-chunked stages: W^T X per row chunk, then a copy of H
-  size_t off_wb = 0;  // prologue-mode stages: the second W buffer
-  size_t off_gpart = 0;  // W-update over row blocks: per-block Gram parts
-  // rank rule (rank_eps > 0): Gram partials, the Gram, eigenvalues, eigensolver workspace
-  size_t off_grp = 0, off_gram = 0, off_eig = 0, off_eigws = 0, eigws_size = 0;
-  // BCD (Alg.3): the two other H buffers, W before and candidate, X H^T and H H^T of the
-  // kept H, W_n^T W_n, the state block
-  size_t off_bh[2] = {0, 0}, off_bwp = 0, off_bwn = 0, off_bxh = 0, off_bhh = 0, off_bgw = 0, off_bst = 0;
-  // stage 1 streamed from host memory (stream_cols > 0): column blocks of kblk columns,
-  // their shapes (full blocks, last block), the staging buffers of X and H, the reduced
-  // products of one block, and per-block sums
-  int64_t kblk = 0, nblk = 0;
-  Stage sst[2];
-  size_t off_xs = 0, off_hs = 0, off_redtmp = 0, off_bsum = 0, off_gram2 = 0;
+// A plan: the host layout (ntt_host.h) and the device-side objects created on first use.
+struct ntt_plan_s : PlanLayout {
   rocblas_handle rb = nullptr;  // created on first use by the rank rule
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
@@ -252,7 +59,6 @@ struct ntt_plan_s {
   // stages may run as one cooperative launch (standalone plans; batched and served
   // problems run concurrently on several streams and keep one launch per pass)
   bool coop_allowed = true;
-  size_t off_coop = 0;  // barrier flags of the cooperative stage (32 per workgroup)
   // replayable blocks of MU iterations, one per (stage, block length, buffers)
   struct GraphEntry {
     int stage, iters;
@@ -270,15 +76,6 @@ struct ntt_plan_s {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
   }
 };
-
-static double compression_of(int d, const int64_t* dims, const int64_t* ranks) {
-  double num = 1.0, den = 0.0;
-  for (int i = 0; i < d; ++i) {
-    num *= (double)dims[i];
-    den += (double)dims[i] * (double)ranks[i] * (double)ranks[i + 1];
-  }
-  return num / den;
-}
 
 extern "C" {
 
@@ -307,241 +104,13 @@ double ntt_compression_ratio(int32_t d, const int64_t* dims, const int64_t* rank
 ntt_status ntt_plan(const ntt_config* cfg, ntt_plan_t* out) {
   if (!cfg || !out) return fail(NTT_ERR_INVALID_ARG, "null config or output");
   *out = nullptr;
-  const int d = cfg->d;
-  if (d < 2 || d > NTT_MAX_DIMS) return fail(NTT_ERR_INVALID_ARG, "d must be in 2..16");
-  if (!cfg->dims || !cfg->ranks) return fail(NTT_ERR_INVALID_ARG, "null dims or ranks");
-  if (cfg->max_iters < 0) return fail(NTT_ERR_INVALID_ARG, "max_iters < 0");
-  if (cfg->check_every < 1) return fail(NTT_ERR_INVALID_ARG, "check_every < 1");
-  if (!(cfg->eps >= 0.0) || !std::isfinite(cfg->eps)) return fail(NTT_ERR_INVALID_ARG, "eps must be finite and >= 0");
-  if (!(cfg->tol >= 0.0) || !std::isfinite(cfg->tol)) return fail(NTT_ERR_INVALID_ARG, "tol must be finite and >= 0");
-  if (cfg->precision != NTT_PREC_FP32 && cfg->precision != NTT_PREC_BF16_MIXED)
-    return fail(NTT_ERR_INVALID_ARG, "unknown precision");
-  if (cfg->fp32_tail_iters < 0) return fail(NTT_ERR_INVALID_ARG, "fp32_tail_iters < 0");
-  if (!(cfg->rank_eps >= 0.0) || !std::isfinite(cfg->rank_eps))
-    return fail(NTT_ERR_INVALID_ARG, "rank_eps must be finite and >= 0");
-  const bool eps_mode = cfg->rank_eps > 0.0;
-  if (cfg->nmf != NTT_NMF_MU && cfg->nmf != NTT_NMF_BCD) return fail(NTT_ERR_INVALID_ARG, "unknown nmf");
-  const bool bcd = cfg->nmf == NTT_NMF_BCD;
-  if (bcd) {
-    if (cfg->precision != NTT_PREC_FP32) return fail(NTT_ERR_INVALID_ARG, "BCD runs in FP32 only");
-    if (cfg->tol != 0.0) return fail(NTT_ERR_INVALID_ARG, "BCD runs a fixed iteration count (tol = 0)");
-    if (!(cfg->bcd_delta >= 0.0 && cfg->bcd_delta < 1.0))
-      return fail(NTT_ERR_INVALID_ARG, "bcd_delta must be in [0, 1)");
-  }
-  if (cfg->stream_cols < 0) return fail(NTT_ERR_INVALID_ARG, "stream_cols < 0");
-  const bool streamed = cfg->stream_cols > 0;
-  if (streamed && (bcd || cfg->precision != NTT_PREC_FP32 || cfg->tol != 0.0 ||
-                   (cfg->flags & NTT_RECORD_OBJECTIVE)))
-    return fail(NTT_ERR_INVALID_ARG, "stream_cols: MU in FP32, tol = 0 and no objective trace");
-  int64_t total = 1;
-  for (int i = 0; i < d; ++i) {
-    if (cfg->dims[i] < 1) return fail(NTT_ERR_INVALID_ARG, "dims must be >= 1");
-    if (total > ((int64_t)1 << 62) / cfg->dims[i]) return fail(NTT_ERR_INVALID_ARG, "tensor too large");
-    total *= cfg->dims[i];
-  }
-  if (cfg->ranks[0] != 1 || cfg->ranks[d] != 1) return fail(NTT_ERR_INVALID_ARG, "r_0 and r_d must be 1");
-  for (int i = 1; i < d; ++i)
-    if (cfg->ranks[i] < 1) return fail(NTT_ERR_INVALID_ARG, "inner ranks must be >= 1");
-
   auto* p = new ntt_plan_s();
-  p->cfg = *cfg;
-  p->cfg.dims = nullptr;
-  p->cfg.ranks = nullptr;
-  p->d = d;
-  for (int i = 0; i < d; ++i) p->dims[i] = cfg->dims[i];
-  // effective ranks: r_l <= min(r_{l-1} n_l, n_{l+1}...n_d), left to right
-  p->eff[0] = 1;
-  for (int l = 1; l < d; ++l) {
-    const int64_t m = p->eff[l - 1] * p->dims[l - 1];
-    int64_t k = 1;
-    for (int j = l; j < d; ++j) k *= p->dims[j];
-    const int64_t r = std::min(cfg->ranks[l], std::min(m, k));
-    if (r != cfg->ranks[l] && (cfg->flags & NTT_STRICT_RANKS)) {
-      delete p;
-      return fail(NTT_ERR_RANK_INFEASIBLE, "rank " + std::to_string(l) + " exceeds min(r_{l-1} n_l, n_{l+1}..n_d)");
-    }
-    if (r > NTT_MAX_RANK) {
-      delete p;
-      return fail(NTT_ERR_INVALID_ARG, "effective rank above NTT_MAX_RANK (32)");
-    }
-    p->eff[l] = r;
-  }
-  p->eff[d] = 1;
-  for (int i = 0; i <= d; ++i) p->cap[i] = p->eff[i];
-  p->compression = compression_of(d, p->dims, p->eff);
-
-  // stages and workspace
-  size_t hsize[2] = {0, 0};
-  size_t xb_size = 0;
-  size_t part_floats = 0;
-  int gmax = 1, gres = 1, gfin = 1;
-  size_t red_max = 0;
-  size_t xt_size = 0, wp_size = 0, hp_size = 0, s_size = 0, wb_size = 0;
-  int64_t m_max = 1;
-  size_t grp_max = 0, gram_max = 0;
-  int64_t n_max = 0;
-  size_t bh_size = 0, bm_size = 0;  // BCD: one H buffer, one m x r factor (elements)
-  // one stage shape: its classes (kept in s, t) and its share of the workspace maxima
-  auto plan_stage = [&](int l, int64_t m, int64_t k, int r, Stage& s, Stage& t_out) {
-    stage_shape(*cfg, m, k, r, s, t_out);
-    if (s.kind == PASS_GENERIC) gres = std::max<int>(gres, (int)((s.k + 255) / 256));  // residual blocks
-    if (s.kind == PASS_C) {
-      gres = std::max(gres, s.G * s.nch);
-      s_size = std::max(s_size, (size_t)(s.nch + 1) * (size_t)s.r * (size_t)s.k * sizeof(float));
-    }
-    if (s.trans_ok) {
-      const Stage& t = t_out;
-      {
-        part_floats = std::max(part_floats, (size_t)std::max(t.G, t.G_pre) * t.part_stride);
-        red_max = std::max(red_max, (size_t)t.m * t.r + (size_t)t.r * t.r);
-        gres = std::max(gres, t.G);
-        gfin = std::max(gfin, std::max(t.G, t.G_pre));
-        xt_size = std::max(xt_size, (size_t)s.m * (size_t)s.k * sizeof(float));
-        wp_size = std::max(wp_size, (size_t)s.k * (size_t)s.r * sizeof(float));
-        hp_size = std::max(hp_size, (size_t)s.r * (size_t)s.m * sizeof(float));
-        if (t.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
-      }
-    }
-    const size_t E = (size_t)s.m * s.r + (size_t)s.r * s.r;
-    red_max = std::max(red_max, E);
-    m_max = std::max(m_max, s.m);
-    if (s.trans_ok) m_max = std::max(m_max, t_out.m);
-    gmax = std::max(gmax, s.G);
-    gfin = std::max(gfin, s.G);
-    part_floats = std::max(part_floats, (size_t)s.G * s.part_stride);
-    if (s.coop_ok) part_floats = std::max(part_floats, (size_t)s.coop_G * E);
-    if (l < d - 1) {
-      const size_t hb = (size_t)s.r * (size_t)s.k * sizeof(float);
-      hsize[(l - 1) & 1] = std::max(hsize[(l - 1) & 1], hb);
-    }
-    if (s.bf16) xb_size = std::max(xb_size, (size_t)s.m * (size_t)s.k * sizeof(uint16_t));
-    if (s.pro_ok) wb_size = std::max(wb_size, (size_t)s.m * (size_t)s.r * sizeof(float));
-    if (bcd) {
-      int G = 1;
-      int64_t chunk = 64;
-      bcd_chunks(s.m, s.k, s.r, &G, &chunk);
-      part_floats = std::max(part_floats, (size_t)G * bcd_part_stride(s.m, s.r));
-      gres = std::max<int>(gres, G * (int)((s.m + 63) / 64));
-      gfin = std::max(gfin, G);
-      bh_size = std::max(bh_size, (size_t)s.r * (size_t)s.k);
-      bm_size = std::max(bm_size, (size_t)s.m * (size_t)s.r);
-    }
-    if (eps_mode) {
-      int ns = 1;
-      size_t pd = 0;
-      gram_plan(s.m, s.k, &ns, &pd);
-      const int64_t n = std::min(s.m, s.k);
-      grp_max = std::max(grp_max, pd);
-      gram_max = std::max(gram_max, (size_t)n * (size_t)n);
-      n_max = std::max(n_max, n);
-    }
-  };
-  for (int l = 1; l < d; ++l) {
-    int64_t k = 1;
-    for (int j = l; j < d; ++j) k *= p->dims[j];
-    plan_stage(l, p->eff[l - 1] * p->dims[l - 1], k, (int)p->eff[l], p->st[l - 1], p->tst[l - 1]);
-    if (eps_mode) {
-      // the rule may choose any r_{l-1} <= cap and r_l <= cap: plan the workspace for all
-      for (int64_t rp_ = 1; rp_ <= p->eff[l - 1]; ++rp_)
-        for (int64_t r_ = 1; r_ <= p->eff[l]; ++r_) {
-          const int64_t m_ = rp_ * p->dims[l - 1];
-          if (r_ > std::min(m_, k)) continue;
-          Stage s2{}, t2{};
-          plan_stage(l, m_, k, (int)r_, s2, t2);
-        }
-    }
-    p->total_iters += cfg->max_iters;
-  }
-  if (streamed) {
-    // stage 1 in column blocks: the full blocks' shape and the last block's
-    const int64_t m1 = p->dims[0], k1 = total / p->dims[0];
-    const int64_t kb = std::min<int64_t>(cfg->stream_cols, k1);
-    p->kblk = kb;
-    p->nblk = (k1 + kb - 1) / kb;
-    Stage tt{};
-    const int64_t last = k1 - (p->nblk - 1) * kb;
-    plan_stage(1, m1, kb, (int)p->eff[1], p->sst[0], tt);
-    plan_stage(1, m1, last, (int)p->eff[1], p->sst[1], tt);
-    if (eps_mode) {
-      // the rule may choose any r_1 up to the cap: the block stages at every rank; the
-      // Gram of X_1 is the n_1 x n_1 sum of the blocks' row Grams
-      for (int64_t r_ = 1; r_ < p->eff[1]; ++r_) {
-        Stage s2{};
-        plan_stage(1, m1, kb, (int)r_, s2, tt);
-        plan_stage(1, m1, last, (int)r_, s2, tt);
-      }
-      for (int64_t w : {kb, last}) {
-        int ns = 1;
-        size_t pd = 0;
-        gram_rows_plan(m1, w, &ns, &pd);
-        grp_max = std::max(grp_max, pd);
-      }
-      gram_max = std::max(gram_max, (size_t)m1 * (size_t)m1);
-      n_max = std::max(n_max, m1);
-    }
-  }
-  if (bcd && m_max > 64 * 65535) {
+  std::string err;
+  const ntt_status st = plan_layout(cfg, p, &err);
+  if (st != NTT_OK) {
     delete p;
-    return fail(NTT_ERR_INVALID_ARG, "BCD: an unfolding has more than 4194240 rows");
+    return fail(st, err);
   }
-  if (eps_mode && n_max > 2048) {
-    delete p;
-    return fail(NTT_ERR_INVALID_ARG, "rank_eps: an unfolding's shorter side exceeds 2048");
-  }
-  gres = std::max(std::max(gres, gmax), kSumsqBlocks);
-  size_t off = 0;
-  p->off_h[0] = off; off = align_up(off + hsize[0], 256);
-  p->off_h[1] = off; off = align_up(off + hsize[1], 256);
-  p->off_part = off; off = align_up(off + part_floats * sizeof(float), 256);
-  p->off_rpart = off; off = align_up(off + (size_t)gres * sizeof(double), 256);
-  p->off_red = off; off = align_up(off + red_max * sizeof(double), 256);
-  if (gfin > 1024) {
-    delete p;
-    return fail(NTT_ERR_INVALID_ARG, "too many partials for the W-update reduction");
-  }
-  p->off_gw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
-  p->off_scal = off; off = align_up(off + (size_t)SCAL_COUNT * (d - 1) * sizeof(double), 256);
-  p->off_ints = off; off = align_up(off + 64 * sizeof(int), 256);
-  p->off_xb = off; off = align_up(off + xb_size, 256);
-  p->off_xt = off; off = align_up(off + xt_size, 256);
-  p->off_wp = off; off = align_up(off + wp_size, 256);
-  p->off_hp = off; off = align_up(off + hp_size, 256);
-  p->off_s = off; off = align_up(off + s_size, 256);
-  p->off_wb = off; off = align_up(off + wb_size, 256);
-  p->off_gpart = off; off = align_up(off + (size_t)((m_max + 255) / 256) * (32 * 32 + 1) * sizeof(double), 256);
-  p->off_coop = off; off = align_up(off + (size_t)512 * 32 * sizeof(unsigned), 256);
-  if (eps_mode) {
-    p->off_grp = off; off = align_up(off + grp_max * sizeof(double), 256);
-    p->off_gram = off; off = align_up(off + gram_max * sizeof(double), 256);
-    p->off_eig = off; off = align_up(off + (2 * (size_t)n_max + 8) * sizeof(double), 256);
-    // eigensolver scratch (eigenvalues only): checked against the solver's own query,
-    // which asked for 110 MB at n = 2048 (about 3.3 n^2 doubles)
-    p->eigws_size = (size_t)32 << 20;
-    p->eigws_size += 4 * gram_max * sizeof(double);
-    p->off_eigws = off; off = align_up(off + p->eigws_size, 256);
-    if (streamed) {  // the Gram of one column block of X_1
-      p->off_gram2 = off;
-      off = align_up(off + (size_t)p->dims[0] * (size_t)p->dims[0] * sizeof(double), 256);
-    }
-  }
-  if (streamed) {
-    const size_t m1 = (size_t)p->dims[0], r1 = (size_t)p->eff[1];
-    p->off_xs = off; off = align_up(off + m1 * (size_t)p->kblk * sizeof(float), 256);
-    p->off_hs = off; off = align_up(off + r1 * (size_t)p->kblk * sizeof(float), 256);
-    p->off_redtmp = off; off = align_up(off + (m1 * r1 + r1 * r1) * sizeof(double), 256);
-    p->off_bsum = off; off = align_up(off + (size_t)p->nblk * sizeof(double), 256);
-  }
-  if (bcd) {
-    p->off_bh[0] = off; off = align_up(off + bh_size * sizeof(float), 256);
-    p->off_bh[1] = off; off = align_up(off + bh_size * sizeof(float), 256);
-    p->off_bwp = off; off = align_up(off + bm_size * sizeof(float), 256);
-    p->off_bwn = off; off = align_up(off + bm_size * sizeof(float), 256);
-    p->off_bxh = off; off = align_up(off + bm_size * sizeof(double), 256);
-    p->off_bhh = off; off = align_up(off + 32 * 32 * sizeof(double), 256);
-    p->off_bgw = off; off = align_up(off + 32 * 32 * sizeof(float), 256);
-    p->off_bst = off; off = align_up(off + sizeof(BcdState), 256);
-  }
-  p->total = off;
   *out = p;
   return NTT_OK;
 }
@@ -1603,6 +1172,12 @@ extern "C" ntt_status ntt_batch_workspace(ntt_batch_t b, size_t* bytes) {
   return NTT_OK;
 }
 
+extern "C" ntt_status ntt_batch_eff_ranks(ntt_batch_t b, int32_t i, int64_t* eff_ranks) {
+  if (!b || !eff_ranks) return fail(NTT_ERR_INVALID_ARG, "null batch or eff_ranks");
+  if (i < 0 || (size_t)i >= b->plans.size()) return fail(NTT_ERR_INVALID_ARG, "problem index out of range");
+  return ntt_plan_workspace(b->plans[(size_t)i], nullptr, eff_ranks, nullptr);
+}
+
 extern "C" void ntt_batch_destroy(ntt_batch_t b) { delete b; }
 
 extern "C" ntt_status ntt_decompose_batch(ntt_batch_t b, void* stream, void* workspace,
@@ -1729,45 +1304,6 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-struct Arena {
-  char* base = nullptr;
-  size_t size = 0;
-  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, bytes), sorted by offset
-  void init(void* b, size_t n) {
-    base = reinterpret_cast<char*>(b);
-    size = n;
-    free_list.assign(1, {0, n});
-  }
-  bool alloc(size_t n, size_t* off) {
-    n = align_up(std::max<size_t>(n, 256), 256);
-    for (size_t i = 0; i < free_list.size(); ++i) {
-      if (free_list[i].second >= n) {
-        *off = free_list[i].first;
-        free_list[i].first += n;
-        free_list[i].second -= n;
-        if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = align_up(std::max<size_t>(n, 256), 256);
-    auto it = free_list.begin();
-    while (it != free_list.end() && it->first < off) ++it;
-    it = free_list.insert(it, {off, n});
-    // merge with the next and the previous ranges
-    if (it + 1 != free_list.end() && it->first + it->second == (it + 1)->first) {
-      it->second += (it + 1)->second;
-      free_list.erase(it + 1);
-    }
-    if (it != free_list.begin() && (it - 1)->first + (it - 1)->second == it->first) {
-      (it - 1)->second += it->second;
-      free_list.erase(it);
-    }
-  }
-};
-
 struct Request {
   int64_t id = 0;
   int state = NTT_REQ_QUEUED;
@@ -1792,14 +1328,14 @@ struct Request {
 
 struct ntt_server_s {
   ntt_server_config cfg;
-  Arena arena;
+  Admission adm;  // arena offsets and slots (ntt_host.h)
+  char* base = nullptr;  // the arena's device memory
   std::vector<hipStream_t> streams;  // slot streams, then the copy stream, then the grouped stream
   hipStream_t copy_stream = nullptr, group_stream = nullptr;
   hipEvent_t group_ev = nullptr;
   std::deque<Request*> queue;
   std::vector<Request*> active;  // admitted, not yet released
   std::map<int64_t, Request*> all;
-  std::vector<int> slot_used;
   int64_t next_id = 1;
   double t0 = 0;
   std::vector<StageArgs> list_host;
@@ -1886,15 +1422,15 @@ static hipError_t server_ring_slot(ntt_server_s* sv, int* slot) {
 
 // input + workspace and the slot go back when a request finishes; cores on release
 static void server_release_work(ntt_server_s* sv, Request* q) {
-  if (q->total_w) sv->arena.release(q->off_w, q->total_w);
+  if (q->total_w) sv->adm.arena.release(q->off_w, q->total_w);
   q->total_w = 0;
-  if (q->slot >= 0) sv->slot_used[q->slot] = 0;
+  if (q->slot >= 0) sv->adm.slot_used[q->slot] = 0;
   q->slot = -1;
 }
 
 static void server_release_memory(ntt_server_s* sv, Request* q) {
   server_release_work(sv, q);
-  if (q->total_c) sv->arena.release(q->off_c, q->total_c);
+  if (q->total_c) sv->adm.arena.release(q->off_c, q->total_c);
   q->total_c = 0;
 }
 
@@ -1908,7 +1444,8 @@ extern "C" ntt_status ntt_server_create(const ntt_server_config* cfg, ntt_server
     return fail(NTT_ERR_INVALID_ARG, "arena must be 256-byte aligned");
   auto* sv = new ntt_server_s();
   sv->cfg = *cfg;
-  sv->arena.init(cfg->arena, cfg->arena_bytes);
+  sv->base = reinterpret_cast<char*>(cfg->arena);
+  sv->adm.init(cfg->arena_bytes, cfg->max_slots);
   const int nstreams = std::min(cfg->max_slots, 8);
   for (int i = 0; i < nstreams + 2; ++i) {
     hipStream_t q;
@@ -1925,7 +1462,6 @@ extern "C" ntt_status ntt_server_create(const ntt_server_config* cfg, ntt_server
     delete sv;
     return fail(NTT_ERR_DEVICE, "hipEventCreate failed");
   }
-  sv->slot_used.assign(cfg->max_slots, 0);
   sv->t0 = now_s();
   *out = sv;
   return NTT_OK;
@@ -1977,7 +1513,7 @@ extern "C" ntt_status ntt_server_submit(ntt_server_t sv, const ntt_request* rq, 
     q->iters_total += c.max_iters;
     q->gflop += (double)c.max_iters * (4.0 * s.m * s.k * s.r + 4.0 * (s.m + s.k) * s.r * s.r) * 1e-9;
   }
-  if (q->bytes_A + q->bytes_cores + q->bytes_ws > sv->arena.size) q->state = NTT_REQ_REJECTED;
+  if (q->bytes_A + q->bytes_cores + q->bytes_ws > sv->adm.arena.size) q->state = NTT_REQ_REJECTED;
   else sv->queue.push_back(q);
   sv->all[q->id] = q;
   *id = q->id;
@@ -1991,28 +1527,17 @@ extern "C" ntt_status ntt_server_tick(ntt_server_t sv, int32_t* n_active, int32_
   while (!sv->queue.empty()) {
     Request* q = sv->queue.front();
     int slot = -1;
-    for (int i = 0; i < (int)sv->slot_used.size(); ++i)
-      if (!sv->slot_used[i]) {
-        slot = i;
-        break;
-      }
-    if (slot < 0) break;
     size_t off_c = 0, off_w = 0;
-    if (!sv->arena.alloc(q->bytes_cores, &off_c)) break;
-    if (!sv->arena.alloc(q->bytes_A + q->bytes_ws, &off_w)) {
-      sv->arena.release(off_c, q->bytes_cores);
-      break;
-    }
+    if (!sv->adm.admit(q->bytes_cores, q->bytes_A + q->bytes_ws, &slot, &off_c, &off_w)) break;
     sv->queue.pop_front();
     q->off_c = off_c;
     q->total_c = q->bytes_cores;
     q->off_w = off_w;
     q->total_w = q->bytes_A + q->bytes_ws;
     q->slot = slot;
-    sv->slot_used[slot] = 1;
-    char* base = sv->arena.base + off_w;
+    char* base = sv->base + off_w;
     q->A = reinterpret_cast<float*>(base);
-    char* cp = sv->arena.base + off_c;
+    char* cp = sv->base + off_c;
     q->cores.clear();
     for (int i = 0; i < q->plan->d; ++i) {
       q->cores.push_back(reinterpret_cast<float*>(cp));
@@ -2200,8 +1725,6 @@ extern "C" ntt_status ntt_server_release(ntt_server_t sv, int64_t id) {
 
 extern "C" ntt_status ntt_server_free_bytes(ntt_server_t sv, size_t* bytes) {
   if (!sv || !bytes) return fail(NTT_ERR_INVALID_ARG, "null server or bytes");
-  size_t f = 0;
-  for (auto& r : sv->arena.free_list) f += r.second;
-  *bytes = f;
+  *bytes = sv->adm.arena.free_bytes();
   return NTT_OK;
 }

@@ -1017,17 +1017,6 @@ bool bcd_args_ok(const BcdArgs& b) {
 
 }  // namespace
 
-void bcd_chunks(int64_t m, int64_t k, int r, int* G, int64_t* chunk) {
-  // about a quarter of X's size in partials at most; up to 1024 chunks of >= 64 columns
-  const double E = (double)m * r + (double)r * r;
-  const int64_t cap = std::max<int64_t>(1, (int64_t)(0.25 * (double)m * (double)k / E));
-  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((k + 63) / 64, 1024), cap));
-  int64_t c = (k + want - 1) / want;
-  c = (c + 63) / 64 * 64;
-  *chunk = c;
-  *G = (int)((k + c - 1) / c);
-}
-
 hipError_t launch_bcd_prepare(const BcdArgs& b, hipStream_t s) {
   if (!bcd_args_ok(b)) return hipErrorInvalidValue;
   const int64_t mr = (int64_t)b.m * b.r, rk = (int64_t)b.r * b.k;

@@ -360,20 +360,6 @@ int max_blocks_ng() {
 
 }  // namespace
 
-int stage_coop_ng(int64_t k) {
-  const int64_t per = (k + 127) / 128;  // workgroups at 8 groups each
-  if (per <= 16) return (k + 15) / 16 <= 128 ? 1 : 2;
-  if (per <= 32) return 2;
-  if (per <= 64) return 4;
-  return 8;
-}
-
-int stage_coop_grid(int64_t k, int ng) { return (int)((k + 16 * ng - 1) / (16 * ng)); }
-
-bool stage_coop_ok(int64_t m, int64_t k, int r) {
-  return m >= 1 && m <= 256 && r >= 1 && r <= 16 && k > 64 && k <= 256 * 128;
-}
-
 int stage_coop_max_grid(int ng) {
   switch (ng) {
     case 1: { static const int v = max_blocks_ng<1>(); return v; }

@@ -7,12 +7,9 @@
 #include <algorithm>
 
 #include "../../include/ntt.h"
+#include "ntt_host.h"
 
 namespace ntt {
-
-// FP64 scalars kept on the device per stage
-enum { SCAL_NX2 = 0, SCAL_OBJ = 1, SCAL_MONITOR = 2, SCAL_OBJ0 = 3, SCAL_BCD_W2 = 4,
-       SCAL_BCD_H2 = 5, SCAL_BCD_CORR = 6, SCAL_BCD_OBJ = 7, SCAL_COUNT = 8 };
 
 // One MU pass over the columns of an m x k unfolding.
 struct PassArgs {
@@ -103,19 +100,6 @@ struct TTArgs {
   double* part;    // MODE 1 per-block (err, ref) pairs, then the two totals
 };
 
-// BCD NMF (Alg.3): state of one stage, in device memory, read and written by the kernels
-// only (so that iterations replay from a captured graph).  Hb[cur] holds the kept H,
-// Hb[prev] the kept H before it, Hb[nxt] receives the candidate; the three indices are
-// always a permutation of 0, 1, 2.
-struct BcdState {
-  double t, obj;   // extrapolation sequence and the objective of the kept pair
-  double wW, wH;   // extrapolation weights of the next iteration
-  double gH, gW;   // ||H H^T||_F and ||W^T W||_F of the kept pair
-  double gWn;      // ||W_n^T W_n||_F of the candidate W (the H step size 1/gWn)
-  double pad0;
-  int cur, prev, nxt, first, corrections, pad1[3];
-};
-
 struct BcdArgs {
   const float* X;    // m x k, row stride k
   float* Hb[3];      // three r x k buffers; Hb[0] is the stage's H (the result goes there)
@@ -138,8 +122,6 @@ struct BcdArgs {
   int64_t k;
   double delta;      // extrapolation cap
 };
-// Column chunks of the BCD products for an m x k unfolding at rank r (G <= 1024).
-void bcd_chunks(int64_t m, int64_t k, int r, int* G, int64_t* chunk);
 // Stage set-up: scale W and Hb[0] to Frobenius norm sqrt(||X||_F) (scal[SCAL_NX2] must
 // hold ||X||^2), reset the state and form X H^T, H H^T of the initial H.
 hipError_t launch_bcd_prepare(const BcdArgs& b, hipStream_t s);
@@ -159,33 +141,22 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, in
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              bool wide, hipStream_t s);
-int pass_L_class(int64_t m, int rp);  // -1 when m is beyond the row-split variant
-int pass_L_waves(int cls);
-// 16-column groups per step of the wide row-split update pass for a row class (0: the
-// class has no wide pass); a wide stage's grid takes ceil(groups / 4) steps.
-int pass_L_batch(int cls, int rp);
 // wide: update passes by the wide pass (a residual with them runs the per-group pass
 // first); otherwise every pass by the per-group row-split pass
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,
                          bool wide, hipStream_t s);
-// Row-chunked pass (m beyond one workgroup): rows per chunk, and the launches of one
+// Row-chunked pass (m beyond one workgroup; rows per chunk in ntt_host.h): the launches of one
 // iteration (phase 1, chunk sum, phase 2) or of the residual (phase 0) on a
 // (G, nchunks) grid.  S holds nchunks x r x k floats, Hs r x k.
-int pass_C_rows(int rp);
 hipError_t launch_pass_C(const PassArgs& a, int rp, int G, bool update, bool resid, hipStream_t s);
-bool stage_1wg_ok(int64_t m, int64_t k, int r);
 hipError_t launch_stage_1wg(const StageArgs& a, hipStream_t s);
-int stage_1wg_ng(int64_t k);  // 16-column groups the kernel instance holds (1, 2 or 4)
 hipError_t launch_stage_1wg_grouped(const StageArgs* list_dev, int count, int ng, hipStream_t s);
 hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s);
 // the grouped kernel instance for ng groups (a graph kernel node's function); its list
 // may be empty (the node then runs one workgroup that returns at once)
 const void* stage_1wg_list_kernel(int ng);
-// Cooperative whole-stage kernel: eligibility, 16-column groups per workgroup, grid, the
-// largest grid the device holds at once for that instance (0 when unknown), and the launch.
-bool stage_coop_ok(int64_t m, int64_t k, int r);
-int stage_coop_ng(int64_t k);
-int stage_coop_grid(int64_t k, int ng);
+// Cooperative whole-stage kernel (eligibility and grid in ntt_host.h): the largest grid the
+// device holds at once for an instance (0 when unknown), and the launch.
 int stage_coop_max_grid(int ng);
 hipError_t launch_stage_coop(const CoopArgs& c, int ng, int G, hipStream_t s);
 hipError_t launch_pass_generic(const PassArgs& a, int rp, int gxht, int64_t chunk, bool update,
@@ -209,13 +180,11 @@ hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s);
 // Rank rule of Alg.2: FP64 Gram of the shorter side of X (m x k, row-major): G = X X^T
 // (n = m) when m <= k, else X^T X (n = k); G is n x n, row-major, both triangles.  The
 // long dimension is split into nsplit chunks whose partials (npairs x nsplit blocks of
-// 64 x 64 doubles in `part`) are added in chunk order.  gram_plan gives the split and the
-// partial size in doubles for an m x k matrix.
-void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles);
+// 64 x 64 doubles in `part`) are added in chunk order (gram_plan: the split and the
+// partial size in doubles for an m x k matrix).
 hipError_t launch_gram(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s);
 // The m x m Gram X X^T whatever the shape (a column block of a streamed unfolding; the
-// blocks' Grams are added by the caller); the split and partial size for it.
-void gram_rows_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles);
+// blocks' Grams are added by the caller; split and partial size by gram_rows_plan).
 hipError_t launch_gram_rows(const float* X, int64_t m, int64_t k, double* part, double* G, hipStream_t s);
 
 }  // namespace ntt

@@ -9,8 +9,11 @@
 // the columns of X does the whole H-update and, while X[:,j] is still in registers,
 // accumulates X[:,j] H_new[:,j]^T and H_new[:,j] H_new[:,j]^T: X is read from HBM once
 // per iteration.  Per-workgroup partial sums are reduced in a fixed order (no float
-// atomics) by the finalize kernel, whose last workgroup applies the W-update and forms
-// the next W^T W.  The result equals the two-pass MU up to summation order.
+// atomics) by separate launches (k_reduce_partials, then k_wupdate or the row-split
+// k_wupdate_rows + k_wupdate_gram), which apply the W-update and form the next W^T W;
+// the r <= 8 passes can instead take that W-update in their own prologue.  Small stages
+// run whole in one workgroup (k_stage_1wg) or in one cooperative launch (ntt_coop.hip).
+// The result equals the two-pass MU up to summation order.
 //
 // Rank r is padded to RP = 16 or 32 (zero rows/columns) to fit the MFMA 16x16x4 f32
 // tiles.  All shapes are runtime values; ragged edges are masked to zero, which is
@@ -23,15 +26,6 @@
 
 #include "ntt_device.h"
 #include "ntt_internal.h"
-
-// Tuning knobs (compile-time): minimum waves per SIMD requested from the
-// register allocator for the r <= 8 pass, and whether it prefetches the next group.
-#ifndef NTT_R8_MIN_WG
-#define NTT_R8_MIN_WG 1
-#endif
-#ifndef NTT_R8_PREFETCH
-#define NTT_R8_PREFETCH 1
-#endif
 
 namespace ntt {
 
@@ -579,7 +573,7 @@ __device__ __forceinline__ void r8_w_setup(const PassArgs& p, float (*sWt)[MPAD 
 // Rows and columns beyond r are zero in G and H_new, so the 8-wide sums are exact for any
 // r <= 8.
 template <int MB, bool XBF>
-__global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
+__global__ __launch_bounds__(256, 1) void k_mu_pass_r8(PassArgs p) {
   constexpr int MPAD = 16 * MB;
   constexpr int SX = 20;
   __shared__ __attribute__((aligned(16))) float sWt[16][MPAD + 4];  // W^T, zero padded
@@ -641,10 +635,8 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
   };
 
   int64_t g = (int64_t)blockIdx.x * 4 + w;
-#if NTT_R8_PREFETCH
-  float xn[MB][4], hn_[4];
+  float xn[MB][4], hn_[4];  // next group's loads, in flight while one is processed
   if (g < ngroups) load_group(g, xn, hn_);
-#endif
   r8_w_setup<MPAD>(p, sWt, sG, tid, w, a, b);
   __syncthreads();
 
@@ -661,7 +653,6 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
     float xr[MB][4], hv[4];
-#if NTT_R8_PREFETCH
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
@@ -669,9 +660,6 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) hv[q] = hn_[q];
     if (g + wstride < ngroups) load_group(g + wstride, xn, hn_);
-#else
-    load_group(g, xr, hv);
-#endif
 
     // H tile to LDS as [column][rank]; rows >= r of the loads hold copies of row r-1,
     // so they are zeroed here
@@ -812,14 +800,8 @@ __global__ __launch_bounds__(256, NTT_R8_MIN_WG) void k_mu_pass_r8(PassArgs p) {
 //   - X H_new^T per 16-row block (X through a per-wave transposition tile) and
 //     H_new H_new^T, both with MFMA (K = columns).
 // Partials as in k_mu_pass_r8 (waves added in the order 3, 2, 1, 0).
-#ifndef NTT_R8W_WAVES
-#define NTT_R8W_WAVES 1
-#endif
-#ifndef NTT_R8W_PF
-#define NTT_R8W_PF 0
-#endif
 template <int NQ, bool XBF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NTT_R8W_WAVES)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
 void k_mu_pass_r8w(PassArgs p) {
   constexpr int MPAD = 4 * NQ;  // 16 or 32 rows
   constexpr int NB = NQ / 4;    // 16-row blocks
@@ -874,8 +856,6 @@ void k_mu_pass_r8w(PassArgs p) {
   };
 
   int64_t st = (int64_t)blockIdx.x * 4 + w;
-  float4 xn[NQ], hn2[2];  // next step's loads, in flight while one is processed
-  if (NTT_R8W_PF && st < nsteps) load_step(st, xn, hn2);
   r8_w_setup<MPAD>(p, sWt, sG, tid, w, a, b);
   __syncthreads();
   float wa[NQ];  // W^T as the A operand of W^T X: W[4i + b][a] (zero past m and r)
@@ -894,15 +874,7 @@ void k_mu_pass_r8w(PassArgs p) {
   for (; st < nsteps; st += wstride) {
     const int64_t j0 = st << 6;
     float4 x[NQ], h[2];
-#if NTT_R8W_PF
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) x[i] = xn[i];
-    h[0] = hn2[0];
-    h[1] = hn2[1];
-    if (st + wstride < nsteps) load_step(st + wstride, xn, hn2);
-#else
     load_step(st, x, h);
-#endif
 
     // W^T X of the four column sets: lane (a, b) value i of set q is rank 4b + i, column
     // j0 + 4a + q
@@ -3092,9 +3064,6 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
   switch (mb) {
     case 1: return pass_fused_mb<RP, 1>(a, grid, update, resid, s);
     case 2: return pass_fused_mb<RP, 2>(a, grid, update, resid, s);
-    case 4: return pass_fused_mb<RP, 4>(a, grid, update, resid, s);
-    case 8: return pass_fused_mb<RP, 8>(a, grid, update, resid, s);
-    case 16: return pass_fused_mb<RP, 16>(a, grid, update, resid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -3164,19 +3133,6 @@ static hipError_t pass_L_rp(const PassArgs& a, int cls, int grid, bool update, b
   }
 }
 
-int pass_L_class(int64_t m, int rp) {
-  if (m <= 64) return 0;
-  if (m <= 128) return 1;
-  if (m <= 256) return 2;
-  if (m <= 512) return 3;
-  if (m <= 1024 && rp == 16) return 4;
-  return -1;
-}
-
-int pass_L_waves(int cls) { return cls <= 2 ? 4 : 8; }
-
-int pass_L_batch(int cls, int rp) { return (rp == 16 && cls >= 0 && cls <= 3) ? 4 : 0; }
-
 template <int MBW, int NW>
 static hipError_t pass_LW(const PassArgs& a, int grid, hipStream_t s) {
   // BF16 X: BF16 matrix cores for waves of 32 rows (wider waves would spill registers)
@@ -3210,14 +3166,6 @@ hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool upda
   }
   return rp == 16 ? pass_L_rp<16>(a, cls, grid, update, resid, s)
                   : pass_L_rp<32>(a, cls, grid, update, resid, s);
-}
-
-bool stage_1wg_ok(int64_t m, int64_t k, int r) { return m <= 256 && k <= 64 && r <= 16; }
-
-// Row-chunked pass: chunks of 512 rows, 8 waves of 64 rows (both paddings).
-int pass_C_rows(int rp) {
-  (void)rp;
-  return 512;
 }
 
 template <int RP>
@@ -3279,8 +3227,6 @@ hipError_t launch_stage_1wg_list(const StageList& L, int ng, hipStream_t s) {
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
-
-int stage_1wg_ng(int64_t k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
 
 const void* stage_1wg_list_kernel(int ng) {
   if (ng == 1) return reinterpret_cast<const void*>(k_stage_1wg_list<1>);
@@ -3412,24 +3358,6 @@ hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s) {
     NTT_CHECK_LAUNCH();
   }
   return hipSuccess;
-}
-
-void gram_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
-  const int64_t n = std::min(m, k), L = std::max(m, k);
-  const int64_t nb = (n + 63) / 64;
-  const int64_t npairs = nb * (nb + 1) / 2;
-  // about 1024 workgroups, each chunk at least 1024 long-side indices
-  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024 / npairs, (L + 1023) / 1024));
-  *nsplit = (int)ns;
-  *part_doubles = (size_t)npairs * (size_t)ns * 4096;
-}
-
-void gram_rows_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
-  const int64_t nb = (m + 63) / 64;
-  const int64_t npairs = nb * (nb + 1) / 2;
-  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024 / npairs, (k + 1023) / 1024));
-  *nsplit = (int)ns;
-  *part_doubles = (size_t)npairs * (size_t)ns * 4096;
 }
 
 static hipError_t launch_gram_impl(const float* X, int64_t m, int64_t k, bool rows, double* part,

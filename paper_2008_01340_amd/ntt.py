@@ -42,7 +42,7 @@ EXPORTED = [
     "ntt_plan", "ntt_plan_workspace", "ntt_decompose", "ntt_tt_workspace", "ntt_reconstruct",
     "ntt_rel_error", "ntt_rel_error_static", "ntt_compression_ratio", "ntt_plan_destroy",
     "ntt_status_string",
-    "ntt_last_error", "ntt_version", "ntt_batch_plan", "ntt_batch_workspace",
+    "ntt_last_error", "ntt_version", "ntt_batch_plan", "ntt_batch_workspace", "ntt_batch_eff_ranks",
     "ntt_decompose_batch", "ntt_batch_destroy", "ntt_server_create", "ntt_server_submit",
     "ntt_server_tick", "ntt_server_info", "ntt_server_cores", "ntt_server_release",
     "ntt_server_free_bytes", "ntt_server_destroy",
@@ -175,6 +175,8 @@ def load(path: str = LIB_PATH):
     lib.ntt_batch_plan.restype = C.c_int
     lib.ntt_batch_workspace.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.ntt_batch_workspace.restype = C.c_int
+    lib.ntt_batch_eff_ranks.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
+    lib.ntt_batch_eff_ranks.restype = C.c_int
     lib.ntt_decompose_batch.argtypes = [P, P, P, C.POINTER(P), C.POINTER(C.POINTER(P)),
                                         C.POINTER(NttReport)]
     lib.ntt_decompose_batch.restype = C.c_int
@@ -431,7 +433,11 @@ class Batch:
         nbytes = C.c_size_t()
         _check(lib.ntt_batch_workspace(self.handle, C.byref(nbytes)), "ntt_batch_workspace")
         self.workspace_bytes = int(nbytes.value)
-        self.eff = [O_effective(dm, rk) for dm, rk, _ in self.problems]
+        self.eff = []
+        for i, (dm, _, _) in enumerate(self.problems):
+            e = (C.c_int64 * (len(dm) + 1))()
+            _check(lib.ntt_batch_eff_ranks(self.handle, i, e), "ntt_batch_eff_ranks")
+            self.eff.append(list(e))
 
     def close(self):
         if self.handle:
@@ -443,19 +449,6 @@ class Batch:
             self.close()
         except Exception:
             pass
-
-
-def O_effective(dims, ranks):
-    """Effective ranks after the clamp rule of ntt_plan (host arithmetic, for allocation)."""
-    out = [1]
-    for l in range(1, len(dims)):
-        m = out[-1] * dims[l - 1]
-        k = 1
-        for n in dims[l:]:
-            k *= n
-        out.append(min(ranks[l], m, k))
-    out.append(1)
-    return out
 
 
 def ntt_decompose_batch(batch: Batch, stream: int, workspace: int, A_ptrs, core_ptrs,

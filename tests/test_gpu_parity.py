@@ -85,7 +85,7 @@ SHAPES = [
     # enough column groups (>= 512, an odd count) for workgroups to take them in pairs:
     # rows split over waves, and rows in chunks
     (100, 9000, 12), (1100, 8200, 5),
-    # one wavefront per group with 4 and 8 row blocks (33..128 rows, >= 1024 groups)
+    # 33..128 rows with >= 1024 groups: the row-split pass in its wide (batched-step) form
     (60, 17000, 7), (120, 16500, 14),
     # the wide row-split update pass: 129..256 rows (4 waves) with an odd k (scalar loads,
     # last step partly past the end) and a k of whole steps at rank 16; 8 waves with a
