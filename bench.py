@@ -65,8 +65,10 @@ def parse():
                     help="skip the precision-mode, paper-workload, batched and serving measurements")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help="comma-separated subset of the extra measurements: " + ", ".join(EXTRAS))
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-max-mb", type=float, default=64.0)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-max-mb", type=float, default=1000.0)
+    ap.add_argument("--serve-rates", default="0.8",
+                    help="comma-separated arrival rates as fractions of the saturated rate")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
@@ -362,29 +364,58 @@ def batched(ntt, S, torch, count=256):
     return out
 
 
-def serving(ntt, S, torch, n_req, max_mb, precision):
-    """Poisson stream of TT-generated requests (d in 3..6, 1 MB..max_mb log-uniform, r 4..32):
-    an untimed saturated warm-up, then saturated (all at t = 0) to find the service rate mu,
-    then arrivals at 0.5 mu and 0.8 mu."""
+def serving_inputs(ntt, S, torch, n_req, max_mb):
+    """The request stream's tensors in pinned host memory (how requests arrive), shared by
+    both precisions: generated on the device from their TT cores and copied into 2 GiB
+    pinned chunks, packed first-fit by decreasing size (one allocation per chunk)."""
     import numpy as np
     reqs = S.serving_stream(n_req, max_bytes=max_mb * 1e6)
-    host = []
-    for q in reqs:
+    t0 = time.perf_counter()
+    chunk = 1 << 29                       # floats (2 GiB)
+    sizes = [int(np.prod(q.work.dims)) for q in reqs]
+    pad = [(n + 63) // 64 * 64 for n in sizes]
+    fill, where = [], {}
+    for i in sorted(range(len(reqs)), key=lambda i: -pad[i]):
+        need = max(pad[i], 64)
+        c = next((c for c in range(len(fill)) if fill[c] + need <= max(chunk, need)), None)
+        if c is None:
+            fill.append(0)
+            c = len(fill) - 1
+        where[i] = (c, fill[c])
+        fill[c] += need
+    pools = [torch.empty(max(chunk, f), dtype=torch.float32, pin_memory=True) for f in fill]
+    t1 = time.perf_counter()
+    host = [None] * len(reqs)
+    for i, q in enumerate(reqs):
         g = _tt_on_gpu(ntt, S, torch, q.work)
-        h = torch.empty(tuple(g.shape), dtype=torch.float32, pin_memory=True)
+        c, off = where[i]
+        h = pools[c][off:off + sizes[i]].view(tuple(q.work.dims))
         h.copy_(g)
-        host.append(h)
+        host[i] = h
         del g
-    progress(f"serving: {len(reqs)} requests generated")
+    torch.cuda.synchronize()
+    progress(f"serving: {len(reqs)} requests, {sum(sizes) * 4 / 1e9:.1f} GB in {len(pools)} pinned "
+             f"chunks ({t1 - t0:.1f} s to allocate, {time.perf_counter() - t1:.1f} s to generate)")
+    return reqs, host
+
+
+def serving(ntt, S, torch, reqs, host, precision, rates):
+    """Poisson stream of TT-generated requests (d in 3..6, 1 MB..max_mb log-uniform, r 4..32):
+    a short warm-up, then saturated (all at t = 0) to find the service rate mu and, after
+    that run, each request's relative error (Eq.(3)) against its input; then arrivals at the
+    given fractions of mu."""
+    import numpy as np
+    n_req = len(reqs)
     need = sum(h.numel() * 4 for h in host)
     arena = int(min(64 << 30, 3 * need + (1 << 30)))
 
-    def run(arrivals):
+    def run(arrivals, subset=None, errors=None):
+        order = list(range(n_req)) if subset is None else list(subset)
         srv = ntt.Server(arena, max_slots=16, iters_per_tick=25)
         t_start = time.perf_counter()
-        pending, done, lat, gfl = list(range(len(reqs))), {}, [], 0.0
-        ids = {}
-        while pending or len(done) < len(reqs):
+        pending, done, lat, gfl = list(order), {}, [], 0.0
+        ids, kept = {}, []
+        while pending or len(done) < len(order):
             now = time.perf_counter() - t_start
             while pending and arrivals[pending[0]] <= now:
                 i = pending.pop(0)
@@ -398,26 +429,58 @@ def serving(ntt, S, torch, n_req, max_mb, precision):
                     lat.append(inf["t_finish"] - inf["t_submit"])
                     gfl += inf["gflop"]
                     done[i] = inf["t_finish"]
-                    srv.release(rid)
+                    if errors is None:
+                        srv.release(rid)
+                    else:
+                        kept.append((rid, i))
                     del ids[rid]
                 elif inf["state"] in (ntt.NTT_REQ_REJECTED, ntt.NTT_REQ_CANCELLED):
                     raise RuntimeError("request not served")
         span = time.perf_counter() - t_start
+        for rid, i in kept:                  # after the timed span: Eq.(3) on the device
+            errors[i] = ntt.rel_error(host[i].to("cuda:0"), srv.cores(rid))
+            srv.release(rid)
         srv.close()
-        progress(f"serving run: {len(reqs)} requests in {span:.2f} s")
+        progress(f"serving run: {len(order)} requests in {span:.2f} s")
         lat = np.array(lat)
-        return {"decomps_per_s": len(reqs) / span, "gflop_per_s": gfl / span,
+        return {"decomps_per_s": len(order) / span, "gflop_per_s": gfl / span,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
-    run([0.0] * len(reqs))  # warm-up: first launches of the kernel variants this mix uses
-    sat = run([0.0] * len(reqs))
+    small = sorted(range(n_req), key=lambda i: host[i].numel())[:8]
+    run([0.0] * n_req, subset=sorted(small))  # warm-up: first launches of the kernel variants
+    errors = [None] * n_req
+    sat = run([0.0] * n_req, errors=errors)
     mu = sat["decomps_per_s"]
-    out = {"requests": n_req, "max_mb": max_mb, "saturated": sat}
-    for frac in (0.5, 0.8):
+    out = {"saturated": sat, "rel_error": errors}
+    for frac in rates:
         rate = frac * mu
         gaps = -np.log(1.0 - S.uniform01(5, 0x301, (n_req,)).astype(np.float64)) / rate
         out[f"rate_{frac}mu"] = run(list(np.cumsum(gaps) - gaps[0]))
     return out
+
+
+def serving_both(ntt, S, torch, n_req, max_mb, rates):
+    """FP32 and BF16-mixed serving of the same stream; per-request errors summarised, with
+    the BF16/FP32 error ratio (the comparison at equal relative error)."""
+    import numpy as np
+    reqs, host = serving_inputs(ntt, S, torch, n_req, max_mb)
+    res = {}
+    for name, prec in (("fp32", ntt.NTT_PREC_FP32), ("bf16", ntt.NTT_PREC_BF16_MIXED)):
+        res[name] = serving(ntt, S, torch, reqs, host, prec, rates)
+    e32, e16 = (np.array(res[k].pop("rel_error"), dtype=np.float64) for k in ("fp32", "bf16"))
+    for k, e in (("fp32", e32), ("bf16", e16)):
+        res[k]["rel_error"] = {"median": float(np.median(e)), "mean": float(e.mean()), "max": float(e.max())}
+    ratio = e16 / np.maximum(e32, 1e-300)
+    sizes = np.array([h.numel() * 4 for h in host], dtype=np.float64)
+    res["bf16_over_fp32_error"] = {"median": float(np.median(ratio)), "max": float(ratio.max())}
+    res["requests"] = n_req
+    res["bytes"] = {"total": float(sizes.sum()), "max": float(sizes.max()), "median": float(np.median(sizes))}
+    res["note"] = (f"{n_req} requests of the serving stream recipe (d 3..6, ranks 4..32, T=200), sizes "
+                   f"log-uniform from 1 MB to {max_mb:g} MB before rounding the modes, inputs in pinned "
+                   f"host memory; arrivals saturated, then Poisson at "
+                   f"{', '.join(str(r) for r in rates)} of the saturated rate")
+    del host
+    return res
 
 
 def main():
@@ -543,11 +606,8 @@ def main():
         out["batched"] = batched(ntt, S, torch)
         torch.cuda.empty_cache()
     if "serving" in extras:
-        out["serving"] = {
-            "fp32": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_FP32),
-            "bf16": serving(ntt, S, torch, args.serve_requests, args.serve_max_mb, ntt.NTT_PREC_BF16_MIXED),
-            "note": f"{args.serve_requests} requests of the serving stream recipe, sizes capped at "
-                    f"{args.serve_max_mb} MB, Poisson arrivals at 0.5 and 0.8 of the saturated rate"}
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        out["serving"] = serving_both(ntt, S, torch, args.serve_requests, args.serve_max_mb, rates)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_seconds,
                                            4.0 if "bcd" in extras else 0.0)

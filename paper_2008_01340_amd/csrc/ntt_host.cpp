@@ -133,10 +133,12 @@ void classify_stage(Stage& s, int precision) {
     s.kind = PASS_C;
     s.nch = (int)((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp));
     s.pairs = ngroups >= 512;
-    // the (G, nchunks) grid has enough workgroups at G = 128; more only adds partials
-    // (G (m r + r r) floats written and reduced per iteration)
+    // the (G, nchunks) grid has enough workgroups at G = 128, or at G nchunks >= 1024
+    // when there are many row chunks; more only adds partials (G (m r + r r) floats
+    // written and reduced per iteration, kept near 10% of the X bytes above that floor)
+    const int64_t gfloor = std::min<int64_t>(128, (1024 + s.nch - 1) / s.nch);
     const int64_t gcap_c = std::max<int64_t>(
-        128, std::min<int64_t>(1024, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
+        gfloor, std::min<int64_t>(1024, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_c));
   } else {
     s.kind = PASS_GENERIC;

@@ -11,7 +11,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/ntt.h"
+#include "ntt.h"
 
 namespace ntt {
 

@@ -6,7 +6,7 @@
 
 #include <algorithm>
 
-#include "../../include/ntt.h"
+#include "ntt.h"
 #include "ntt_host.h"
 
 namespace ntt {

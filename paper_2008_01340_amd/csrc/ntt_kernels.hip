@@ -2461,6 +2461,32 @@ __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
 constexpr int kReduceLanes = 64;
 constexpr int kMaxReduceG = 16 * kReduceLanes;
 
+// The same sums for G <= 64 with one thread per entry (consecutive threads, consecutive
+// entries: every load is coalesced): partial g goes into group g / 8 in order, the groups
+// in order, each sum starting from 0.0 -- the operations and their order are those of
+// k_reduce_partials for G <= 64 (there lane g holds partial g alone), so the results are
+// bitwise the same with far fewer threads.
+__global__ __launch_bounds__(256) void k_reduce_partials_small(const float* __restrict__ part,
+                                                               int64_t stride, int G, int64_t E,
+                                                               double* __restrict__ red) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  double tot = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    float v[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int g = 8 * q + l;
+      v[l] = zmask(part[(int64_t)min(g, G - 1) * stride + e], g < G);
+    }
+    double sq = 0.0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) sq += (double)v[l];
+    tot += sq;
+  }
+  red[e] = tot;
+}
+
 __global__ __launch_bounds__(1024) void k_reduce_partials(const float* __restrict__ part,
                                                           int64_t stride, int G, int64_t E,
                                                           double* __restrict__ red) {
@@ -3284,9 +3310,8 @@ hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
   const bool fused = f.G <= 4 && !blocks;
   if (!fused) {
     if (f.G > kMaxReduceG) return hipErrorInvalidValue;
-    const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
-    k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
-    NTT_CHECK_LAUNCH();
+    const hipError_t e = launch_reduce(f, s);
+    if (e != hipSuccess) return e;
   }
   if (blocks) {
     if (!f.gpart) return hipErrorInvalidValue;
@@ -3308,7 +3333,10 @@ hipError_t launch_wupdate_red(const FinArgs& f, hipStream_t s) {
 hipError_t launch_reduce(const FinArgs& f, hipStream_t s) {
   if (f.G < 1 || f.G > kMaxReduceG) return hipErrorInvalidValue;
   const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
-  k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  if (f.G <= kReduceLanes)
+    k_reduce_partials_small<<<(unsigned)((E + 255) / 256), 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  else
+    k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }

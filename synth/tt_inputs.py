@@ -47,13 +47,19 @@ _CHUNK = 1 << 22
 def splitmix64(seed: int, tag: int, start: int, count: int) -> np.ndarray:
     """Raw 64-bit outputs ``start .. start+count-1`` of stream ``tag``."""
     seed &= _M64
-    ctr = (np.uint64((tag << 32) & _M64)
-           + np.arange(start + 1, start + 1 + count, dtype=np.uint64))
-    with np.errstate(over="ignore"):
-        z = np.uint64(seed) + np.uint64(GAMMA) * ctr
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(_MIX1)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(_MIX2)
-        z = z ^ (z >> np.uint64(31))
+    z = np.arange(start + 1, start + 1 + count, dtype=np.uint64)   # counter i + 1
+    z += np.uint64((tag << 32) & _M64)
+    with np.errstate(over="ignore"):   # in place, one temporary: all arithmetic mod 2**64
+        z *= np.uint64(GAMMA)
+        z += np.uint64(seed)
+        t = z >> np.uint64(30)
+        z ^= t
+        z *= np.uint64(_MIX1)
+        np.right_shift(z, np.uint64(27), out=t)
+        z ^= t
+        z *= np.uint64(_MIX2)
+        np.right_shift(z, np.uint64(31), out=t)
+        z ^= t
     return z
 
 
@@ -214,7 +220,8 @@ def serving_stream(count: int = 1000, seed: int = 5, rate_per_s: float = 10.0,
     Per request q: d ~ U{3..6}; total bytes log-uniform on [min_bytes, max_bytes]
     (N = bytes/4 entries); mode sizes from log N split by Dirichlet(1) weights
     (normalised exponentials), rounded, each >= 2; one target rank r ~ U{rmin..rmax}
-    for every bond (generating cores use the same rank).  Inter-arrival times are
+    for every bond (generating cores use the same rank, clamped per bond to the largest
+    rank the mode sizes allow).  Inter-arrival times are
     exponential with the given rate.
     """
     reqs = []
@@ -230,8 +237,11 @@ def serving_stream(count: int = 1000, seed: int = 5, rate_per_s: float = 10.0,
         dims = tuple(max(2, int(round(math.exp(logn * wi)))) for wi in w)
         r = rmin + int(math.floor(u[2 + d] * (rmax - rmin + 1)))
         ranks = (1,) + (r,) * (d - 1) + (1,)
+        # the generating cores take the same rank, clamped at each bond to the largest a
+        # TT of these mode sizes can have (min of the products of the modes on each side)
+        gen = (1,) + tuple(min(r, math.prod(dims[:k]), math.prod(dims[k:])) for k in range(1, d)) + (1,)
         ua = float(uniform01(seed, TAG_ARRIVAL, (1,), start=q)[0])
         t += -math.log(1.0 - ua) / rate_per_s
-        reqs.append(Request(q, t, Workload(f"req{q}", dims, ranks, ranks, iters,
+        reqs.append(Request(q, t, Workload(f"req{q}", dims, gen, ranks, iters,
                                            _sub_seed(seed + 1, q))))
     return reqs

@@ -120,6 +120,26 @@ def test_single_stage_per_iterate_parity(m, k, r):
         assert Wg.min() >= 0 and Hg.min() >= 0
 
 
+@pytest.mark.parametrize("m,k,r", [(30000, 1100, 8), (9000, 2100, 31)])
+def test_row_chunked_many_chunks_per_iterate_parity(m, k, r):
+    """Tall unfoldings on the row-chunked pass with many 512-row chunks (59 and 18): few
+    column chunks (partials near 10% of X) and the one-thread-per-entry reduction of
+    G <= 64 partials."""
+    say(f"case: d=2 NMF, row-chunked with many chunks, m={m} k={k} r={r}")
+    rng = np.random.default_rng(m + 3 * k)
+    X = (rng.random((m, k)) + 0.05).astype(np.float32)
+    W0, H0 = O.init_factors(5, 1, m, r, k)
+    T = 12
+    ref = O.mu_nmf(X.astype(np.float64), W0, H0, T, snapshots=(1, T))
+    for t in (1, T):
+        g = ntt.decompose(dev(X), (1, r, 1), t, init_W=[dev(W0)], init_H=[dev(H0)])
+        Wo, Ho = ref["snaps"][t]
+        eW = rows_rel(host(g.cores[0]).reshape(m, r), Wo)
+        eH = cols_rel(host(g.cores[1]).reshape(r, k), Ho)
+        say(f"  t={t}: W rows {eW:.2e} H columns {eH:.2e}")
+        assert eW <= TOL and eH <= TOL
+
+
 # ------------------------------------------------------------------ the sweep (workload 1)
 def test_sweep_16cubed_per_iterate_parity_chained():
     say("case: sweep 16^3 ranks (4,4), T=200, chained")
