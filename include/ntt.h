@@ -83,8 +83,11 @@ typedef enum {
 #define NTT_RECORD_OBJECTIVE 4u /* explicit FP64 objective of every iterate into objective_trace */
 #define NTT_PROFILE 8u          /* fill ntt_report.pass_ms with per-launch kernel timings */
 #define NTT_NO_COOP 16u         /* every stage keeps one launch per pass and W-update (no
-                                   whole-stage cooperative launch for m <= 256, r <= 16,
-                                   k <= 32768); the iterates are the same up to summation order */
+                                   whole-stage launch with grid barriers for m <= 256,
+                                   r <= 16, k <= 32768; that launch needs its workgroups
+                                   resident together and fails with NTT_ERR_DEVICE when
+                                   other work keeps some of them waiting about a quarter
+                                   second); the iterates are the same up to summation order */
 
 typedef struct {
   int32_t d;            /* number of modes, 2..NTT_MAX_DIMS */
@@ -148,6 +151,14 @@ typedef struct {
   double total_gflop;
   double compression_ratio;            /* Eq.(4) at eff_ranks */
   int32_t corrections[NTT_MAX_DIMS];   /* BCD: dropped iterations per stage (MU: 0) */
+  int32_t bf16_iters[NTT_MAX_DIMS];    /* iterations per stage whose X passes read the BF16
+                                          copy of X (precision NTT_PREC_BF16_MIXED); 0 for
+                                          stages that stay FP32: those the whole-stage
+                                          kernels take (X stays on chip: m <= 256, r <= 16
+                                          and k <= 64, or k <= 32768 for a standalone plan
+                                          with tol = 0), the generic path, the
+                                          one-wavefront pass at rank padding 32 (m <= 32,
+                                          r > 16), BCD, streamed */
 } ntt_report;
 
 typedef struct ntt_plan_s* ntt_plan_t;

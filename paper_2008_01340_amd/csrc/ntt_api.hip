@@ -56,7 +56,7 @@ struct ntt_plan_s : PlanLayout {
   std::vector<hipEvent_t> prof_events;
   hipEvent_t stage_ev[2 * NTT_MAX_DIMS] = {};
   bool events_ready = false;
-  // stages may run as one cooperative launch (standalone plans; batched and served
+  // stages may run as one grid-synchronised launch (standalone plans; batched and served
   // problems run concurrently on several streams and keep one launch per pass)
   bool coop_allowed = true;
   // replayable blocks of MU iterations, one per (stage, block length, buffers)
@@ -208,6 +208,7 @@ struct NttJob {
   bool prepared = false, done = false;
   int64_t trace_off = 0;
   int iters[NTT_MAX_DIMS] = {};
+  int bf_planned[NTT_MAX_DIMS] = {};  // per stage: leading iterations on the BF16 copy of X
   // state of the current stage
   const float* X = nullptr;
   float* H = nullptr;
@@ -430,6 +431,7 @@ struct NttJob {
     pa_bf = pa;
     // (a cooperative stage keeps X on chip: it reads X once per launch, in FP32)
     bf_iters = (e.bf16 && !bcd && !streamed && !coop) ? std::max(0, cfg.max_iters - cfg.fp32_tail_iters) : 0;
+    bf_planned[l - 1] = bf_iters;
     if (bf_iters > 0) {
       HIP_TRY(launch_cast_bf16(c.xb(), pa.X, s.m * s.k, q));
       pa_bf.Xb = c.xb();
@@ -895,6 +897,7 @@ struct NttJob {
       const double* v = sc + (size_t)SCAL_COUNT * (ll - 1);
       rep->iters[ll - 1] = iters[ll - 1];
       if (p->cfg.nmf == NTT_NMF_BCD) rep->corrections[ll - 1] = (int32_t)v[SCAL_BCD_CORR];
+      rep->bf16_iters[ll - 1] = std::min(bf_planned[ll - 1], iters[ll - 1]);
       rep->norm_x[ll - 1] = std::sqrt(v[SCAL_NX2]);
       rep->objective[ll - 1] = v[SCAL_OBJ];
       rep->stage_rel_err[ll - 1] =

@@ -80,7 +80,7 @@ struct Stage {
   size_t part_stride = 0;  // floats between the per-workgroup partials of this stage
   // generic stages whose transposed problem (X^T = H^T W^T) fits the fused passes
   bool trans_ok = false;
-  // the whole stage in one cooperative launch (m <= 256, r <= 16, 64 < k <= 32768):
+  // the whole stage in one grid-synchronised launch (m <= 256, r <= 16, 64 < k <= 32768):
   // 16-column groups per workgroup and workgroups
   bool coop_ok = false;
   int coop_ng = 0, coop_G = 0;

@@ -63,7 +63,7 @@ struct StageArgs {
   float eps;
 };
 
-// A whole stage of MU iterations in one cooperative launch (m <= 256, r <= 16, k <= 32768):
+// A whole stage of MU iterations in one grid-synchronised launch (m <= 256, r <= 16, k <= 32768):
 // G workgroups of 16 NG columns each, X and H on chip for all iterations.
 struct CoopArgs {
   const float* X;    // m x k

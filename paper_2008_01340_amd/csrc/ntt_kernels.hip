@@ -12,7 +12,7 @@
 // atomics) by separate launches (k_reduce_partials, then k_wupdate or the row-split
 // k_wupdate_rows + k_wupdate_gram), which apply the W-update and form the next W^T W;
 // the r <= 8 passes can instead take that W-update in their own prologue.  Small stages
-// run whole in one workgroup (k_stage_1wg) or in one cooperative launch (ntt_coop.hip).
+// run whole in one workgroup (k_stage_1wg) or in one grid-synchronised launch (ntt_coop.hip).
 // The result equals the two-pass MU up to summation order.
 //
 // Rank r is padded to RP = 16 or 32 (zero rows/columns) to fit the MFMA 16x16x4 f32
@@ -2462,26 +2462,26 @@ constexpr int kReduceLanes = 64;
 constexpr int kMaxReduceG = 16 * kReduceLanes;
 
 // The same sums for G <= 64 with one thread per entry (consecutive threads, consecutive
-// entries: every load is coalesced): partial g goes into group g / 8 in order, the groups
-// in order, each sum starting from 0.0 -- the operations and their order are those of
-// k_reduce_partials for G <= 64 (there lane g holds partial g alone), so the results are
-// bitwise the same with far fewer threads.
+// entries: every load is coalesced), NQ = ceil(G / 8) groups of eight partials, all loads
+// issued at once: partial g goes into group g / 8 in order, the groups in order, each sum
+// starting from 0.0 -- the operations and their order are those of k_reduce_partials for
+// G <= 64 (there lane g holds partial g alone, and zeros for the missing ones), so the
+// results are bitwise the same with far fewer threads.
+template <int NQ>
 __global__ __launch_bounds__(256) void k_reduce_partials_small(const float* __restrict__ part,
                                                                int64_t stride, int G, int64_t E,
                                                                double* __restrict__ red) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= E) return;
-  double tot = 0.0;
-  for (int q = 0; q < 8; ++q) {
-    float v[8];
+  float v[8 * NQ];
 #pragma unroll
-    for (int l = 0; l < 8; ++l) {
-      const int g = 8 * q + l;
-      v[l] = zmask(part[(int64_t)min(g, G - 1) * stride + e], g < G);
-    }
+  for (int g = 0; g < 8 * NQ; ++g) v[g] = zmask(part[(int64_t)min(g, G - 1) * stride + e], g < G);
+  double tot = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
     double sq = 0.0;
 #pragma unroll
-    for (int l = 0; l < 8; ++l) sq += (double)v[l];
+    for (int l = 0; l < 8; ++l) sq += (double)v[8 * q + l];
     tot += sq;
   }
   red[e] = tot;
@@ -3333,10 +3333,19 @@ hipError_t launch_wupdate_red(const FinArgs& f, hipStream_t s) {
 hipError_t launch_reduce(const FinArgs& f, hipStream_t s) {
   if (f.G < 1 || f.G > kMaxReduceG) return hipErrorInvalidValue;
   const int64_t E = (int64_t)f.m * f.r + (int64_t)f.r * f.r;
-  if (f.G <= kReduceLanes)
-    k_reduce_partials_small<<<(unsigned)((E + 255) / 256), 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
-  else
-    k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  const unsigned gs = (unsigned)((E + 255) / 256);
+  switch ((f.G + 7) / 8) {
+    case 1: k_reduce_partials_small<1><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 2: k_reduce_partials_small<2><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 3: k_reduce_partials_small<3><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 4: k_reduce_partials_small<4><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 5: k_reduce_partials_small<5><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 6: k_reduce_partials_small<6><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 7: k_reduce_partials_small<7><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    case 8: k_reduce_partials_small<8><<<gs, 256, 0, s>>>(f.part, f.part_stride, f.G, E, f.red); break;
+    default:
+      k_reduce_partials<<<(unsigned)((E + 15) / 16), 1024, 0, s>>>(f.part, f.part_stride, f.G, E, f.red);
+  }
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -85,6 +85,7 @@ class NttReport(C.Structure):
         ("total_gflop", C.c_double),
         ("compression_ratio", C.c_double),
         ("corrections", C.c_int32 * NTT_MAX_DIMS),
+        ("bf16_iters", C.c_int32 * NTT_MAX_DIMS),
     ]
 
     def to_dict(self, d: int) -> dict:
@@ -102,6 +103,7 @@ class NttReport(C.Structure):
             "total_gflop": self.total_gflop,
             "compression_ratio": self.compression_ratio,
             "corrections": list(self.corrections[:s]),
+            "bf16_iters": list(self.bf16_iters[:s]),
         }
 
 
