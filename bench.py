@@ -357,8 +357,18 @@ def batched(ntt, S, torch, count=256):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     gflop = sum(r["total_gflop"] for r in reps)
+    # algorithmic HBM bytes: per MU iteration of a stage, X read once, H read and written,
+    # W read (4mk + 8rk + 4mr), as for the headline kernel
+    nbytes = 0.0
+    for w, r in zip(mix, reps):
+        e = r["eff_ranks"]
+        for l in range(len(w.dims) - 1):
+            m, k, rr = e[l] * w.dims[l], math.prod(w.dims[l + 1:]), e[l + 1]
+            nbytes += r["iters"][l] * (4.0 * m * k + 8.0 * rr * k + 4.0 * m * rr)
     out = {"problems": count, "entries": int(sum(t.numel() for t in tensors)), "s": sec,
            "decomps_per_s": count / sec, "gflop_per_s": gflop / sec,
+           "hbm_bytes": nbytes, "hbm_gbs": nbytes / sec / 1e9,
+           "hbm_frac": nbytes / sec / 1e9 / HBM_PEAK_GBS,
            "mean_stage_rel_err": float(sum(sum(r["stage_rel_err"]) / len(r["stage_rel_err"]) for r in reps) / count)}
     del tensors, cores
     return out

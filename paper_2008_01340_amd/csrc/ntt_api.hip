@@ -1131,7 +1131,10 @@ struct ntt_batch_s {
   }
 };
 
-constexpr int kBatchStreams = 4;
+// Streams of the batched pool, problems dealt to them in order.  Measured on the 256-problem
+// mix (MI355X): 4 streams 3.25 s, 8 2.97 s, 16 2.80 s, 32 2.72 s; dealing the largest
+// problems first to the least-loaded stream was no faster than dealing in order.
+constexpr int kBatchStreams = 16;
 
 extern "C" ntt_status ntt_batch_plan(int32_t count, const ntt_config* cfgs, ntt_batch_t* out) {
   if (!out || !cfgs || count < 1) return fail(NTT_ERR_INVALID_ARG, "bad batch arguments");
@@ -1449,7 +1452,7 @@ extern "C" ntt_status ntt_server_create(const ntt_server_config* cfg, ntt_server
   sv->cfg = *cfg;
   sv->base = reinterpret_cast<char*>(cfg->arena);
   sv->adm.init(cfg->arena_bytes, cfg->max_slots);
-  const int nstreams = std::min(cfg->max_slots, 8);
+  const int nstreams = std::min(cfg->max_slots, 16);  // slot streams (as the batched pool)
   for (int i = 0; i < nstreams + 2; ++i) {
     hipStream_t q;
     hipError_t e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
