@@ -180,6 +180,14 @@ PassArgs pass_args(const Ctx& c, const Stage& s, const float* X, float* H, const
 }
 
 hipError_t run_pass(hipStream_t q, const Stage& s, const PassArgs& a, bool update, bool resid) {
+  if (s.kind == PASS_S && s.tiny && update) {
+    // a residual with the update: the 16-row-block pass first, on the incoming (W, H)
+    if (resid) {
+      const hipError_t e = launch_pass_fused(a, s.rp, s.mb, s.G, false, true, false, q);
+      if (e != hipSuccess) return e;
+    }
+    return launch_pass_tiny(a, s.G, q);
+  }
   if (s.kind == PASS_S) return launch_pass_fused(a, s.rp, s.mb, s.G, update, resid, s.wide, q);
   if (s.kind == PASS_L) return launch_pass_L(a, s.rp, s.cls, s.G, update, resid, s.wide, q);
   if (s.kind == PASS_C) return launch_pass_C(a, s.rp, s.G, update, resid, q);

@@ -37,6 +37,12 @@ int pass_L_waves(int cls) { return cls <= 2 ? 4 : 8; }
 
 int pass_L_batch(int cls, int rp) { return (rp == 16 && cls >= 0 && cls <= 3) ? 4 : 0; }
 
+// 256 threads, one column each, 4 columns per thread
+int pass_tiny_cols(int64_t m) {
+  (void)m;
+  return 1024;
+}
+
 // chunks of 512 rows, 8 waves of 64 rows (both paddings)
 int pass_C_rows(int rp) {
   (void)rp;
@@ -115,6 +121,15 @@ void classify_stage(Stage& s, int precision) {
     const int64_t units = s.wide ? ((ngroups + 3) / 4 + 3) / 4 : (ngroups + 3) / 4;
     if (s.wide && s.mb == 2) cap = std::min<int64_t>(cap, kR8WCap);
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, cap));
+    // at most 4 rows (then r <= 4): the update passes take one column per lane on the
+    // VALU once there are enough columns; the partials (m r + r r <= 32 floats per
+    // workgroup) stay far below the X bytes at up to 1024 workgroups
+    if (s.m <= 4 && ngroups >= 256) {
+      s.tiny = true;
+      s.wide = false;
+      s.G = (int)std::max<int64_t>(
+          1, std::min<int64_t>(kMaxPassBlocks, (s.k + pass_tiny_cols(s.m) - 1) / pass_tiny_cols(s.m)));
+    }
   } else if (s.cls >= 0) {
     s.kind = PASS_L;
     // the batched update pass takes B whole groups per step; otherwise column groups
@@ -146,7 +161,7 @@ void classify_stage(Stage& s, int precision) {
   s.fused = s.kind == PASS_S || s.kind == PASS_L;
   // (a prologue in the wide row-split pass was measured slower than the separate
   // W-update launch: every workgroup waits for it before its first load)
-  s.pro_ok = s.kind == PASS_S && s.r <= 8 && s.m <= 32;
+  s.pro_ok = s.kind == PASS_S && s.r <= 8 && s.m <= 32 && !s.tiny;
   // BF16 X is read by the S passes at rank padding 16, the row-split and the row-chunked
   // passes; stages the single-workgroup kernel takes (small unfoldings), the S pass at
   // padding 32 and the generic path stay FP32

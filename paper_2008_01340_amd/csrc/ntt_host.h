@@ -40,6 +40,8 @@ int pass_L_waves(int cls);
 // 16-column groups per step of the wide row-split update pass for a row class (0: the
 // class has no wide pass); a wide stage's grid takes ceil(groups / 4) steps.
 int pass_L_batch(int cls, int rp);
+// Pass for m <= 4 rows: columns one workgroup takes per round.
+int pass_tiny_cols(int64_t m);
 // Row-chunked pass (m beyond one workgroup): rows per chunk.
 int pass_C_rows(int rp);
 // Whole stage in one workgroup (small unfoldings), and the 16-column groups its kernel
@@ -74,6 +76,7 @@ struct Stage {
   bool pro_ok = false;  // the update pass can apply the W-update in its prologue (r <= 8 pass)
   bool pairs = false;  // PASS_L, PASS_C: column groups taken in pairs
   bool wide = false;   // PASS_L, PASS_S (r <= 8): update passes in 64-column steps
+  bool tiny = false;   // PASS_S, m <= 4: update passes one column per lane (no MFMA)
   int G = 1;        // number of partials (pass workgroups or column chunks)
   int64_t chunk = 0;  // generic: columns per chunk
   bool bf16 = false;  // BF16 mode: this stage's X passes read a BF16 copy of X

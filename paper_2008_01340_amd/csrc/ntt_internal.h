@@ -141,6 +141,9 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* part, int nblocks, in
 hipError_t launch_gram_w(const float* W, int m, int r, int rp, float* G, hipStream_t s);
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,
                              bool wide, hipStream_t s);
+// Update pass for m <= 4 rows (one column per lane, no MFMA); grid: any number of
+// workgroups, each taking pass_tiny_cols(m) columns per round.
+hipError_t launch_pass_tiny(const PassArgs& a, int grid, hipStream_t s);
 // wide: update passes by the wide pass (a residual with them runs the per-group pass
 // first); otherwise every pass by the per-group row-split pass
 hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool update, bool resid,

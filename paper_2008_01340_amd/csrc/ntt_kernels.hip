@@ -788,6 +788,110 @@ __global__ __launch_bounds__(256, 1) void k_mu_pass_r8(PassArgs p) {
   for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * 8 + (e % r)];
 }
 
+// ------------------------------------------------------------------ pass for at most 4 rows
+// Update pass for unfoldings of m <= MP <= 4 rows (so r <= 4 too), where a 16-row MFMA
+// tile would be mostly padding: one column per lane on the VALU.  Per column j:
+// x = X[:, j], h = H[:, j] (coalesced across the workgroup, U columns per lane with all
+// their loads issued together); N = W^T x and D = G_W h (rows and ranks in order, FP32),
+// H_new = max(0, h N / (D + eps)) stored; x H_new^T and H_new H_new^T accumulated per
+// lane.  At the end each accumulator is summed over the wave's 64 lanes by a fixed
+// butterfly and over the 4 waves in order: one partial per workgroup (m x r, then r x r).
+// Rows >= m and ranks >= r: W, G_W and H beyond them are zero, so they add nothing.
+// (At 8 rows the loop-invariant W and G_W held in registers next to 128 accumulators
+// take all 256 VGPRs, one wave per SIMD; 5..8 rows stay on the 16-row-block pass.)
+template <int MP, int U, bool XBF>
+__global__ __launch_bounds__(256) void k_mu_pass_tiny(PassArgs p) {
+  __shared__ float sW[MP][MP];  // W (m x r), zero padded
+  __shared__ float sG[MP][MP];  // W^T W, zero padded
+  __shared__ float sAcc[4][2 * MP * MP];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  if (tid < MP * MP) {
+    const int i = tid / MP, q = tid % MP;
+    sW[i][q] = zmask(p.W[(int64_t)min(i, m - 1) * r + min(q, r - 1)], i < m && q < r);
+    sG[i][q] = zmask(p.GW[i * 16 + q], i < r && q < r);
+  }
+  __syncthreads();
+  float axh[MP][MP], ahh[MP][MP];
+#pragma unroll
+  for (int i = 0; i < MP; ++i)
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+      axh[i][q] = 0.f;
+      ahh[i][q] = 0.f;
+    }
+  const int64_t span = (int64_t)256 * U;
+  for (int64_t base = (int64_t)blockIdx.x * span; base < k; base += (int64_t)gridDim.x * span) {
+    float x[U][MP], h[U][MP];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t cc = min(base + 256 * u + tid, k - 1);
+#pragma unroll
+      for (int i = 0; i < MP; ++i) x[u][i] = ldx<XBF>(p, (int64_t)min(i, m - 1) * k + cc);
+#pragma unroll
+      for (int q = 0; q < MP; ++q) h[u][q] = p.H[(int64_t)min(q, r - 1) * k + cc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = base + 256 * u + tid;
+      const bool ok = c < k;
+      float hn[MP];
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        float nq = 0.f, dq = 0.f;
+#pragma unroll
+        for (int i = 0; i < MP; ++i) nq = fmaf(sW[i][q], x[u][i], nq);
+#pragma unroll
+        for (int pp = 0; pp < MP; ++pp) dq = fmaf(sG[q][pp], h[u][pp], dq);
+        const float hq = zmask(h[u][q], ok && q < r);
+        hn[q] = fmaxf(0.f, fast_div(hq * nq, dq + p.eps));
+      }
+      if (ok) {
+#pragma unroll
+        for (int q = 0; q < MP; ++q)
+          if (q < r) p.H[(int64_t)q * k + c] = hn[q];
+      }
+#pragma unroll
+      for (int i = 0; i < MP; ++i)
+#pragma unroll
+        for (int q = 0; q < MP; ++q) axh[i][q] = fmaf(x[u][i], hn[q], axh[i][q]);
+#pragma unroll
+      for (int q = 0; q < MP; ++q)
+#pragma unroll
+        for (int pp = 0; pp < MP; ++pp) ahh[q][pp] = fmaf(hn[q], hn[pp], ahh[q][pp]);
+    }
+  }
+  // the 64 lanes by a fixed butterfly, then the waves in order
+#pragma unroll
+  for (int i = 0; i < MP; ++i)
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+      float v = axh[i][q], g = ahh[i][q];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        v += __shfl_xor(v, off, 64);
+        g += __shfl_xor(g, off, 64);
+      }
+      if (lane == 0) {
+        sAcc[w][i * MP + q] = v;
+        sAcc[w][MP * MP + i * MP + q] = g;
+      }
+    }
+  __syncthreads();
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+  if (tid < 2 * MP * MP) {
+    const float v = ((sAcc[0][tid] + sAcc[1][tid]) + sAcc[2][tid]) + sAcc[3][tid];
+    if (tid < MP * MP) {
+      const int i = tid / MP, q = tid % MP;
+      if (i < m && q < r) dst[i * r + q] = v;
+    } else {
+      const int e = tid - MP * MP, q = e / MP, pp = e % MP;
+      if (q < r && pp < r) dst[m * r + q * r + pp] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ wide r <= 8 pass
 // The r <= 8 pass over 64-column steps, one step per wave, X read as in the wide
 // row-split pass: lane (a, b) loads X[4i + b][j0 + 4a .. 4a + 3] for row quads i (4 rows
@@ -3092,6 +3196,20 @@ static hipError_t pass_fused_rp(const PassArgs& a, int mb, int grid, bool update
     case 2: return pass_fused_mb<RP, 2>(a, grid, update, resid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_pass_tiny(const PassArgs& a, int grid, hipStream_t s) {
+  if (a.m < 1 || a.m > 4 || a.r < 1 || a.r > a.m || a.Wprev != nullptr || grid < 1) return hipErrorInvalidValue;
+  const bool xb = a.Xb != nullptr;
+  if (a.m <= 2) {
+    if (xb) k_mu_pass_tiny<2, 4, true><<<grid, 256, 0, s>>>(a);
+    else k_mu_pass_tiny<2, 4, false><<<grid, 256, 0, s>>>(a);
+  } else {
+    if (xb) k_mu_pass_tiny<4, 4, true><<<grid, 256, 0, s>>>(a);
+    else k_mu_pass_tiny<4, 4, false><<<grid, 256, 0, s>>>(a);
+  }
+  NTT_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool update, bool resid,

@@ -65,6 +65,9 @@ void check_stage(const PlanLayout& p, const Stage& s, int l, const char* what) {
   switch (s.kind) {
     case PASS_S:
       CHECK(s.m <= 32 && (s.mb == 1 || s.mb == 2) && 16 * s.mb >= s.m, "%s %d: S pass rows", what, l);
+      CHECK(!s.tiny || (s.m <= 4 && s.r <= s.m && !s.wide && !s.pro_ok && s.G <= 1024 &&
+                        (int64_t)s.G * pass_tiny_cols(s.m) >= std::min<int64_t>(s.k, 1024LL * pass_tiny_cols(s.m))),
+            "%s %d: pass for at most 4 rows", what, l);
       break;
     case PASS_L:
       CHECK(s.cls >= 0 && s.m <= (s.rp == 16 ? 1024 : 512), "%s %d: row-split class", what, l);

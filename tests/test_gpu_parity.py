@@ -94,6 +94,9 @@ SHAPES = [
     # the wide r <= 8 pass (>= 4096 groups): 32 rows with an odd k (every step on the
     # masked path), 16 rows of whole steps, 25 rows with a ragged last step
     (30, 70001, 7), (16, 65600, 8), (25, 66000, 5),
+    # at most 4 rows past the whole-stage kernel's 32768 columns: one column per lane
+    # (ragged last round, r < m, r = m)
+    (2, 300001, 2), (3, 65537, 3), (4, 200000, 2), (1, 40000, 1),
 ]
 
 
@@ -670,6 +673,8 @@ BF16_BAR = 1e-3  # |e_bf16 - e_oracle| on the final relative error (Eq.(3))
     # cores), and rows in chunks of 512 (stage 2, 1280 x 1200)
     ((128, 24, 40, 36), (1, 16, 16, 8, 1), "absnormal", 0.01, 100),
     ((40, 80, 40, 30), (1, 16, 16, 8, 1), "absnormal", 0.01, 100),
+    # stage 1 of 3 rows (3 x 64000) on the pass that takes one column per lane
+    ((3, 40, 40, 40), (1, 3, 8, 6, 1), "mult", 0.01, 100),
 ])
 def test_bf16_mode_final_error_matches_oracle(dims, gen, noise, level, T):
     say(f"case: BF16 mode dims={dims} ranks={gen} T={T} tail=20")
@@ -721,11 +726,12 @@ def _mix_problems():
             ((9, 20, 8, 6), (1, 5, 6, 3, 1), 5), ((30, 40, 12), (1, 12, 9, 1), 8),
             ((12, 10, 11, 9, 8), (1, 4, 7, 5, 2, 1), 21), ((64, 33, 50), (1, 10, 12, 1), 3),
             ((8, 8, 8), (1, 2, 2, 1), 13), ((40, 9, 17, 23), (1, 8, 11, 6, 1), 17),
-            ((1100, 6, 5), (1, 5, 4, 1), 23)]  # stage 1 (1100 x 30) iterates transposed
+            ((1100, 6, 5), (1, 5, 4, 1), 23),  # stage 1 (1100 x 30) iterates transposed
+            ((3, 50, 100), (1, 3, 6, 1), 29)]  # stage 1 (3 x 5000): one column per lane
 
 
 def test_batched_results_equal_standalone_results_bitwise():
-    say("case: batch of 8 uneven problems vs ntt_decompose one by one")
+    say("case: batch of 10 uneven problems vs ntt_decompose one by one")
     probs = _mix_problems()
     tensors = [dev(S.contract_cores(S.random_cores(dm, rk, seed=sd))) for dm, rk, sd in probs]
     T = 60
@@ -741,7 +747,7 @@ def test_batched_results_equal_standalone_results_bitwise():
 
 
 def test_batched_results_match_oracle():
-    say("case: batch of 8 uneven problems vs the oracle")
+    say("case: batch of 10 uneven problems vs the oracle")
     probs = _mix_problems()
     host_t = [S.contract_cores(S.random_cores(dm, rk, seed=sd)) for dm, rk, sd in probs]
     T = 40
@@ -775,7 +781,7 @@ def _pinned(a):
 
 
 def test_serving_results_equal_standalone_results_and_budget_defers_admission():
-    say("case: serving, 8 requests, arena for ~2 at a time, 25 iterations per tick")
+    say("case: serving, 10 requests, arena for ~2 at a time, 25 iterations per tick")
     probs = _mix_problems()
     T = 80
     host_t = [S.contract_cores(S.random_cores(dm, rk, seed=sd)) for dm, rk, sd in probs]
