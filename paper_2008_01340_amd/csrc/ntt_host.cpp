@@ -152,8 +152,14 @@ void classify_stage(Stage& s, int precision) {
     // when there are many row chunks; more only adds partials (G (m r + r r) floats
     // written and reduced per iteration, kept near 10% of the X bytes above that floor)
     const int64_t gfloor = std::min<int64_t>(128, (1024 + s.nch - 1) / s.nch);
-    const int64_t gcap_c = std::max<int64_t>(
+    int64_t gcap_c = std::max<int64_t>(
         gfloor, std::min<int64_t>(1024, (int64_t)(0.1 * (double)s.m * (double)s.k / Ed)));
+    // up to 64 partials are reduced one thread per entry with every load in flight; a grid
+    // of 65..128 column chunks gains less in the pass than its slower reduction costs
+    // (128^4 stage 2, 2048 x 16384: 64 chunks 18.1 ms, 101 21.4 ms, 128 20.4 ms), while
+    // far larger grids pay off (256^4 stage 2, 2560 x 65536: 652 chunks 41.6 ms, 64 57.2
+    // ms); the (64, chunks) grid keeps at least 256 workgroups from 4 chunks on
+    if (gcap_c <= 128 && s.nch >= 4) gcap_c = std::min<int64_t>(gcap_c, 64);
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(s.pairs ? (ngroups + 1) / 2 : ngroups, gcap_c));
   } else {
     s.kind = PASS_GENERIC;
