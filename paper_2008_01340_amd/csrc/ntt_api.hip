@@ -1027,7 +1027,7 @@ extern "C" ntt_status ntt_tt_workspace(int32_t d, const int64_t* dims, const int
   ntt_status st = tt_args(d, dims, ranks, dummy.data(), &t);
   if (st != NTT_OK) return st;
   if (!bytes) return fail(NTT_ERR_INVALID_ARG, "null bytes");
-  const int64_t nb = (t.rows + 63) / 64;
+  const int64_t nb = tt_blocks(t.rows, t.dims[d - 1]);
   *bytes = align_up((size_t)(2 * nb + 2) * sizeof(double), 256);
   return NTT_OK;
 }
@@ -1059,7 +1059,7 @@ extern "C" ntt_status ntt_rel_error(int32_t d, const int64_t* dims, const int64_
   t.part = reinterpret_cast<double*>(workspace);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_tt_expand(t, 1, s));
-  const int64_t nb = (t.rows + 63) / 64;
+  const int64_t nb = tt_blocks(t.rows, t.dims[d - 1]);
   double tot[2];
   HIP_TRY(hipMemcpyAsync(tot, t.part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1106,11 +1106,16 @@ extern "C" ntt_status ntt_rel_error_static(int32_t d, const int64_t* dims, const
   size_t need = 0;
   ntt_status st = ntt_tt_workspace(d, dims, ranks, &need);
   if (st != NTT_OK) return st;
-  if (need > NTT_REL_ERROR_STATIC_BYTES)
+  // the limit in rows: (8 MiB / 8 - 2) / 2 blocks of 64 rows; the partials of every tensor
+  // within it fit the array whatever n_d (fewer blocks for n_d < 64, column ranges only
+  // below 2048 row blocks)
+  constexpr int64_t kStaticRows = (int64_t)((NTT_REL_ERROR_STATIC_BYTES / sizeof(double) - 2) / 2) * 64;
+  int64_t rows = 1;
+  for (int i = 0; i < d - 1; ++i) rows *= dims[i];
+  if (rows > kStaticRows || need > NTT_REL_ERROR_STATIC_BYTES)
     return fail(NTT_ERR_WORKSPACE_TOO_SMALL,
                 "tensor too large for ntt_rel_error_static: n_1...n_{d-1} must be at most " +
-                    std::to_string((NTT_REL_ERROR_STATIC_BYTES / sizeof(double) - 2) / 2 * 64) +
-                    " (use ntt_rel_error with a workspace)");
+                    std::to_string(kStaticRows) + " (use ntt_rel_error with a workspace)");
   double* ws = nullptr;
   st = static_scratch(&ws);
   if (st != NTT_OK) return st;

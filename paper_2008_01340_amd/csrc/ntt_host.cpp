@@ -96,6 +96,22 @@ void gram_rows_plan(int64_t m, int64_t k, int* nsplit, size_t* part_doubles) {
   *part_doubles = (size_t)npairs * (size_t)ns * 4096;
 }
 
+int tt_rows_per_block(int64_t nd) { return nd < 64 ? 128 : 64; }
+
+// about 2048 blocks in all when the rows alone give fewer, each column range at least
+// 1024 columns
+int64_t tt_col_splits(int64_t rows, int64_t nd) {
+  const int rpb = tt_rows_per_block(nd);
+  const int64_t rb = (rows + rpb - 1) / rpb;
+  if (rb >= 2048 || nd <= 1024) return 1;
+  return std::max<int64_t>(1, std::min<int64_t>({(2048 + rb - 1) / rb, (nd + 1023) / 1024, 65535}));
+}
+
+int64_t tt_blocks(int64_t rows, int64_t nd) {
+  const int rpb = tt_rows_per_block(nd);
+  return (rows + rpb - 1) / rpb * tt_col_splits(rows, nd);
+}
+
 // ------------------------------------------------------------------ stage classes
 // Pass kind, row class and workgroup count of an m x k, rank-r problem.
 void classify_stage(Stage& s, int precision) {

@@ -98,6 +98,13 @@ void stage_shape(const ntt_config& cfg, int64_t m, int64_t k, int r, Stage& s, S
 // Column chunks of the generic X H^T partials.
 void generic_chunks(const Stage& s, int* G, int64_t* chunk);
 
+// Eq.(1)-(3) kernels: rows per block of the n_1...n_{d-1} x n_d matrix (64, or 128 for
+// n_d < 64), column ranges per row block (more than one when there are few row blocks),
+// and the blocks' FP64 partial pairs.
+int tt_rows_per_block(int64_t nd);
+int64_t tt_col_splits(int64_t rows, int64_t nd);
+int64_t tt_blocks(int64_t rows, int64_t nd);
+
 // ---- the plan: validated config, effective ranks, stage classes, workspace layout
 struct Region {
   const char* name;

@@ -3017,33 +3017,40 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
 }
 
 // ------------------------------------------------------------------ TT expand (Eq.(2))
-// Rows of the (n_1...n_{d-1}) x n_d matrix of the full tensor, 64 per block.  Each row's
-// left factor P[row,:] = G_1[i_1,:] G_2[:,i_2,:] ... G_{d-1}[:,i_{d-1},:] is formed in
-// LDS (FP32), then Ahat[row, col] = P[row,:] . G_d[:, col].  MODE 0 writes Ahat; MODE 1
-// accumulates sum (A - Ahat)^2 and sum A^2 in FP64 per block.
-template <int MODE>
+// Rows of the (n_1...n_{d-1}) x n_d matrix of the full tensor, ROWS per block (blockIdx.x),
+// columns split into gridDim.y ranges (blockIdx.y) when there are few row blocks.  Each
+// row's left factor P[row,:] = G_1[i_1,:] G_2[:,i_2,:] ... G_{d-1}[:,i_{d-1},:] is formed
+// in LDS (FP32, zero beyond the rank), then Ahat[row, col] = P[row,:] . G_d[:, col]
+// (ranks in order, RLP >= r_{d-1} terms, the padding adding exact zeros): each thread
+// takes CPT adjacent columns at a time, holds their G_d columns in registers and runs down
+// a share of the block's rows.  MODE 0 writes Ahat; MODE 1 accumulates sum (A - Ahat)^2
+// and sum A^2 in FP64 (thread order, a fixed butterfly, the waves in order) into
+// part[2 b], part[2 b + 1] with b = blockIdx.x + gridDim.x blockIdx.y.
+template <int MODE, int ROWS, int RLP, int CPT>
 __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
-  __shared__ float sP[2][64][NTT_MAX_RANK + 1];
-  __shared__ int sIdx[64][NTT_MAX_DIMS];
+  constexpr int PW = NTT_MAX_RANK + 1;
+  __shared__ float sP[2][ROWS][PW];
+  __shared__ int sIdx[ROWS][NTT_MAX_DIMS];
   __shared__ double sRed[2][4];
   const int tid = threadIdx.x;
   const int d = t.d;
   const int64_t rows = t.rows;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int nrow = (int)min((int64_t)64, rows - r0);
-  if (tid < nrow) {
-    int64_t rem = r0 + tid;
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+  const int nrow = (int)min((int64_t)ROWS, rows - r0);
+  for (int rr = tid; rr < nrow; rr += 256) {
+    int64_t rem = r0 + rr;
     for (int kx = d - 2; kx >= 0; --kx) {
-      sIdx[tid][kx] = (int)(rem % t.dims[kx]);
+      sIdx[rr][kx] = (int)(rem % t.dims[kx]);
       rem /= t.dims[kx];
     }
   }
+  for (int e = tid; e < 2 * ROWS * PW; e += 256) (&sP[0][0][0])[e] = 0.f;
   __syncthreads();
   // P_1 = G_1[i_1, :]
   int cur = 0;
   {
     const int rk = t.ranks[1];
-    for (int e = tid; e < 64 * rk; e += 256) {
+    for (int e = tid; e < ROWS * rk; e += 256) {
       const int rr = e / rk, c = e % rk;
       sP[0][rr][c] = zmask(t.cores[0][(int64_t)sIdx[min(rr, nrow - 1)][0] * rk + c], rr < nrow);
     }
@@ -3053,7 +3060,7 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
     const int ra = t.ranks[kx], rb = t.ranks[kx + 1];
     const int64_t nk = t.dims[kx];
     const float* G = t.cores[kx];
-    for (int e = tid; e < 64 * rb; e += 256) {
+    for (int e = tid; e < ROWS * rb; e += 256) {
       const int rr = e / rb, c = e % rb;
       float s = 0.f;
       if (rr < nrow) {
@@ -3069,21 +3076,62 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
   const int rl = t.ranks[d - 1];
   const int64_t nd = t.dims[d - 1];
   const float* Gd = t.cores[d - 1];
-  const int64_t base = r0 * nd;
-  const int64_t cnt = (int64_t)nrow * nd;
+  const int64_t span = ((nd + gridDim.y - 1) / gridDim.y + CPT - 1) / CPT * CPT;
+  const int64_t c0 = (int64_t)blockIdx.y * span, c1 = min(nd, c0 + span);
+  // W threads across the range's CPT-column groups (rounded up to a power of two, at most
+  // 256) times 256 / W across rows
+  const int64_t ngrp = c1 > c0 ? (c1 - c0 + CPT - 1) / CPT : 0;
+  int W = 256;
+  while (W > 1 && W / 2 >= ngrp) W >>= 1;
+  const int lanes = 256 / W;
   double s_err = 0.0, s_ref = 0.0;
-  for (int64_t e = tid; e < cnt; e += 256) {
-    const int rr = (int)(e / nd);
-    const int64_t col = e - (int64_t)rr * nd;
-    float s = 0.f;
-    for (int q = 0; q < rl; ++q) s = fmaf(sP[cur][rr][q], Gd[(int64_t)q * nd + col], s);
-    if (MODE == 0) {
-      t.out[base + e] = s;
-    } else {
-      const double av = (double)t.A[base + e];
-      const double dv = av - (double)s;
-      s_err += dv * dv;
-      s_ref += av * av;
+  for (int64_t gi = tid % W; gi < ngrp; gi += W) {
+    const int64_t col = c0 + CPT * gi;
+    float g[CPT][RLP];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u)
+#pragma unroll
+      for (int q = 0; q < RLP; ++q)
+        g[u][q] = zmask(Gd[(int64_t)min(q, rl - 1) * nd + min(col + u, c1 - 1)], q < rl);
+    for (int rr = tid / W; rr < nrow; rr += lanes) {
+      float sv[CPT];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) sv[u] = 0.f;
+#pragma unroll
+      for (int q = 0; q < RLP; ++q) {
+        const float pq = sP[cur][rr][q];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) sv[u] = fmaf(pq, g[u][q], sv[u]);
+      }
+      const int64_t at = (r0 + rr) * nd + col;
+      if (CPT == 4 && col + 4 <= c1) {
+        if (MODE == 0) {
+          *reinterpret_cast<float4*>(t.out + at) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+        } else {
+          const float4 a4 = *reinterpret_cast<const float4*>(t.A + at);
+          const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double dv = (double)av[u] - (double)sv[u];
+            s_err += dv * dv;
+            s_ref += (double)av[u] * (double)av[u];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          if (col + u < c1) {
+            if (MODE == 0) {
+              t.out[at + u] = sv[u];
+            } else {
+              const double av = (double)t.A[at + u];
+              const double dv = av - (double)sv[u];
+              s_err += dv * dv;
+              s_ref += av * av;
+            }
+          }
+        }
+      }
     }
   }
   if (MODE == 1) {
@@ -3095,8 +3143,9 @@ __global__ __launch_bounds__(256) void k_tt_expand(TTArgs t) {
     }
     __syncthreads();
     if (tid == 0) {
-      t.part[2 * blockIdx.x] = ((sRed[0][0] + sRed[0][1]) + sRed[0][2]) + sRed[0][3];
-      t.part[2 * blockIdx.x + 1] = ((sRed[1][0] + sRed[1][1]) + sRed[1][2]) + sRed[1][3];
+      const int64_t b = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+      t.part[2 * b] = ((sRed[0][0] + sRed[0][1]) + sRed[0][2]) + sRed[0][3];
+      t.part[2 * b + 1] = ((sRed[1][0] + sRed[1][1]) + sRed[1][2]) + sRed[1][3];
     }
   }
 }
@@ -3502,14 +3551,41 @@ hipError_t launch_resid_sum(const double* rpart, int G, double* obj, double* tra
   return hipSuccess;
 }
 
+template <int MODE, int ROWS, int RLP>
+static void tt_launch(const TTArgs& t, dim3 grid, bool vec4, hipStream_t s) {
+  if (vec4) k_tt_expand<MODE, ROWS, RLP, 4><<<grid, 256, 0, s>>>(t);
+  else k_tt_expand<MODE, ROWS, RLP, 1><<<grid, 256, 0, s>>>(t);
+}
+
+template <int MODE, int ROWS>
+static void tt_launch_rl(const TTArgs& t, int rl, dim3 grid, bool vec4, hipStream_t s) {
+  if (rl <= 8) tt_launch<MODE, ROWS, 8>(t, grid, vec4, s);
+  else if (rl <= 16) tt_launch<MODE, ROWS, 16>(t, grid, vec4, s);
+  else tt_launch<MODE, ROWS, 32>(t, grid, vec4, s);
+}
+
 hipError_t launch_tt_expand(const TTArgs& t, int mode, hipStream_t s) {
-  const int64_t nb = (t.rows + 63) / 64;
-  if (nb <= 0) return hipSuccess;
-  if (mode == 0) k_tt_expand<0><<<(unsigned)nb, 256, 0, s>>>(t);
-  else k_tt_expand<1><<<(unsigned)nb, 256, 0, s>>>(t);
+  const int64_t nd = t.dims[t.d - 1];
+  const int rpb = tt_rows_per_block(nd);
+  const int64_t rb = (t.rows + rpb - 1) / rpb;
+  if (rb <= 0) return hipSuccess;
+  const int64_t cs = tt_col_splits(t.rows, nd);
+  if (rb > 0x7fffffffLL || cs > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)rb, (unsigned)cs);
+  const int rl = t.ranks[t.d - 1];
+  // four adjacent columns per thread (16-byte accesses) on rows of whole float4s
+  const void* io = mode == 0 ? static_cast<const void*>(t.out) : static_cast<const void*>(t.A);
+  const bool vec4 = nd % 4 == 0 && nd >= 256 && (reinterpret_cast<uintptr_t>(io) & 15) == 0;
+  if (mode == 0) {
+    if (rpb == 128) tt_launch_rl<0, 128>(t, rl, grid, vec4, s);
+    else tt_launch_rl<0, 64>(t, rl, grid, vec4, s);
+  } else {
+    if (rpb == 128) tt_launch_rl<1, 128>(t, rl, grid, vec4, s);
+    else tt_launch_rl<1, 64>(t, rl, grid, vec4, s);
+  }
   NTT_CHECK_LAUNCH();
   if (mode == 1) {
-    k_sum_pairs<<<1, 64, 0, s>>>(t.part, nb, t.part + 2 * nb);
+    k_sum_pairs<<<1, 64, 0, s>>>(t.part, rb * cs, t.part + 2 * rb * cs);
     NTT_CHECK_LAUNCH();
   }
   return hipSuccess;

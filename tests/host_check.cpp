@@ -286,6 +286,26 @@ void check_admission(int rounds) {
   printf("admission: %d rounds\n", rounds);
 }
 
+// Eq.(3) partial blocks: at least one column range, at most 65535, and the fixed 8 MiB
+// array of ntt_rel_error_static holds the partials of every tensor of up to 33,554,368
+// rows n_1...n_{d-1}, whatever n_d
+void check_tt_blocks(int n) {
+  Rng g{99};
+  for (int it = 0; it < n; ++it) {
+    const int64_t rows = g.logint(g.uniform(0, 3) == 0 ? 33554368 : (1LL << 40));
+    const int64_t nd = g.logint(1LL << 34);
+    const int64_t cs = tt_col_splits(rows, nd);
+    const int rpb = tt_rows_per_block(nd);
+    CHECK((rpb == 64 || rpb == 128) && cs >= 1 && cs <= 65535 && (cs == 1 || (rows + rpb - 1) / rpb < 2048),
+          "tt splits %lld for %lld x %lld", (long long)cs, (long long)rows, (long long)nd);
+    CHECK(tt_blocks(rows, nd) == (rows + rpb - 1) / rpb * cs, "tt blocks");
+    if (rows <= 33554368)
+      CHECK((size_t)(2 * tt_blocks(rows, nd) + 2) * sizeof(double) <= NTT_REL_ERROR_STATIC_BYTES,
+            "static Eq.(3) array too small for %lld x %lld", (long long)rows, (long long)nd);
+  }
+  printf("tt blocks: %d shapes\n", n);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -293,6 +313,7 @@ int main(int argc, char** argv) {
   check_plans(n);
   check_arena(n / 100 + 1);
   check_admission(n / 100 + 1);
+  check_tt_blocks(n);
   if (g_fail) {
     printf("%d checks failed\n", g_fail);
     return 1;
