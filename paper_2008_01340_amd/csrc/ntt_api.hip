@@ -143,7 +143,8 @@ struct Ctx {
   double* scal(int l) const {  // FP64 scalars of stage l (1-based)
     return reinterpret_cast<double*>(ws + p->off_scal) + (size_t)SCAL_COUNT * (l - 1);
   }
-  int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }  // [0] input flags
+  // [0] input flags, [8] cooperative-stage status, [32] W-update arrival counter
+  int* ints() const { return reinterpret_cast<int*>(ws + p->off_ints); }
   uint16_t* xb() const { return reinterpret_cast<uint16_t*>(ws + p->off_xb); }
   float* xt() const { return reinterpret_cast<float*>(ws + p->off_xt); }
   float* wp() const { return reinterpret_cast<float*>(ws + p->off_wp); }
@@ -452,6 +453,7 @@ struct NttJob {
     fa.r = e.r;
     fa.red = c.red();
     fa.gpart = c.gpart();
+    fa.arrive = reinterpret_cast<unsigned*>(c.ints() + 32);  // zeroed with the ints at job start
     fa.W = trans ? c.wp() : W;
     fa.GW = c.gw();
     fa.scal = c.scal(l);

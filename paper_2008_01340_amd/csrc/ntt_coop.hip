@@ -42,19 +42,6 @@ namespace {
 constexpr int kCoopWaves = 8;           // 512 threads, wave w owns rows 32 w .. 32 w + 31
 constexpr long kCoopMaxPolls = 1L << 18;
 
-__device__ __forceinline__ void st_dev(float* p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ld_dev(const float* p) {
-  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Grid barrier at `epoch` (1, 2, ...): false when it timed out (then every thread of the
 // workgroup returns false and the caller leaves).
 __device__ __forceinline__ bool coop_barrier(const CoopArgs& c, unsigned epoch, int* sAbort) {

@@ -1,6 +1,6 @@
 // ntt_device.h -- device helpers shared by the kernel sources: MFMA wrappers, wave-level
 // synchronisation and sums, masked loads, the FP32 divide of the MU epilogues, the
-// W-update row and the FP64 Gram of W's rows.
+// W-update entry, device-scope accesses and the FP64 Gram of W's rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,23 +40,33 @@ __device__ __forceinline__ v4d mfma16_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One row of the W-update in FP64 on FP32 data (shared by k_wupdate and the pass
-// prologues, so that both give the same bits): out[c] = max(0, w[c] n[c] / (sum_q w[q]
-// G_H[q][c] + eps)) for c < r, 0 beyond; *dot accumulates <out, n>.
+// Entry c of a row of the W-update in FP64 on FP32 data (shared by the W-update kernel and
+// the pass prologues, so that both give the same bits): with D = sum_{q < RB} w[q] G_H[q][c]
+// (q in order; w and G_H zero padded past r), max(0, w[c] n / (D + eps)) rounded to FP32.
+// The caller masks columns c >= r.
 template <int RB>
-__device__ __forceinline__ void wupdate_row(const float (&wrow)[RB], const double (&nrow)[RB],
-                                            const double (*sGH)[RB + 1], int r, float eps,
-                                            float* out, double* dot) {
+__device__ __forceinline__ float wupdate_entry(const float* wrow, double n, const double (*sGH)[RB + 1],
+                                               int c, float eps) {
+  double dw = 0.0;
 #pragma unroll
-  for (int c = 0; c < RB; ++c) {
-    double dw = 0.0;
-#pragma unroll
-    for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
-    const double wn = fmax(0.0, (double)wrow[c] * nrow[c] / (dw + (double)eps));
-    const float wf = (c < r) ? (float)wn : 0.f;
-    out[c] = wf;
-    *dot += (double)wf * nrow[c];
-  }
+  for (int q = 0; q < RB; ++q) dw += (double)wrow[q] * sGH[q][c];
+  return (float)fmax(0.0, (double)wrow[c] * n / (dw + (double)eps));
+}
+
+// Device-scope relaxed accesses for data that crosses workgroups within one launch: they go
+// past the XCDs' non-coherent L2s, so a value stored by one workgroup (after the storing
+// wave's s_waitcnt) is what another workgroup loads, without a fence.
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_dev(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wavefront w's part of the Gram of the rows in LDS (FP64 MFMA, 16 x 16 x 4 tiles): rows

@@ -52,6 +52,7 @@ struct FinArgs {
   float eps;
   float* Wout;     // where the new W goes (NULL: W is updated in place)
   double* gpart;   // m > 256: per-block parts of W'^T W' and <W', X H^T>, ceil(m/256) x (32*32+1)
+  unsigned* arrive;  // m > 256: arrival counter of the W-update's blocks (zero between launches)
 };
 
 // A whole stage of MU iterations in one workgroup (small unfoldings).

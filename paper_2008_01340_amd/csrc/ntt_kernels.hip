@@ -9,8 +9,8 @@
 // the columns of X does the whole H-update and, while X[:,j] is still in registers,
 // accumulates X[:,j] H_new[:,j]^T and H_new[:,j] H_new[:,j]^T: X is read from HBM once
 // per iteration.  Per-workgroup partial sums are reduced in a fixed order (no float
-// atomics) by separate launches (k_reduce_partials, then k_wupdate or the row-split
-// k_wupdate_rows + k_wupdate_gram), which apply the W-update and form the next W^T W;
+// atomics) by separate launches (k_reduce_partials, then k_wupdate_t over blocks of 256
+// rows), which apply the W-update and form the next W^T W;
 // the r <= 8 passes can instead take that W-update in their own prologue.  Small stages
 // run whole in one workgroup (k_stage_1wg) or in one grid-synchronised launch (ntt_coop.hip).
 // The result equals the two-pass MU up to summation order.
@@ -480,53 +480,49 @@ __global__ __launch_bounds__(256) void k_mu_pass(PassArgs p) {
 
 // W^T (zero padded, 16 x MPAD) and G_W (8 x 8) of the r <= 8 passes in LDS: from W and
 // W^T W, or, in prologue mode (p.Wprev set), by applying the previous iteration's
-// W-update first (the rows of k_wupdate, one thread per row; the Gram by wavefront 0,
-// which holds every row since m <= 64); workgroup 0 then stores W to p.Wout.
+// W-update first (the entries of the W-update kernel, one thread per entry (row tid / 8,
+// column tid % 8); the Gram by wavefront 0, which holds every row since m <= 32);
+// workgroup 0 then stores W to p.Wout.
 template <int MPAD>
 __device__ __forceinline__ void r8_w_setup(const PassArgs& p, float (*sWt)[MPAD + 4], float (*sG)[8],
                                            int tid, int w, int a, int b) {
+  static_assert(8 * MPAD <= 256, "one thread per entry");
   const int m = p.m, r = p.r;
   if (p.Wprev) {
     __shared__ float sWc[MPAD][9];
     __shared__ double sGH[8][9];
     __shared__ double sGW[8][9];
-    float wrow[8];
-    double nrow[8];
-    {
-      const int64_t base = (int64_t)min(tid, m - 1) * r;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int qc = min(q, r - 1);
-        wrow[q] = zmask(p.Wprev[base + qc], q < r);
-        nrow[q] = zmask(p.red[base + qc], q < r);
-      }
-    }
+    const int i = tid >> 3, c = tid & 7;
     const int64_t mr = (int64_t)m * r;
-    if (tid < 64) {
-      const int c = tid >> 3, q = tid & 7;
-      sGH[c][q] = zmask(p.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
+    float wv = 0.f;
+    double nv = 0.0;
+    if (i < MPAD) {
+      const int64_t idx = (int64_t)min(i, m - 1) * r + min(c, r - 1);
+      wv = zmask(p.Wprev[idx], i < m && c < r);
+      nv = zmask(p.red[idx], i < m && c < r);
     }
+    if (tid < 64) {
+      const int gc = tid >> 3, gq = tid & 7;
+      sGH[gc][gq] = zmask(p.red[mr + min(gc, r - 1) * r + min(gq, r - 1)], gc < r && gq < r);
+    }
+    if (i < MPAD) sWc[i][c] = wv;
     __syncthreads();
-    if (tid < MPAD) {
-      if (tid < m) {
-        double dot = 0.0;
-        wupdate_row<8>(wrow, nrow, sGH, r, p.eps, sWc[tid], &dot);
-        if (blockIdx.x == 0) {
-#pragma unroll
-          for (int c = 0; c < 8; ++c)
-            if (c < r) p.Wout[(int64_t)tid * r + c] = sWc[tid][c];
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) sWc[tid][c] = 0.f;
-      }
+    float wf = 0.f;
+    if (i < MPAD) {
+      const float v = wupdate_entry<8>(sWc[i], nv, sGH, c, p.eps);
+      wf = (c < r && i < m) ? v : 0.f;
+    }
+    __syncthreads();  // every row has been read before it is replaced
+    if (i < MPAD) {
+      sWc[i][c] = wf;
+      if (blockIdx.x == 0 && i < m && c < r) p.Wout[(int64_t)i * r + c] = wf;
     }
     __syncthreads();
     if (w == 0) {
       v4d acc[1][1] = {{v4d{0.0, 0.0, 0.0, 0.0}}};
       gram_rows_f64<8, 1, MPAD>(sWc, acc, 0, a, b);
-      // the other wavefronts of k_wupdate add exact zeros; value i of lane (a, b) is
-      // row 4 i + b, column a
+      // (the W-update kernel's wavefront 0 forms the same sums over its 64 rows, the other
+      // wavefronts add exact zeros); value i of lane (a, b) is row 4 i + b, column a
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (4 * i + b < 8 && a < 8) sGW[4 * i + b][a] = acc[0][0][i];
@@ -2559,8 +2555,8 @@ __global__ __launch_bounds__(256) void k_gen_xht(PassArgs p, int64_t chunk) {
 //     of the E = m r + r r partial entries (X H^T then H H^T) over all G <= 1024
 //     partials: 64 lanes per entry, lane l taking partials l, l + 64, ... (all loads
 //     issued at once), then lanes in groups of eight and the groups in order, in FP64;
-// (2) k_wupdate: one block reads the sums and updates W.
-// With G <= 4, k_wupdate sums the FP32 partials itself (g = 0..G-1 in order).
+// (2) k_wupdate_t reads the sums and updates W.
+// With G <= 4, k_wupdate_t sums the FP32 partials itself (g = 0..G-1 in order).
 // The summation order is fixed, so results do not depend on scheduling.
 constexpr int kReduceLanes = 64;
 constexpr int kMaxReduceG = 16 * kReduceLanes;
@@ -2626,30 +2622,40 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const float* __restric
 }
 
 
-// k_wupdate: one block.  W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T
-//     and G_H = H H^T, 256 rows at a time, one thread per row (rows are independent,
-//     so the update is in place; each thread reads its whole row before writing it).
-//     FP64 arithmetic on FP32 data, rounded to FP32.  The new rows also go to LDS,
-//     from where each wavefront accumulates its 64 rows of G_W' = W'^T W' with FP64
-//     MFMA (16 x 16 x 4 tiles; four rows per step, in row order); the four wavefront
-//     sums are added in order.  It also writes the Gram-identity monitor
+// k_wupdate_t: W <- max(0, W .* N_W ./ (W G_H + eps)) with N_W = X H^T and G_H = H H^T,
+//     over blocks of 256 rows (block j: rows [256 j, 256 j + 256)) of 1024 threads, one
+//     thread per entry: thread t takes entries t, t + 1024, ... of the block's 256 x RB
+//     (row, column) grid.  Rows are independent, so the update is in place; each thread
+//     loads its entries, and the block its rows into LDS, before any is replaced.  FP64
+//     arithmetic on FP32 data, rounded to FP32 (wupdate_entry).  The new rows go to LDS,
+//     from where each of four wavefronts accumulates its 64 rows of the block's part of
+//     G_W' = W'^T W' with FP64 MFMA (16 x 16 x 4 tiles; four rows per step, in row order);
+//     the four wavefront sums are added in order, and the block parts in block order.
+//     With one block (m <= 256) the block writes G_W and the Gram-identity monitor
 //       f = 1/2 (||X||^2 - 2 <W', X H^T> + <W'^T W', H H^T>)
-//     and, when this iteration accumulated one, the explicit residual objective.
-//     RB >= r bounds the loops.  Entries are read from `red` or, when FUSED (G <= 4),
-//     summed from the FP32 partials in order.  The first 256 rows, G_H and ||X||^2 are
-//     loaded in one round before the first barrier (the kernel is latency-bound).
+//     and, when this iteration accumulated one, the explicit residual objective.  With
+//     several, each block stores its parts (G_W' and <W', N_W>) to gpart[j] with
+//     device-scope stores, waits for them to complete and counts itself in at `arrive`
+//     (a device-scope atomic add); the block that arrives last adds the parts, writes
+//     G_W and the monitor, and sets the counter back to zero for the next launch.  No
+//     block waits for another and no fence is needed: the parts are written and read past
+//     the XCDs' non-coherent L2s.  RB >= r bounds the loops.  Entries are read from `red`
+//     or, when FUSED (G <= 4), summed from the FP32 partials in order.
 template <int RB, bool FUSED>
-__global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
+__global__ __launch_bounds__(1024) void k_wupdate_t(FinArgs f) {
   constexpr int NT = (RB + 15) / 16;  // 16 x 16 tiles per side of the Gram
+  constexpr int EPT = RB / 4;         // entries per thread: 256 RB / 1024
   __shared__ double sGH[RB][RB + 1];
   __shared__ double sGW[RB][RB + 1];
+  __shared__ float sW[256][RB + 1];
   __shared__ double sGp[4][NT * NT][64][4];
-  __shared__ float sWc[256][RB + 1];
-  __shared__ double sRed[4];
+  __shared__ double sRed[16];
+  __shared__ int sLast;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int a = lane & 15, b = lane >> 4;
   const int m = f.m, r = f.r;
   const int64_t mr = (int64_t)m * r;
+  const int i0 = blockIdx.x * 256;
   auto entry = [&](int64_t e) -> double {
     if (FUSED) {
       double v = 0.0;
@@ -2660,206 +2666,135 @@ __global__ __launch_bounds__(256) void k_wupdate(FinArgs f) {
     }
     return f.red[e];
   };
-  float wrow[RB];
-  double nrow[RB];
-  auto load_row = [&](int i) {
-    const int64_t base = (int64_t)i * r;
+  // one round of loads: this thread's entries of W and N_W, and G_H
+  float wv[EPT];
+  double nv[EPT];
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int qc = min(q, r - 1);
-      const float wv = f.W[base + qc];
-      wrow[q] = zmask(wv, q < r);
-      nrow[q] = zmask(entry(base + qc), q < r);
-    }
-  };
-  load_row(min(tid, m - 1));  // rows past m are loaded but not used
-  for (int pidx = tid; pidx < RB * RB; pidx += 256) {
-    const int c = pidx / RB, q = pidx % RB;
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 1024 * u, row = e / RB, c = e % RB;
+    const int i = i0 + row;
+    const int64_t idx = (int64_t)min(i, m - 1) * r + min(c, r - 1);
+    const bool ok = i < m && c < r;
+    wv[u] = zmask(f.W[idx], ok);
+    nv[u] = zmask(entry(idx), ok);
+  }
+  if (tid < RB * RB) {
+    const int c = tid / RB, q = tid % RB;
     sGH[c][q] = zmask(entry(mr + min(c, r - 1) * r + min(q, r - 1)), c < r && q < r);
   }
-  const double nx2 = f.scal[SCAL_NX2];
-  double rsum = 0.0;
-  if (f.rpart && tid < 64) {
-    for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
-    rsum = wave_sum(rsum);
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 1024 * u;
+    sW[e / RB][e % RB] = wv[u];
   }
   __syncthreads();
-  v4d acc[NT][NT];
-#pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int q = 0; q < NT; ++q) acc[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
-  double dot_wn = 0.0;
-  for (int i0 = 0; i0 < m; i0 += 256) {
-    const int i = i0 + tid;
-    if (i < m) {
-      if (i0 > 0) load_row(i);
-      const int64_t base = (int64_t)i * r;
-      wupdate_row<RB>(wrow, nrow, sGH, r, f.eps, sWc[tid], &dot_wn);
-      float* wdst = f.Wout ? f.Wout : f.W;
-#pragma unroll
-      for (int c = 0; c < RB; ++c)
-        if (c < r) wdst[base + c] = sWc[tid][c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
-    }
-    __syncthreads();
-    // this wavefront's 64 rows of the chunk, four per MFMA step (rows past m are zero)
-    gram_rows_f64<RB, NT, 256>(sWc, acc, w, a, b);
-    __syncthreads();
+  float wn[EPT];
+  double dot = 0.0;
+  constexpr int kUnroll = RB == 32 ? 2 : EPT;  // RB = 32: bounded register use (1024 threads)
+#pragma unroll kUnroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 1024 * u, row = e / RB, c = e % RB;
+    const float v = wupdate_entry<RB>(sW[row], nv[u], sGH, c, f.eps);
+    wn[u] = (c < r && i0 + row < m) ? v : 0.f;
+    dot += (double)wn[u] * nv[u];
   }
-  // the four wavefronts' Grams, added in order
+  __syncthreads();  // every row has been read before it is replaced
+  float* wdst = f.Wout ? f.Wout : f.W;
 #pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sGp[w][h * NT + q][lane][i] = acc[h][q][i];
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 1024 * u, row = e / RB, c = e % RB;
+    sW[row][c] = wn[u];
+    if (c < r && i0 + row < m) wdst[(int64_t)(i0 + row) * r + c] = wn[u];
+  }
+  dot = wave_sum(dot);
+  if (lane == 0) sRed[w] = dot;
   __syncthreads();
-  for (int pidx = tid; pidx < NT * NT * 256; pidx += 256) {
-    const int tq = pidx >> 8, l = (pidx >> 2) & 63, i = pidx & 3;
-    const double s = ((sGp[0][tq][l][i] + sGp[1][tq][l][i]) + sGp[2][tq][l][i]) + sGp[3][tq][l][i];
-    // FP64 16 x 16 x 4 result layout: value i of lane (a, b) is row 4 i + b, column a
-    const int row = 16 * (tq / NT) + 4 * i + (l >> 4), col = 16 * (tq % NT) + (l & 15);
-    if (row < RB && col < RB) sGW[row][col] = s;
+  if (w < 4) {  // wavefront w's 64 rows of the block's Gram
+    v4d acc[NT][NT];
+#pragma unroll
+    for (int h = 0; h < NT; ++h)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    gram_rows_f64<RB, NT, 256>(sW, acc, w, a, b);
+#pragma unroll
+    for (int h = 0; h < NT; ++h)
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) sGp[w][h * NT + q][lane][ii] = acc[h][q][ii];
   }
   __syncthreads();
-  // next G_W, zero padded to the pass kernels' RP x RP layout
-  const int rp = r <= 16 ? 16 : 32;
-  for (int pidx = tid; pidx < rp * rp; pidx += 256) {
-    const int c = pidx / rp, q = pidx % rp;
-    f.GW[pidx] = (c < RB && q < RB && c < r && q < r) ? (float)sGW[c][q] : 0.f;
-  }
-  // monitor: <W'^T W', H H^T> over the first wavefront, then one thread
-  double gg = 0.0;
-  if (tid < 64)
-    for (int pidx = tid; pidx < r * r; pidx += 64) gg += sGW[pidx / r][pidx % r] * sGH[pidx / r][pidx % r];
-  gg = wave_sum(gg);
-  dot_wn = wave_sum(dot_wn);
-  if (lane == 0) sRed[w] = dot_wn;
-  __syncthreads();
-  if (tid == 0) {
-    const double wn = ((sRed[0] + sRed[1]) + sRed[2]) + sRed[3];
-    f.scal[SCAL_MONITOR] = 0.5 * (nx2 - 2.0 * wn + gg);
-    if (f.rpart) {
-      const double obj = 0.5 * rsum;
-      f.scal[SCAL_OBJ] = obj;
-      if (f.trace) f.trace[0] = obj;
-    }
-  }
-}
-
-// W-update for m > 256 rows, over blocks: block j updates rows [256 j, 256 j + 256) as
-// k_wupdate does (same row code), and writes its part of G_W' = W'^T W' (FP64 MFMA over
-// its rows by four wavefronts, added in order) and of <W', N_W> to gpart[j]
-// (RB RB + 1 doubles); k_wupdate_gram then adds the blocks' parts in block order and
-// writes G_W and the monitor.  Entries are read from `red`.
-template <int RB>
-__global__ __launch_bounds__(256) void k_wupdate_rows(FinArgs f, double* __restrict__ gpart) {
-  constexpr int NT = (RB + 15) / 16;
-  __shared__ double sGH[RB][RB + 1];
-  __shared__ double sGp[4][NT * NT][64][4];
-  __shared__ float sWc[256][RB + 1];
-  __shared__ double sRed[4];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int a = lane & 15, b = lane >> 4;
-  const int m = f.m, r = f.r;
-  const int64_t mr = (int64_t)m * r;
-  const int i = blockIdx.x * 256 + tid;
-  float wrow[RB];
-  double nrow[RB];
-  {
-    const int64_t base = (int64_t)min(i, m - 1) * r;
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int qc = min(q, r - 1);
-      wrow[q] = zmask(f.W[base + qc], q < r);
-      nrow[q] = zmask(f.red[base + qc], q < r);
-    }
-  }
-  for (int pidx = tid; pidx < RB * RB; pidx += 256) {
-    const int c = pidx / RB, q = pidx % RB;
-    sGH[c][q] = zmask(f.red[mr + min(c, r - 1) * r + min(q, r - 1)], c < r && q < r);
-  }
-  __syncthreads();
-  double dot_wn = 0.0;
-  if (i < m) {
-    wupdate_row<RB>(wrow, nrow, sGH, r, f.eps, sWc[tid], &dot_wn);
-    float* wdst = f.Wout ? f.Wout : f.W;
-#pragma unroll
-    for (int c = 0; c < RB; ++c)
-      if (c < r) wdst[(int64_t)i * r + c] = sWc[tid][c];
-  } else {
-#pragma unroll
-    for (int c = 0; c < RB; ++c) sWc[tid][c] = 0.f;
-  }
-  __syncthreads();
-  v4d acc[NT][NT];
-#pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int q = 0; q < NT; ++q) acc[h][q] = v4d{0.0, 0.0, 0.0, 0.0};
-  gram_rows_f64<RB, NT, 256>(sWc, acc, w, a, b);
-#pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) sGp[w][h * NT + q][lane][ii] = acc[h][q][ii];
-  dot_wn = wave_sum(dot_wn);
-  if (lane == 0) sRed[w] = dot_wn;
-  __syncthreads();
-  double* dst = gpart + (int64_t)blockIdx.x * (RB * RB + 1);
-  for (int pidx = tid; pidx < NT * NT * 256; pidx += 256) {
-    const int tq = pidx >> 8, l = (pidx >> 2) & 63, ii = pidx & 3;
+  if (tid < NT * NT * 256) {
+    const int tq = tid >> 8, l = (tid >> 2) & 63, ii = tid & 3;
     const double sg = ((sGp[0][tq][l][ii] + sGp[1][tq][l][ii]) + sGp[2][tq][l][ii]) + sGp[3][tq][l][ii];
     // FP64 16 x 16 x 4 result layout: value ii of lane (a, b) is row 4 ii + b, column a
     const int row = 16 * (tq / NT) + 4 * ii + (l >> 4), col = 16 * (tq % NT) + (l & 15);
-    if (row < RB && col < RB) dst[row * RB + col] = sg;
+    if (row < RB && col < RB) sGW[row][col] = sg;
   }
-  if (tid == 0) dst[RB * RB] = ((sRed[0] + sRed[1]) + sRed[2]) + sRed[3];
-}
-
-template <int RB>
-__global__ __launch_bounds__(256) void k_wupdate_gram(FinArgs f, const double* __restrict__ gpart, int nb) {
-  __shared__ double sGW[RB * RB];
-  __shared__ double sDot;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int r = f.r;
-  const int64_t mr = (int64_t)f.m * r;
-  for (int pidx = tid; pidx < RB * RB + 1; pidx += 256) {
-    double sg = 0.0;
-    for (int j = 0; j < nb; ++j) sg += gpart[(int64_t)j * (RB * RB + 1) + pidx];
-    if (pidx < RB * RB) sGW[pidx] = sg;
-    else sDot = sg;
-  }
-  double rsum = 0.0;
-  if (f.rpart && tid < 64) {
-    for (int g = tid; g < f.G; g += 64) rsum += f.rpart[g];
-    rsum = wave_sum(rsum);
+  double dot_wn = 0.0;  // thread 0: <W', N_W> of the block, wavefronts in order
+  if (tid == 0) {
+    dot_wn = sRed[0];
+#pragma unroll
+    for (int ww = 1; ww < 16; ++ww) dot_wn += sRed[ww];
   }
   __syncthreads();
-  const int rp = r <= 16 ? 16 : 32;
-  for (int pidx = tid; pidx < rp * rp; pidx += 256) {
-    const int c = pidx / rp, q = pidx % rp;
-    f.GW[pidx] = (c < RB && q < RB && c < r && q < r) ? (float)sGW[c * RB + q] : 0.f;
+  if (gridDim.x > 1) {
+    constexpr int PS = 32 * 32 + 1;  // gpart stride per block: G_W' part, then <W', N_W>
+    const int nb = gridDim.x;
+    double* dst = f.gpart + (int64_t)blockIdx.x * PS;
+    if (tid < RB * RB) st_dev(dst + tid, sGW[tid / RB][tid % RB]);
+    if (tid == 0) st_dev(dst + RB * RB, dot_wn);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+    __syncthreads();
+    if (tid == 0)
+      sLast = __hip_atomic_fetch_add(f.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+              (unsigned)(nb - 1);
+    __syncthreads();
+    if (!sLast) return;
+    // the last block: entry e of every part added in block order (from 0.0), eight loads
+    // in flight; entry RB RB is <W', N_W>
+    for (int e = tid; e <= RB * RB; e += 1024) {
+      double acc = 0.0;
+      for (int j0 = 0; j0 < nb; j0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = ld_dev(f.gpart + (int64_t)min(j0 + u, nb - 1) * PS + e);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += zmask(x[u], j0 + u < nb);
+      }
+      if (e < RB * RB) sGW[e / RB][e % RB] = acc;
+      else sRed[0] = acc;
+    }
+    if (tid == 0) __hip_atomic_store(f.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (tid == 0) dot_wn = sRed[0];
   }
-  // monitor: <W'^T W', H H^T> over the first wavefront
-  double gg = 0.0;
-  if (tid < 64)
-    for (int pidx = tid; pidx < r * r; pidx += 64)
-      gg += sGW[(pidx / r) * RB + (pidx % r)] * f.red[mr + pidx];
-  gg = wave_sum(gg);
+  // next G_W, zero padded to the pass kernels' RP x RP layout
+  const int rp = r <= 16 ? 16 : 32;
+  if (tid < rp * rp) {
+    const int c = tid / rp, q = tid % rp;
+    f.GW[tid] = (c < RB && q < RB && c < r && q < r) ? (float)sGW[c < RB ? c : 0][q < RB ? q : 0] : 0.f;
+  }
+  // monitor: <W'^T W', H H^T> over the first wavefront, residual partials over the second
+  double gg = 0.0, rsum = 0.0;
+  if (w == 0) {
+    for (int pidx = lane; pidx < r * r; pidx += 64) gg += sGW[pidx / r][pidx % r] * sGH[pidx / r][pidx % r];
+    gg = wave_sum(gg);
+    if (lane == 0) sRed[1] = gg;
+  } else if (w == 1 && f.rpart) {
+    for (int g = lane; g < f.G; g += 64) rsum += f.rpart[g];
+    rsum = wave_sum(rsum);
+    if (lane == 0) sRed[2] = rsum;
+  }
+  __syncthreads();
   if (tid == 0) {
-    f.scal[SCAL_MONITOR] = 0.5 * (f.scal[SCAL_NX2] - 2.0 * sDot + gg);
+    f.scal[SCAL_MONITOR] = 0.5 * (f.scal[SCAL_NX2] - 2.0 * dot_wn + sRed[1]);
     if (f.rpart) {
-      const double obj = 0.5 * rsum;
+      const double obj = 0.5 * sRed[2];
       f.scal[SCAL_OBJ] = obj;
       if (f.trace) f.trace[0] = obj;
     }
   }
-  (void)lane;
 }
 
 __global__ void k_zero_ints(int* __restrict__ p, int64_t n) {
@@ -3455,36 +3390,21 @@ hipError_t launch_xht_partials(const PassArgs& a, int rp, int gxht, int64_t chun
 
 template <int RB>
 static hipError_t launch_wupdate(const FinArgs& f, bool fused, hipStream_t s) {
-  if (fused) k_wupdate<RB, true><<<1, 256, 0, s>>>(f);
-  else k_wupdate<RB, false><<<1, 256, 0, s>>>(f);
-  NTT_CHECK_LAUNCH();
-  return hipSuccess;
-}
-
-template <int RB>
-static hipError_t launch_wupdate_blocks(const FinArgs& f, hipStream_t s) {
   const int nb = (f.m + 255) / 256;
-  k_wupdate_rows<RB><<<nb, 256, 0, s>>>(f, f.gpart);
-  NTT_CHECK_LAUNCH();
-  k_wupdate_gram<RB><<<1, 256, 0, s>>>(f, f.gpart, nb);
+  if (f.m < 1 || (nb > 1 && (!f.gpart || !f.arrive))) return hipErrorInvalidValue;
+  if (fused) k_wupdate_t<RB, true><<<nb, 1024, 0, s>>>(f);
+  else k_wupdate_t<RB, false><<<nb, 1024, 0, s>>>(f);
   NTT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
 hipError_t launch_finalize(const FinArgs& f, int rp, hipStream_t s) {
   (void)rp;
-  const bool blocks = f.m > 256;  // rows over blocks (the one-block update loops otherwise)
-  const bool fused = f.G <= 4 && !blocks;
+  const bool fused = f.G <= 4;  // the W-update sums the partials itself
   if (!fused) {
     if (f.G > kMaxReduceG) return hipErrorInvalidValue;
     const hipError_t e = launch_reduce(f, s);
     if (e != hipSuccess) return e;
-  }
-  if (blocks) {
-    if (!f.gpart) return hipErrorInvalidValue;
-    if (f.r <= 8) return launch_wupdate_blocks<8>(f, s);
-    if (f.r <= 16) return launch_wupdate_blocks<16>(f, s);
-    return launch_wupdate_blocks<32>(f, s);
   }
   if (f.r <= 8) return launch_wupdate<8>(f, fused, s);
   if (f.r <= 16) return launch_wupdate<16>(f, fused, s);
