@@ -1610,21 +1610,19 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LW(PassArgs p) {
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t bf16_bits_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-// hi and lo BF16 parts of eight FP32 values, packed two per 32-bit word
+// hi and lo BF16 parts of eight FP32 values, packed two per 32-bit word, by the
+// conversion instruction (round to nearest even)
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void split_bf8(const float (&f)[8], bf8& hi, bf8& lo) {
   u4v h, l;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t h0 = bf16_bits_rne(f[2 * j]), h1 = bf16_bits_rne(f[2 * j + 1]);
-    const uint32_t l0 = bf16_bits_rne(f[2 * j] - __uint_as_float(h0 << 16));
-    const uint32_t l1 = bf16_bits_rne(f[2 * j + 1] - __uint_as_float(h1 << 16));
-    h[j] = h0 | (h1 << 16);
-    l[j] = l0 | (l1 << 16);
+    const bf2 hv = {(__bf16)f[2 * j], (__bf16)f[2 * j + 1]};
+    const uint32_t hb = __builtin_bit_cast(uint32_t, hv);
+    const bf2 lv = {(__bf16)(f[2 * j] - __uint_as_float(hb << 16)),
+                    (__bf16)(f[2 * j + 1] - __uint_as_float(hb & 0xffff0000u))};
+    h[j] = hb;
+    l[j] = __builtin_bit_cast(uint32_t, lv);
   }
   hi = __builtin_bit_cast(bf8, h);
   lo = __builtin_bit_cast(bf8, l);
@@ -1632,10 +1630,12 @@ __device__ __forceinline__ void split_bf8(const float (&f)[8], bf8& hi, bf8& lo)
 __device__ __forceinline__ v4f mfma32bf(const bf8& a, const bf8& b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
-// BF16 value q (0..7) of a raw 8 x BF16 load
-__device__ __forceinline__ uint32_t bf_at(const uint4& v, int q) {
-  const uint32_t w = (q < 2) ? v.x : (q < 4) ? v.y : (q < 6) ? v.z : v.w;
-  return (q & 1) ? (w >> 16) : (w & 0xffffu);
+// BF16 values q (0..7) of two raw 8 x BF16 loads, packed as lo | hi << 16 (one byte
+// permute: selector bytes 0-3 pick bytes of the second source, 4-7 of the first)
+__device__ __forceinline__ uint32_t bf_pair(const uint4& lo, const uint4& hi, int q) {
+  const uint32_t wl = (q < 2) ? lo.x : (q < 4) ? lo.y : (q < 6) ? lo.z : lo.w;
+  const uint32_t wh = (q < 2) ? hi.x : (q < 4) ? hi.y : (q < 6) ? hi.z : hi.w;
+  return __builtin_amdgcn_perm(wh, wl, (q & 1) ? 0x07060302u : 0x05040100u);
 }
 
 template <int MBW, int NW>
@@ -1745,7 +1745,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LWB(PassArgs p) {
         u4v xb;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          xb[j] = bf_at(x[8 * gq + 2 * j], q) | (bf_at(x[8 * gq + 2 * j + 1], q) << 16);
+          xb[j] = bf_pair(x[8 * gq + 2 * j], x[8 * gq + 2 * j + 1], q);
         const bf8 xv = __builtin_bit_cast(bf8, xb);
         nh = mfma32bf(wa_hi[gq], xv, nh);
         nh = mfma32bf(wa_lo[gq], xv, nh);
