@@ -136,7 +136,7 @@ def precision_mode(ntt, S, torch, cpu_seconds=0.0):
     out = {"workload": f"{w.name}: {w.note}"}
     progress("precision mode: 128^4 tensor generated")
     m, k, r = w.dims[0], int(np.prod(w.dims[1:])), w.target_ranks[1]
-    kernels = {"fp32": "k_mu_pass_LW<2, 4, false>", "bf16": "k_mu_pass_LWB<2, 4>"}
+    kernels = {"fp32": "k_mu_pass_LW<2, 4, false, true>", "bf16": "k_mu_pass_LWB<2, 4, true>"}
     for name, prec in (("fp32", ntt.NTT_PREC_FP32), ("bf16", ntt.NTT_PREC_BF16_MIXED)):
         plan = ntt.Plan(w.dims, w.target_ranks, w.iters, eps=w.eps, seed=w.seed, precision=prec,
                         fp32_tail_iters=w.fp32_tail)
