@@ -801,6 +801,218 @@ __global__ __launch_bounds__(256, 1) void k_mu_pass_r8(PassArgs p) {
   for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * 8 + (e % r)];
 }
 
+// ------------------------------------------------------------------ r <= 8 pass on 4 x 4 MFMA blocks
+// The wide r <= 8 update pass (FP32 X) on the 16-block form of the matrix cores,
+// v_mfma_f32_4x4x1_16b_f32: block b = lane / 4 multiplies a 4 x 1 A (lanes 4b .. 4b + 3, or,
+// with the broadcast controls cbsz = 4 / abid = a, the lanes 4a .. 4a + 3 for every block)
+// by a 1 x 4 B (lanes 4b .. 4b + 3), and lane 4b + j holds column j of the block's 4 x 4
+// sum in its four registers (checked on the GPU against host products).  These blocks do
+// not pad rank 8 to 16, so the MFMA work per column is less than half that of the 16 x 16
+// tiles.  Per 64-column step of a wave, with one column per lane (lane L <-> column j0 + L):
+//   - each lane loads X[R][j0 + L] (rows R < MPAD) and H[c][j0 + L] (c < 8): every load
+//     instruction reads 256 contiguous bytes of one row;
+//   - W^T X (K = rows): for each row R and rank quad g one MFMA, B = the lanes' X[R], A =
+//     W[R][4g .. 4g + 3] broadcast from slot 2R + g of the W registers (lane 4s + i of
+//     register v holds W[R][4g + i] for slot 16v + s = 2R + g); lane L then holds ranks
+//     4g .. 4g + 3 of its own column, which is what the epilogue needs;
+//   - D_H = G_W H and the epilogue of the lane's column (VALU, as in k_mu_pass_r8w), H_new
+//     stored;
+//   - X and H_new go to per-wave LDS tiles ([row][column]) for X H_new^T and
+//     H_new H_new^T (K = columns): block b = 4u + s takes the columns 16s .. 16s + 15 of
+//     the step, one per MFMA; for X H_new^T, u = (rank quad kq, row half rh) of each 8-row
+//     group; for H_new H_new^T, u = (rank quads cg, qg).  The four column slots s of a
+//     block are added at the end of the pass.
+// Partials as in k_mu_pass_r8w (X H_new^T as m x r, then H_new H_new^T as r x r, the waves
+// added in the order 3, 2, 1, 0).
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+// the same with A taken from block `abid` for every block (abid folds to a constant when
+// the caller's loops are unrolled)
+__device__ __forceinline__ v4f mfma4_bc(float a, float b, v4f c, int abid) {
+  switch (abid) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 0, 0);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 1, 0);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 2, 0);
+    case 3: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 3, 0);
+    case 4: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 4, 0);
+    case 5: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 5, 0);
+    case 6: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 6, 0);
+    case 7: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 7, 0);
+    case 8: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 8, 0);
+    case 9: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 9, 0);
+    case 10: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 10, 0);
+    case 11: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 11, 0);
+    case 12: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 12, 0);
+    case 13: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 13, 0);
+    case 14: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 14, 0);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 15, 0);
+  }
+}
+
+template <int MPAD>
+__global__ __launch_bounds__(256) void k_mu_pass_r8m(PassArgs p) {
+  constexpr int NP = MPAD / 8;  // 8-row groups
+  constexpr int NV = MPAD / 8;  // W registers: 2 MPAD slots of four lanes, 16 per register
+  constexpr int SX = 68;        // row stride of the per-wave tiles (floats)
+  __shared__ __attribute__((aligned(16))) float sWt[16][MPAD + 4];
+  __shared__ __attribute__((aligned(16))) float sG[8][8];
+  __shared__ __attribute__((aligned(16))) float sX[4][MPAD * SX];
+  __shared__ __attribute__((aligned(16))) float sHn[4][8 * SX];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = p.m, r = p.r;
+  const int64_t k = p.k;
+  const int64_t nsteps = (k + 63) >> 6;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+
+  r8_w_setup<MPAD>(p, sWt, sG, tid, tid >> 6, lane & 15, lane >> 4);
+  __syncthreads();
+  float wab[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int slot = 16 * v + (lane >> 2);
+    wab[v] = sWt[4 * (slot & 1) + (lane & 3)][slot >> 1];  // W[R][4g + i], zero past m and r
+  }
+  // roles in the K = columns products: block blk = 4u + s, lane index i4 within the block
+  const int blk = lane >> 2, i4 = lane & 3, cs = blk & 3, u = blk >> 2;
+  const int kq = u & 1, rh = u >> 1;  // X H^T: rank quad, row half; H H^T: qg = kq, cg = rh
+
+  v4f accX[NP];
+  v4f accG = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) accX[pp] = v4f{0.f, 0.f, 0.f, 0.f};
+  float* sXw = sX[w];
+  float* sHw = sHn[w];
+
+  // X and H through buffer loads: a row's byte offset (below 2^32, checked at launch) in
+  // the scalar offset, the lane's column in the vector offset, so no per-load address
+  // arithmetic.  Rows past m and columns past k read clamped (valid) addresses: W is zero
+  // there and G_W past r, so they add exact zeros, and H_new is masked to zero past k.
+  const __amdgpu_buffer_rsrc_t rsX =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p.X), (short)0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsH = __builtin_amdgcn_make_buffer_rsrc(p.H, (short)0, -1, 0x00020000);
+  const uint32_t k4 = (uint32_t)k * 4u;
+
+  for (int64_t st = (int64_t)blockIdx.x * 4 + w; st < nsteps; st += wstride) {
+    const int64_t j0 = st << 6;
+    const bool colok = j0 + lane < k;
+    const int lc4 = 4 * (colok ? lane : (int)(k - 1 - j0));  // clamped column (ragged last step)
+    const uint32_t j04 = (uint32_t)j0 * 4u;
+    float x[MPAD], hv[8];
+#pragma unroll
+    for (int R = 0; R < MPAD; ++R)
+      x[R] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsX, lc4, (int)((uint32_t)min(R, m - 1) * k4 + j04), 0));
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      hv[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsH, lc4, (int)((uint32_t)min(c, r - 1) * k4 + j04), 0));
+
+    // W^T X: ranks 4g .. 4g + 3 of the lane's column, the even and the odd rows in separate
+    // sums (four independent MFMA chains), added at the end
+    v4f n2[2][2] = {{v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}},
+                    {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}}};
+#pragma unroll
+    for (int R = 0; R < MPAD; ++R)
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        n2[R & 1][g] = mfma4_bc(wab[(2 * R + g) >> 4], x[R], n2[R & 1][g], (2 * R + g) & 15);
+    const v4f n[2] = {n2[0][0] + n2[1][0], n2[0][1] + n2[1][1]};
+
+    // D_H = G_W H and the epilogue of the lane's column (ranks 0..7)
+    float hnew[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float4 g0 = *reinterpret_cast<const float4*>(&sG[c][0]);
+      const float4 g1 = *reinterpret_cast<const float4*>(&sG[c][4]);
+      float dh = g0.x * hv[0];
+      dh = fmaf(g0.y, hv[1], dh);
+      dh = fmaf(g0.z, hv[2], dh);
+      dh = fmaf(g0.w, hv[3], dh);
+      dh = fmaf(g1.x, hv[4], dh);
+      dh = fmaf(g1.y, hv[5], dh);
+      dh = fmaf(g1.z, hv[6], dh);
+      dh = fmaf(g1.w, hv[7], dh);
+      const float q = fmaxf(0.f, fast_div(hv[c] * n[c >> 2][c & 3], dh + p.eps));
+      hnew[c] = (c < r && colok) ? q : 0.f;
+    }
+    if (colok) {
+      float* hd = p.H + j0 + lane;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < r) __builtin_nontemporal_store(hnew[c], hd + (int64_t)c * k);
+    }
+    // X and H_new to the wave's tiles, then X H_new^T and H_new H_new^T (K = columns)
+    wave_sync();
+#pragma unroll
+    for (int R = 0; R < MPAD; ++R) sXw[R * SX + lane] = x[R];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sHw[c * SX + lane] = hnew[c];
+    wave_sync();
+#pragma unroll
+    for (int mq = 0; mq < 4; ++mq) {
+      const int c0 = 16 * cs + 4 * mq;
+      const float4 hb4 = *reinterpret_cast<const float4*>(&sHw[(4 * kq + i4) * SX + c0]);
+      const float4 ha4 = *reinterpret_cast<const float4*>(&sHw[(4 * rh + i4) * SX + c0]);
+      float4 xa4[NP];
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp)
+        xa4[pp] = *reinterpret_cast<const float4*>(&sXw[(8 * pp + 4 * rh + i4) * SX + c0]);
+      const float hb[4] = {hb4.x, hb4.y, hb4.z, hb4.w};
+      const float ha[4] = {ha4.x, ha4.y, ha4.z, ha4.w};
+      // column by column, the NP + 1 accumulators interleaved (independent chains)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        accG = mfma4(ha[q], hb[q], accG);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+          const float xq = q == 0 ? xa4[pp].x : q == 1 ? xa4[pp].y : q == 2 ? xa4[pp].z : xa4[pp].w;
+          accX[pp] = mfma4(xq, hb[q], accX[pp]);
+        }
+      }
+    }
+  }
+
+  // the four column slots of every block added (lanes 16u + 4s + j, s = 0..3): lane s = 0
+  // then holds X H^T[8pp + 4rh + i][4kq + j] and H H^T[4rh + i][4kq + j] in register i
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int pp = 0; pp < NP; ++pp) {
+      float v = accX[pp][q];
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      accX[pp][q] = v;
+    }
+    float v = accG[q];
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    accG[q] = v;
+  }
+  // per-workgroup partials, waves added in the order 3, 2, 1, 0
+  float* dst = p.part + (int64_t)blockIdx.x * p.part_stride;
+  float* buf = &sX[0][0];    // MPAD x 8 floats
+  float* gbuf = &sHn[0][0];  // 8 x 8 floats
+  __syncthreads();
+  for (int turn = 3; turn >= 0; --turn) {
+    if (w == turn && cs == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+          const int idx = (8 * pp + 4 * rh + q) * 8 + 4 * kq + i4;
+          buf[idx] = (turn == 3) ? accX[pp][q] : buf[idx] + accX[pp][q];
+        }
+        const int gi = (4 * rh + q) * 8 + 4 * kq + i4;
+        gbuf[gi] = (turn == 3) ? accG[q] : gbuf[gi] + accG[q];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * r; e += 256) dst[e] = buf[(e / r) * 8 + (e % r)];
+  for (int e = tid; e < r * r; e += 256) dst[m * r + e] = gbuf[(e / r) * 8 + (e % r)];
+}
+
 // ------------------------------------------------------------------ pass for at most 4 rows
 // Update pass for unfoldings of m <= MP <= 4 rows (so r <= 4 too), where a 16-row MFMA
 // tile would be mostly padding: one column per lane on the VALU.  Per column j:
@@ -3225,12 +3437,17 @@ hipError_t launch_pass_fused(const PassArgs& a, int rp, int mb, int grid, bool u
   if (rp == 16 && a.r <= 8 && mb <= 2 && update && !resid) {
     const bool xb = a.Xb != nullptr;
     if (wide) {
+      // FP32 X: the 4 x 4-block pass; the BF16 copy: the 16 x 16-tile pass
+      // (the 4 x 4-block pass addresses X and H by 32-bit byte offsets)
+      const bool small = 4.0 * (double)std::max(a.m, 8) * (double)a.k < 4294967296.0;
       if (mb == 1) {
-        if (xb) k_mu_pass_r8w<4, true><<<grid, 256, 0, s>>>(a);
-        else k_mu_pass_r8w<4, false><<<grid, 256, 0, s>>>(a);
+        if (xb || !small) { if (xb) k_mu_pass_r8w<4, true><<<grid, 256, 0, s>>>(a);
+                            else k_mu_pass_r8w<4, false><<<grid, 256, 0, s>>>(a); }
+        else k_mu_pass_r8m<16><<<grid, 256, 0, s>>>(a);
       } else {
-        if (xb) k_mu_pass_r8w<8, true><<<grid, 256, 0, s>>>(a);
-        else k_mu_pass_r8w<8, false><<<grid, 256, 0, s>>>(a);
+        if (xb || !small) { if (xb) k_mu_pass_r8w<8, true><<<grid, 256, 0, s>>>(a);
+                            else k_mu_pass_r8w<8, false><<<grid, 256, 0, s>>>(a); }
+        else k_mu_pass_r8m<32><<<grid, 256, 0, s>>>(a);
       }
       NTT_CHECK_LAUNCH();
       return hipSuccess;
