@@ -865,7 +865,6 @@ __global__ __launch_bounds__(256) void k_mu_pass_r8m(PassArgs p) {
   const int m = p.m, r = p.r;
   const int64_t k = p.k;
   const int64_t nsteps = (k + 63) >> 6;
-  const int64_t wstride = (int64_t)gridDim.x * 4;
 
   r8_w_setup<MPAD>(p, sWt, sG, tid, tid >> 6, lane & 15, lane >> 4);
   __syncthreads();
@@ -895,7 +894,12 @@ __global__ __launch_bounds__(256) void k_mu_pass_r8m(PassArgs p) {
   const __amdgpu_buffer_rsrc_t rsH = __builtin_amdgcn_make_buffer_rsrc(p.H, (short)0, -1, 0x00020000);
   const uint32_t k4 = (uint32_t)k * 4u;
 
-  for (int64_t st = (int64_t)blockIdx.x * 4 + w; st < nsteps; st += wstride) {
+  // every wave takes a contiguous run of steps: at any moment the waves of the GPU then
+  // read few, long runs of each row of X (DRAM page locality), rather than 256-byte pieces
+  // spread over whole rows
+  const int64_t spw = (nsteps + 4 * (int64_t)gridDim.x - 1) / (4 * (int64_t)gridDim.x);
+  const int64_t sw0 = ((int64_t)blockIdx.x * 4 + w) * spw, sw1 = min(nsteps, sw0 + spw);
+  for (int64_t st = sw0; st < sw1; ++st) {
     const int64_t j0 = st << 6;
     const bool colok = j0 + lane < k;
     const int lc4 = 4 * (colok ? lane : (int)(k - 1 - j0));  // clamped column (ragged last step)
@@ -1200,7 +1204,10 @@ void k_mu_pass_r8w(PassArgs p) {
   float* sHw = sHn[w];
   float* sTw = sT[w];
 
-  for (; st < nsteps; st += wstride) {
+  // every wave takes a contiguous run of steps (DRAM page locality)
+  const int64_t spw = (nsteps + wstride - 1) / wstride;
+  const int64_t sw0 = ((int64_t)blockIdx.x * 4 + w) * spw, sw1 = min(nsteps, sw0 + spw);
+  for (st = sw0; st < sw1; ++st) {
     const int64_t j0 = st << 6;
     float4 x[NQ], h[2];
     load_step(st, x, h);
@@ -1697,6 +1704,8 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LW(PassArgs p) {
 #pragma unroll
   for (int blk = 0; blk < MBW; ++blk) accW[blk] = v4f{0.f, 0.f, 0.f, 0.f};
 
+  // (steps taken cyclically: measured slightly faster here than contiguous runs per
+  // workgroup, unlike the 32-row pass, whose waves read only 32 rows per step)
   for (int64_t st = blockIdx.x; st < nsteps; st += nblk) {
     const int64_t j0 = st << 6;
     const bool full = vec_ok && (j0 + 64 <= k);
