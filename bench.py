@@ -586,8 +586,8 @@ def main():
         "stage_ms": rep_graph["ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_mu_pass_r8w<8, false>", w.name),
-                     "kernel": f"k_mu_pass stage 1 ({m1}x{k1}, r={r1})",
+                     "traffic": profiled_traffic("k_mu_pass_r8m<32>", w.name),
+                     "kernel": f"k_mu_pass_r8m<32> stage 1 ({m1}x{k1}, r={r1})",
                      "pass_ms": pass_ms, "bytes_per_launch": bytes_per_launch},
     }
     extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]

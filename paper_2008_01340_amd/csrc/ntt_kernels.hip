@@ -2251,7 +2251,11 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
   // 128-byte line of X (and H) are then read by the same workgroup, so the line is
   // fetched once; small stages keep one group per workgroup for parallelism
   const bool pairs = p.pair_groups != 0;
+  // on the BF16 copy each workgroup takes a contiguous run of groups instead (measured on
+  // the 2048 x 16,384 stage: 19.4 -> 18.0 ms in BF16, but 16.6 -> 18.4 ms in FP32)
+  const int64_t gpb = (ngroups + gridDim.x - 1) / gridDim.x;
   auto group_of = [&](int64_t it) -> int64_t {
+    if (XBF) return it < gpb ? (int64_t)blockIdx.x * gpb + it : ngroups;
     return pairs ? 2 * ((int64_t)blockIdx.x + (it >> 1) * (int64_t)gridDim.x) + (it & 1)
                  : (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
   };
