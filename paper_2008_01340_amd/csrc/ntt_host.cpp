@@ -156,8 +156,9 @@ void classify_stage(Stage& s, int precision) {
     s.pairs = nb == 0 && ngroups >= 512;
     const int64_t units = nb > 0 ? (ngroups + nb - 1) / nb : (s.pairs ? (ngroups + 1) / 2 : ngroups);
     // one resident round of workgroups; partials up to ~25% of the X bytes
+    // (65..128 rows: two workgroups per CU, its wide pass prefetching the next step)
     const int64_t gcap_l = std::max<int64_t>(
-        256, std::min<int64_t>(s.cls <= 2 ? kMaxLBlocks : 512,
+        256, std::min<int64_t>((s.cls <= 2 && s.cls != 1) ? kMaxLBlocks : 512,
                                (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, gcap_l));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {

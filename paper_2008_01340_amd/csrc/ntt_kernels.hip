@@ -1706,12 +1706,30 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LW(PassArgs p) {
 
   // (steps taken cyclically: measured slightly faster here than contiguous runs per
   // workgroup, unlike the 32-row pass, whose waves read only 32 rows per step)
+  // 65..128 rows (MBW = 2): the next step's loads are issued before the current step is
+  // processed (two waves per SIMD then; one resident round of 512 workgroups).  Measured
+  // on the 128 x 2,097,152 stage: 60.7 -> 58.8 ms for 200 iterations; the 256-row class
+  // was slower with it (the 256^4 stage 1 446 -> 510 ms) and keeps single-step loads.
+  constexpr bool PF = MBW == 2;
+  float4 xn[PF ? NQ : 1];
+  float hn[PF ? 4 : 1];
+  if constexpr (PF) {
+    if (blockIdx.x < nsteps) load_step(blockIdx.x, xn, hn);
+  }
   for (int64_t st = blockIdx.x; st < nsteps; st += nblk) {
     const int64_t j0 = st << 6;
     const bool full = vec_ok && (j0 + 64 <= k);
     float4 x[NQ];
     float hv[4];
-    load_step(st, x, hv);
+    if constexpr (PF) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) x[q] = xn[q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hv[q] = hn[q];
+      if (st + nblk < nsteps) load_step(st + nblk, xn, hn);
+    } else {
+      load_step(st, x, hv);
+    }
 
     // A: parts of W^T X of the four column sets, stored as [a][rank 4b + i]
     {
