@@ -2141,7 +2141,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_LWB(PassArgs p) {
 //            (chunk 0 also its H H^T part), so the gridDim.x partials are complete, as
 //            after the fused passes;
 //   phase 0: the residual of the wave's rows, to rpart[y gridDim.x + x].
-template <int RP, int MBW, int NW, int PH, bool XBF>
+template <int RP, int MBW, int NW, int PH, bool XBF, int PD = 1>
 __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
   constexpr int NH = RP / 16;
   constexpr int SX = 20;
@@ -2264,7 +2264,6 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
       }
   };
 
-  float xn[MBW][4], hn_[NH][4], sn[NH][4];
   // with pair_groups, groups in pairs (2p, 2p + 1), one after the other: both halves of a
   // 128-byte line of X (and H) are then read by the same workgroup, so the line is
   // fetched once; small stages keep one group per workgroup for parallelism
@@ -2277,10 +2276,10 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
     return pairs ? 2 * ((int64_t)blockIdx.x + (it >> 1) * (int64_t)gridDim.x) + (it & 1)
                  : (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
   };
-  int64_t it = 0;
-  if (group_of(0) < ngroups) load_group(group_of(0), xn, hn_, sn);
-  int par = 0;
-  for (int64_t g = group_of(0); g < ngroups; g = group_of(++it), par ^= 1) {
+  // PD groups in flight: with PD = 2 the loop is unrolled by two over buffers A and B, so
+  // taking a group out of its buffer waits only for that group's loads
+  static_assert(PD == 1 || PD == 2, "one or two groups in flight");
+  auto step = [&](int64_t g, int64_t it, int par, float (&xn)[MBW][4], float (&hn_)[NH][4], float (&sn)[NH][4]) {
     const int64_t j0 = g << 4;
     const bool full = vec_ok && (j0 + 16 <= k);
     float xr[MBW][4], hv[NH][4], sv[NH][4];
@@ -2296,7 +2295,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[h][q] = sn[h][q];
-    if (group_of(it + 1) < ngroups) load_group(group_of(it + 1), xn, hn_, sn);
+    if (group_of(it + PD) < ngroups) load_group(group_of(it + PD), xn, hn_, sn);
     mask_group(j0, full, xr, hv, sv);
 
     if (PH != 2) {
@@ -2359,7 +2358,7 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
             }
         }
       }
-      continue;
+      return;
     }
 
     // phase 2: N_H, D_H = G_W H, the epilogue (identical in every wave)
@@ -2422,6 +2421,21 @@ __global__ __launch_bounds__(64 * NW) void k_mu_pass_C(PassArgs p) {
         accW[blk][h] = mfma16(xr[blk][2], hn4[h].z, accW[blk][h]);
         accW[blk][h] = mfma16(xr[blk][3], hn4[h].w, accW[blk][h]);
       }
+  };
+  float xA[MBW][4], hA[NH][4], sA[NH][4];
+  if (group_of(0) < ngroups) load_group(group_of(0), xA, hA, sA);
+  if constexpr (PD == 2) {
+    float xB[MBW][4], hB[NH][4], sB[NH][4];
+    if (group_of(1) < ngroups) load_group(group_of(1), xB, hB, sB);
+    for (int64_t it = 0;; it += 2) {
+      if (group_of(it) >= ngroups) break;
+      step(group_of(it), it, 0, xA, hA, sA);
+      if (group_of(it + 1) >= ngroups) break;
+      step(group_of(it + 1), it + 1, 1, xB, hB, sB);
+    }
+  } else {
+    int par = 0;
+    for (int64_t it = 0, g = group_of(0); g < ngroups; g = group_of(++it), par ^= 1) step(g, it, par, xA, hA, sA);
   }
 
   if (PH == 2) {
@@ -3578,6 +3592,8 @@ hipError_t launch_pass_L(const PassArgs& a, int rp, int cls, int grid, bool upda
                   : pass_L_rp<32>(a, cls, grid, update, resid, s);
 }
 
+constexpr int kNumCUs = 256;  // MI355X: 8 XCDs of 32 CUs
+
 template <int RP>
 static hipError_t pass_C_rp(const PassArgs& a, int G, bool update, bool resid, hipStream_t s) {
   dim3 grid((unsigned)G, (unsigned)a.nchunks);
@@ -3587,13 +3603,27 @@ static hipError_t pass_C_rp(const PassArgs& a, int G, bool update, bool resid, h
   }
   if (update) {
     const int64_t n_el = (int64_t)a.r * a.k;
-    if (a.Xb != nullptr) k_mu_pass_C<RP, 4, 8, 1, true><<<grid, 512, 0, s>>>(a);
-    else k_mu_pass_C<RP, 4, 8, 1, false><<<grid, 512, 0, s>>>(a);
+    // at most one workgroup per CU (8 waves): two groups in flight per wave, which the
+    // registers allow at rank 16 (at three waves per SIMD, too many for two workgroups)
+    constexpr int PD = RP == 16 ? 2 : 1;
+    const bool deep = PD == 2 && (int64_t)G * a.nchunks <= kNumCUs;
+    if (a.Xb != nullptr) {
+      if (deep) k_mu_pass_C<RP, 4, 8, 1, true, PD><<<grid, 512, 0, s>>>(a);
+      else k_mu_pass_C<RP, 4, 8, 1, true><<<grid, 512, 0, s>>>(a);
+    } else {
+      if (deep) k_mu_pass_C<RP, 4, 8, 1, false, PD><<<grid, 512, 0, s>>>(a);
+      else k_mu_pass_C<RP, 4, 8, 1, false><<<grid, 512, 0, s>>>(a);
+    }
     NTT_CHECK_LAUNCH();
     k_sum_chunks<<<(unsigned)((n_el + 255) / 256), 256, 0, s>>>(a.S, n_el, a.nchunks);
     NTT_CHECK_LAUNCH();
-    if (a.Xb != nullptr) k_mu_pass_C<RP, 4, 8, 2, true><<<grid, 512, 0, s>>>(a);
-    else k_mu_pass_C<RP, 4, 8, 2, false><<<grid, 512, 0, s>>>(a);
+    if (a.Xb != nullptr) {
+      if (deep) k_mu_pass_C<RP, 4, 8, 2, true, PD><<<grid, 512, 0, s>>>(a);
+      else k_mu_pass_C<RP, 4, 8, 2, true><<<grid, 512, 0, s>>>(a);
+    } else {
+      if (deep) k_mu_pass_C<RP, 4, 8, 2, false, PD><<<grid, 512, 0, s>>>(a);
+      else k_mu_pass_C<RP, 4, 8, 2, false><<<grid, 512, 0, s>>>(a);
+    }
     NTT_CHECK_LAUNCH();
   }
   return hipSuccess;
