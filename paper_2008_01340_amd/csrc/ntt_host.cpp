@@ -11,8 +11,9 @@ namespace ntt {
 namespace {
 
 constexpr int kMaxPassBlocks = 1024;  // persistent grid of the fused pass
-// grid cap of the row-split pass with 4 waves (three 256-thread workgroups per CU are
-// resident at its register use: one full round on 256 CUs); 8-wave classes keep 512
+// grid cap of the row-split pass over at most 64 rows (three 256-thread workgroups per CU
+// are resident at its register use: one full round on 256 CUs); the classes of 65..256
+// rows (two 4-wave workgroups per CU) and the 8-wave classes take one round of 512
 constexpr int kMaxLBlocks = 768;
 // grid cap of the r <= 8 pass in 64-column steps over 32 rows (two workgroups per CU at
 // its register use)
@@ -156,9 +157,10 @@ void classify_stage(Stage& s, int precision) {
     s.pairs = nb == 0 && ngroups >= 512;
     const int64_t units = nb > 0 ? (ngroups + nb - 1) / nb : (s.pairs ? (ngroups + 1) / 2 : ngroups);
     // one resident round of workgroups; partials up to ~25% of the X bytes
-    // (65..128 rows: two workgroups per CU, its wide pass prefetching the next step)
+    // (65..256 rows: two workgroups per CU; 768 workgroups left a half-filled second
+    // round: the 256^4 stage 1 took 446 ms at 768, 425 ms at 512)
     const int64_t gcap_l = std::max<int64_t>(
-        256, std::min<int64_t>((s.cls <= 2 && s.cls != 1) ? kMaxLBlocks : 512,
+        256, std::min<int64_t>(s.cls == 0 ? kMaxLBlocks : 512,
                                (int64_t)(0.25 * (double)s.m * (double)s.k / Ed)));
     s.G = (int)std::max<int64_t>(1, std::min<int64_t>(units, gcap_l));
   } else if ((s.m + pass_C_rows(s.rp) - 1) / pass_C_rows(s.rp) <= 65535) {
